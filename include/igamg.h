@@ -1,0 +1,191 @@
+/*
+ * igamg.h -- C ABI of the MI355X (gfx950) solver for B-spline isogeometric
+ * Poisson problems by geometric multigrid accelerated with restarted
+ * polynomial vector extrapolation (RRE / MPE).
+ *
+ * Method: arXiv 2412.20205.  The linear system is the SPD stiffness system
+ * A u = b of Section 2, eq. (2); one V-cycle (Algorithm 2 with mu = 1) is the
+ * fixed-point map s_{k+1} = G(s_k) of eq. (7); RRE and MPE are Algorithms 3 and 4
+ * (QR of the first differences of the iterates); the restarted driver is
+ * Algorithm 5.
+ *
+ * Conventions shared by every call
+ *  - Unknowns are the interior B-spline coefficients (homogeneous Dirichlet
+ *    functions removed), n = N_el + p - 2 per direction, ordered
+ *    I = i + n j (+ n^2 k), x index fastest.
+ *  - Vectors passed in (x_dev, b_dev, ...) are caller-owned, contiguous FP64
+ *    device buffers on the context's device, with the number of entries that
+ *    igamg_ndof / igamg_level_ndof report.  The context owns every other
+ *    device buffer (operators, transfer tables, level vectors, iterates).
+ *  - All device work is enqueued on options.stream (a hipStream_t; NULL makes
+ *    the context create its own blocking stream).  Calls that return host
+ *    values synchronise that stream before returning.
+ *  - Every call returns an igamg_status.  Argument errors are reported before
+ *    any work is enqueued.  On an error x_dev keeps the last accepted iterate.
+ *    igamg_last_error() gives a text for the last failing call on this thread.
+ *  - A context must not be used by two host threads at the same time.
+ */
+#ifndef IGAMG_H
+#define IGAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct igamg_ctx igamg_ctx;
+
+typedef enum {
+    IGAMG_OK = 0,
+    IGAMG_EINVAL = -1,      /* bad argument                                     */
+    IGAMG_ENOMEM = -2,      /* device or host allocation failed                 */
+    IGAMG_EHIP = -3,        /* HIP runtime error (text in igamg_last_error)     */
+    IGAMG_ENOTSPD = -4,     /* coarsest-level Cholesky factorisation failed     */
+    IGAMG_EBREAKDOWN = -5,  /* extrapolation coefficients undefined (sum d = 0) */
+    IGAMG_ENOCONV = -6,     /* max_restarts reached before the tolerance        */
+    IGAMG_ENONFINITE = -7   /* NaN or Inf met in the data or the iteration      */
+} igamg_status;
+
+/* Geometry of Section 4: the unit square and cube use Kronecker operators
+ * built from 1D stiffness and mass matrices; the quarter annulus (radii 1 and
+ * 2) is the degree-2 B-spline surface F(xi, eta) = (1 + xi)(1 - eta^2, 2 eta - eta^2)
+ * and stores (2p+1)^2 stencil coefficients per unknown. */
+typedef enum {
+    IGAMG_UNIT_SQUARE = 0,
+    IGAMG_QUARTER_ANNULUS = 1,
+    IGAMG_UNIT_CUBE = 2
+} igamg_geom_kind;
+
+typedef struct {
+    int kind;   /* igamg_geom_kind                               */
+    int n_el;   /* elements per direction on the finest level    */
+} igamg_geometry;
+
+/* Smoothers of Algorithm 2.  MCGS: multicolour Gauss-Seidel with (p+1)^d
+ * colours c(I) = sum_d (i_d mod (p+1)) (p+1)^d swept in increasing order;
+ * JACOBI: x += omega D^{-1} (b - A x).  LEXGS and LEARNED are reserved. */
+typedef enum {
+    IGAMG_SMOOTH_MCGS = 0,
+    IGAMG_SMOOTH_LEXGS = 1,
+    IGAMG_SMOOTH_JACOBI = 2,
+    IGAMG_SMOOTH_LEARNED = 3
+} igamg_smoother;
+
+typedef enum { IGAMG_EXTRAP_NONE = 0, IGAMG_RRE = 1, IGAMG_MPE = 2 } igamg_extrap;
+
+/* FP64: every operation in FP64.  FP32_IR: G(x) = x + V32(round32(b - A x)),
+ * i.e. the V-cycle in FP32 inside FP64 iterative refinement; the outer
+ * residual, the extrapolation and the coarsest solve stay FP64. */
+typedef enum { IGAMG_FP64 = 0, IGAMG_FP32_IR = 1 } igamg_precision;
+
+typedef struct {
+    int nu1, nu2;        /* pre- and post-smoothing steps (default 2, 2)      */
+    int smoother;        /* igamg_smoother (default MCGS)                     */
+    double omega;        /* Jacobi damping (default 2/3)                      */
+    int precision;       /* igamg_precision (default FP64)                    */
+    int n_el_coarsest;   /* elements per direction on level 0 (default 4)     */
+    int use_graphs;      /* capture restart cycles as HIP graphs (default 1)  */
+    void* stream;        /* hipStream_t or NULL                               */
+} igamg_options;
+
+typedef struct {
+    int restarts;        /* Algorithm 5 cycles (plain MG: V-cycles)           */
+    int vcycles;         /* applications of G                                 */
+    int breakdowns;      /* cycles whose extrapolation broke down             */
+    int learned_fallbacks;
+    double rel_residual; /* ||b - A x||_2 / ||b||_2 of the returned x          */
+    double setup_ms;     /* time spent in igamg_setup                         */
+    double solve_ms;     /* wall time of the solve call                       */
+} igamg_stats;
+
+/* Fills the defaults listed above. */
+void igamg_options_default(igamg_options* opt);
+
+/* Builds the hierarchy (Section 2): knots and Gauss rules, the finest
+ * operator (Kronecker factors or mapped stencil assembled on the device),
+ * knot-insertion prolongations, Galerkin coarse operators A_{l-1} = R A_l P
+ * (eq. (4)), multicolour layouts, FP32 copies when needed and the FP64
+ * Cholesky factor of the coarsest operator.  degree in 1..5 (3D: 1..3);
+ * n_el must be n_el_coarsest * 2^k.  levels = 0 coarsens down to
+ * n_el_coarsest; otherwise exactly `levels` levels are built.
+ * The right-hand side starts at zero.  *out is owned by the caller and
+ * released with igamg_destroy.  Errors: EINVAL, ENOMEM, EHIP, ENOTSPD. */
+igamg_status igamg_setup(const igamg_geometry* geom, int degree, int levels,
+                         const igamg_options* opt, igamg_ctx** out);
+void igamg_destroy(igamg_ctx* ctx);
+
+/* Unknowns on the finest level / on level l (0 = coarsest). */
+igamg_status igamg_ndof(const igamg_ctx* ctx, long long* n);
+igamg_status igamg_num_levels(const igamg_ctx* ctx, int* nlevels);
+igamg_status igamg_level_ndof(const igamg_ctx* ctx, int level, long long* n);
+
+/* Right-hand side.  set_rhs copies n FP64 values (host or device memory).
+ * set_rhs_field assembles b_I = int f phi_I on the device with p+1 Gauss
+ * points per direction for f(x) = sum_m a_m sin(pi (k_m . x) + phi_m) in
+ * physical coordinates; modes holds (a, k, l, phi) per mode in 2D and
+ * (a, k, l, m, phi) in 3D (host memory).  get_rhs copies b to a device buffer. */
+igamg_status igamg_set_rhs(igamg_ctx* ctx, const double* b, int b_on_device);
+igamg_status igamg_set_rhs_field(igamg_ctx* ctx, const double* modes, int n_modes);
+igamg_status igamg_get_rhs(igamg_ctx* ctx, double* b_dev);
+
+/* x <- G(x): one V(nu1, nu2) cycle (Algorithm 2, mu = 1) on the finest level,
+ * or its FP32-in-FP64 refinement form.  In place. */
+igamg_status igamg_vcycle(igamg_ctx* ctx, double* x_dev);
+
+/* One cycle of Algorithm 5 without the accuracy test: s_0 = x,
+ * s_{j+1} = G(s_j) for j = 0..q, then x <- t_{0,q} by Algorithm 3 (RRE) or 4
+ * (MPE), using a Householder QR of Delta S_{q+1} computed as a tall-skinny QR
+ * tree on the device.  q in 1..8.  Optional outputs (NULL to skip):
+ * iterates_dev receives s_0 .. s_{q+1} (q+2 blocks of n values, device);
+ * gamma receives gamma_0 .. gamma_q (host).  Breakdown (lambda ~ 0) leaves
+ * x = s_{q+1} and returns EBREAKDOWN. */
+igamg_status igamg_extrapolate(igamg_ctx* ctx, int method, int q, double* x_dev,
+                               double* iterates_dev, double* gamma);
+
+/* Algorithm 5: restarted RRE(q)/MPE(q) from the initial guess in x_dev until
+ * ||b - A x||_2 / ||b||_2 <= tol (tested on t only); method EXTRAP_NONE runs
+ * plain V-cycles tested after each one.  max_restarts bounds the cycles
+ * (V-cycles for the plain method).  stats may be NULL.  Returns ENOCONV with
+ * stats filled when the bound is reached, ENONFINITE on NaN/Inf. */
+igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int method, int q,
+                         double* x_dev, igamg_stats* stats);
+
+/* rel = ||b - A x||_2 / ||b||_2 in FP64 on the finest level. */
+igamg_status igamg_residual(igamg_ctx* ctx, const double* x_dev, double* rel);
+
+/* ---- Per-component entry points (the pieces of one V-cycle) ---------------
+ * level l in 1..L unless stated; buffers hold level-l vectors. */
+
+/* FP64 operator rows in stencil form: for each row index rows[r] (host),
+ * out[r * S + o] = A_l[I, I + di + n dj (+ n^2 dk)] with
+ * o = (di+p) + (2p+1)(dj+p) (+ (2p+1)^2 (dk+p)); zero outside the grid.
+ * level in 0..L.  Host output. */
+igamg_status igamg_get_operator_rows(igamg_ctx* ctx, int level, const long long* rows,
+                                     int nrows, double* out);
+/* y = A_l x (FP64), level in 0..L. */
+igamg_status igamg_apply(igamg_ctx* ctx, int level, const double* x_dev, double* y_dev);
+/* nsweeps smoothing steps on A_l x = b (FP64), level in 1..L. */
+igamg_status igamg_smooth(igamg_ctx* ctx, int level, const double* b_dev, double* x_dev,
+                          int nsweeps);
+/* rc = P_l^T r (level l -> l-1). */
+igamg_status igamg_restrict(igamg_ctx* ctx, int level, const double* r_dev, double* rc_dev);
+/* x += P_l e (level l-1 -> l). */
+igamg_status igamg_prolong_add(igamg_ctx* ctx, int level, const double* e_dev, double* x_dev);
+/* x = A_0^{-1} b on the coarsest level (FP64 Cholesky factor). */
+igamg_status igamg_coarse_solve(igamg_ctx* ctx, const double* b_dev, double* x_dev);
+/* Coefficients gamma_0..gamma_q (host) of Algorithm 3/4 for the q+2 iterates
+ * stored back to back in iterates_dev (device, (q+2) * n values).  info
+ * receives 0 (regular), 1 (lucky breakdown) or -1 (lambda ~ 0). */
+igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q,
+                                 const double* iterates_dev, double* gamma, int* info);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* igamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGAMG_H */

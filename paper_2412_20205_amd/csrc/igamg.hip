@@ -1,0 +1,1067 @@
+// Extrapolated geometric multigrid for B-spline IGA Poisson problems on
+// MI355X: context, setup, V-cycle orchestration, restarted RRE/MPE driver and
+// the C ABI declared in include/igamg.h.
+//
+// Method: arXiv 2412.20205 -- Algorithm 2 (mu-cycle, mu = 1) as the fixed-point
+// map G of eq. (7), Algorithms 3/4 (RRE/MPE by QR of the differences) and
+// Algorithm 5 (restarted extrapolation); Galerkin coarse operators eq. (4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/igamg.h"
+#include "common.hpp"
+#include "host_spline.hpp"
+#include "kernels.hpp"
+
+using namespace igamg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+enum OpKind { OP_STENCIL2D = 0, OP_KRON2D = 1, OP_KRON3D = 2 };
+
+inline unsigned grid_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+struct Level {
+    int n_el = 0, n = 0;
+    long long N = 0;
+    int ncol = 0, ncp = 0;
+    double* coef64 = nullptr;
+    float* coef32 = nullptr;
+    double *K64 = nullptr, *M64 = nullptr;
+    float *K32 = nullptr, *M32 = nullptr;
+    Band1D Kh, Mh;
+    int *r_start = nullptr, *p_start = nullptr;
+    double *r_w64 = nullptr, *p_w64 = nullptr;
+    float *r_w32 = nullptr, *p_w32 = nullptr;
+    int RW = 0, PW = 0;
+    double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
+    float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+
+    template <typename T> T* x() { if constexpr (std::is_same_v<T, double>) return x64; else return x32; }
+    template <typename T> T* b() { if constexpr (std::is_same_v<T, double>) return b64; else return b32; }
+    template <typename T> T* r() { if constexpr (std::is_same_v<T, double>) return r64; else return r32; }
+    template <typename T> const T* rw() const { if constexpr (std::is_same_v<T, double>) return r_w64; else return r_w32; }
+    template <typename T> const T* pw() const { if constexpr (std::is_same_v<T, double>) return p_w64; else return p_w32; }
+    template <typename T> const T* coef() const { if constexpr (std::is_same_v<T, double>) return coef64; else return coef32; }
+    template <typename T> const T* Kb() const { if constexpr (std::is_same_v<T, double>) return K64; else return K32; }
+    template <typename T> const T* Mb() const { if constexpr (std::is_same_v<T, double>) return M64; else return M32; }
+};
+
+int colour_size_host(int n, int p, int dim, int c) {
+    int s = 1;
+    for (int d = 0; d < dim; ++d) {
+        int cd = c % (p + 1);
+        c /= (p + 1);
+        s *= (n - cd + p) / (p + 1);
+    }
+    return s;
+}
+
+}  // namespace
+
+struct igamg_ctx {
+    int geom = 0, p = 0, dim = 2, L = 0;
+    OpKind kind = OP_STENCIL2D;
+    igamg_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<Level> lv;
+    std::vector<void*> allocs;
+    double* Ainv0 = nullptr;
+    int n0 = 0;
+    double* b = nullptr;
+    double bnorm = 0.0;
+    double* partial = nullptr;
+    long long npartial = 0;
+    double* scal = nullptr;       // device scalars: [0] relative residual, [1] ||b||
+    double* host_scal = nullptr;  // pinned
+    std::vector<double*> S;       // iterate buffers
+    double* Rbuf[2] = {nullptr, nullptr};
+    size_t Rcap = 0;
+    ExtrapCoeffs* coeffs = nullptr;
+    ExtrapCoeffs* host_coeffs = nullptr;
+    // element tables of the finest level (2D assembly / loads)
+    double *tabV = nullptr, *tabD = nullptr, *tabPts = nullptr, *tabWts = nullptr;
+    int nq = 0;
+    double setup_ms = 0.0;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int graph_method = -1, graph_q = -1;
+
+    ~igamg_ctx() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (void* a : allocs) (void)hipFree(a);
+        if (host_scal) (void)hipHostFree(host_scal);
+        if (host_coeffs) (void)hipHostFree(host_coeffs);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+
+    template <typename T>
+    T* alloc(size_t count) {
+        void* p = nullptr;
+        if (count == 0) count = 1;
+        if (hipMalloc(&p, count * sizeof(T)) != hipSuccess)
+            throw Error(IGAMG_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        allocs.push_back(p);
+        return (T*)p;
+    }
+    void release(void* p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) allocs.erase(it);
+        (void)hipFree(p);
+    }
+    template <typename T>
+    T* upload(const std::vector<T>& v) {
+        T* d = alloc<T>(v.size());
+        IGAMG_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+        return d;
+    }
+    void check_launch() { IGAMG_HIP(hipGetLastError()); }
+    template <typename T>
+    void fill(T* p, long long n) {
+        if (n <= 0) return;
+        hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kBlock), 0, stream, p, (T)0, n);
+        check_launch();
+    }
+    template <typename A, typename B>
+    void copy(const A* a, B* b, long long n) {
+        if (n <= 0) return;
+        hipLaunchKernelGGL((k_copy<A, B>), dim3(grid_for(n)), dim3(kBlock), 0, stream, a, b, n);
+        check_launch();
+    }
+
+    // ---- degree dispatch
+    template <class F>
+    void with_p(F&& f) {
+        switch (p) {
+            case 1: f(std::integral_constant<int, 1>{}); break;
+            case 2: f(std::integral_constant<int, 2>{}); break;
+            case 3: f(std::integral_constant<int, 3>{}); break;
+            case 4: f(std::integral_constant<int, 4>{}); break;
+            case 5: f(std::integral_constant<int, 5>{}); break;
+            default: throw Error(IGAMG_EINVAL, "degree must be 1..5");
+        }
+    }
+    template <class F>
+    void with_p3(F&& f) {
+        switch (p) {
+            case 1: f(std::integral_constant<int, 1>{}); break;
+            case 2: f(std::integral_constant<int, 2>{}); break;
+            case 3: f(std::integral_constant<int, 3>{}); break;
+            default: throw Error(IGAMG_EINVAL, "3D degree must be 1..3");
+        }
+    }
+    // Calls f(op) with the operator view of level l in precision T.
+    template <typename T, class F>
+    void with_op(int l, F&& f) {
+        Level& v = lv[l];
+        if (kind == OP_STENCIL2D) {
+            with_p([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                Stencil2D<P, T> op{v.coef<T>(), v.n, v.ncp};
+                f(op);
+            });
+        } else if (kind == OP_KRON2D) {
+            with_p([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                Kron2D<P, T> op{v.Kb<T>(), v.Mb<T>(), v.n, v.ncp};
+                f(op);
+            });
+        } else {
+            with_p3([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                Kron3D<P, T> op{v.Kb<T>(), v.Mb<T>(), v.n, v.ncp};
+                f(op);
+            });
+        }
+    }
+
+    long long residual_blocks(int l) const {
+        const Level& v = lv[l];
+        if (kind == OP_STENCIL2D) return (long long)v.ncol * ((v.ncp + kBlock - 1) / kBlock);
+        return (v.N + kBlock - 1) / kBlock;
+    }
+
+    // out = b - A x (mode 0), A x (mode 1), Jacobi step (mode 2)
+    template <typename T, typename Tout>
+    void residual(int l, const T* bb, const T* x, Tout* out, int mode, double* part) {
+        long long nb = residual_blocks(l);
+        with_op<T>(l, [&](auto op) {
+            using Op = decltype(op);
+            hipLaunchKernelGGL((k_residual<Op, Tout>), dim3((unsigned)nb), dim3(kBlock), 0, stream,
+                               op, bb, x, out, mode, opt.omega, lv[l].N, part);
+        });
+        check_launch();
+    }
+
+    template <typename T>
+    void smooth(int l, const T* bb, T* x, int nsweeps) {
+        Level& v = lv[l];
+        for (int s = 0; s < nsweeps; ++s) {
+            if (opt.smoother == IGAMG_SMOOTH_JACOBI) {
+                residual<T, T>(l, bb, x, v.r<T>(), 2, nullptr);
+                copy(v.r<T>(), x, v.N);
+                continue;
+            }
+            with_op<T>(l, [&](auto op) {
+                using Op = decltype(op);
+                for (int c = 0; c < v.ncol; ++c) {
+                    int cs = colour_size_host(v.n, p, dim, c);
+                    if (cs == 0) continue;
+                    hipLaunchKernelGGL((k_gs_colour<Op>), dim3(grid_for(cs)), dim3(kBlock), 0, stream,
+                                       op, bb, x, c);
+                }
+            });
+            check_launch();
+        }
+    }
+
+    template <typename T>
+    void restrict_(int l, const T* rf, T* bc) {
+        Level& f = lv[l];
+        Level& c = lv[l - 1];
+        if (dim == 2)
+            hipLaunchKernelGGL(k_restrict2d<T>, dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf, f.n,
+                               bc, c.n, f.r_start, f.rw<T>(), f.RW);
+        else
+            hipLaunchKernelGGL(k_restrict3d<T>, dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf, f.n,
+                               bc, c.n, f.r_start, f.rw<T>(), f.RW);
+        check_launch();
+    }
+    template <typename T>
+    void prolong_(int l, const T* ec, T* xf) {
+        Level& f = lv[l];
+        Level& c = lv[l - 1];
+        if (dim == 2)
+            hipLaunchKernelGGL(k_prolong2d<T>, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, ec, c.n,
+                               xf, f.n, f.p_start, f.pw<T>(), f.PW);
+        else
+            hipLaunchKernelGGL(k_prolong3d<T>, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, ec, c.n,
+                               xf, f.n, f.p_start, f.pw<T>(), f.PW);
+        check_launch();
+    }
+    template <typename T>
+    void coarse(const T* bb, T* x) {
+        hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(kBlock), 0, stream, Ainv0, n0, bb, x);
+        check_launch();
+    }
+
+    // One V(nu1, nu2) cycle (Algorithm 2, mu = 1) in precision T on the finest
+    // level with right-hand side bL and iterate xL (in place).
+    template <typename T>
+    void vcycle(const T* bL, T* xL) {
+        if (L == 0) {
+            coarse<T>(bL, xL);
+            return;
+        }
+        for (int l = L; l >= 1; --l) {
+            const T* bl = (l == L) ? bL : lv[l].b<T>();
+            T* xl = (l == L) ? xL : lv[l].x<T>();
+            smooth<T>(l, bl, xl, opt.nu1);
+            residual<T, T>(l, bl, xl, lv[l].r<T>(), 0, nullptr);
+            restrict_<T>(l, lv[l].r<T>(), lv[l - 1].b<T>());
+            fill(lv[l - 1].x<T>(), lv[l - 1].N);
+        }
+        coarse<T>(lv[0].b<T>(), lv[0].x<T>());
+        for (int l = 1; l <= L; ++l) {
+            const T* bl = (l == L) ? bL : lv[l].b<T>();
+            T* xl = (l == L) ? xL : lv[l].x<T>();
+            prolong_<T>(l, lv[l - 1].x<T>(), xl);
+            smooth<T>(l, bl, xl, opt.nu2);
+        }
+    }
+
+    // The fixed-point map G of eq. (7) on the finest level, in place.
+    void G(double* x) {
+        if (opt.precision == IGAMG_FP64) {
+            vcycle<double>(b, x);
+            return;
+        }
+        Level& f = lv[L];
+        residual<double, float>(L, b, x, f.b32, 0, nullptr);  // round32(b - A x)
+        fill(f.x32, f.N);
+        vcycle<float>(f.b32, f.x32);
+        hipLaunchKernelGGL(k_add_f32_to_f64, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, f.x32, x,
+                           f.N);
+        check_launch();
+    }
+
+    // scal[0] = ||b - A x|| / ||b|| (device); no host synchronisation.
+    void resnorm_async(const double* x) {
+        residual<double, double>(L, b, x, lv[L].r64, 0, partial);
+        long long nb = residual_blocks(L);
+        hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(kBlock), 0, stream, partial, (int)nb, 1.0,
+                           (const double*)(scal + 1), scal);
+        check_launch();
+    }
+
+    // Stores ||b|| (1 for a zero right-hand side) where the residual kernels read it.
+    void set_bnorm(double v) {
+        bnorm = v;
+        host_scal[1] = v > 0.0 ? v : 1.0;
+        IGAMG_HIP(hipMemcpyAsync(scal + 1, host_scal + 1, sizeof(double), hipMemcpyHostToDevice, stream));
+        sync();
+    }
+
+    // Relative residual and extrapolation status of the last restart cycle.
+    double read_cycle(ExtrapCoeffs& c) {
+        IGAMG_HIP(hipMemcpyAsync(host_scal, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
+        IGAMG_HIP(hipMemcpyAsync(host_coeffs, coeffs, sizeof(ExtrapCoeffs), hipMemcpyDeviceToHost, stream));
+        IGAMG_HIP(hipStreamSynchronize(stream));
+        c = *host_coeffs;
+        return host_scal[0];
+    }
+
+    void ensure_iterates(int q) {
+        while ((int)S.size() < q + 2) S.push_back(alloc<double>(lv[L].N));
+        int ncols = q + 1;
+        long long leaves = (lv[L].N + kQrRows - 1) / kQrRows;
+        size_t need = (size_t)leaves * ncols * ncols;
+        if (need > Rcap) {
+            release(Rbuf[0]);
+            release(Rbuf[1]);
+            Rbuf[0] = alloc<double>(need);
+            Rbuf[1] = alloc<double>(need);
+            Rcap = need;
+        }
+    }
+
+    // Tall-skinny QR tree of Delta S from iterates it[0..q+1] and the small
+    // solve; result in coeffs (device).
+    void extrap_coeffs_async(const IterPtrs& it, int q, int method) {
+        int ncols = q + 1;
+        long long N = lv[L].N;
+        long long count = (N + kQrRows - 1) / kQrRows;
+        size_t shm = (size_t)kQrRows * ncols * sizeof(double);
+        hipLaunchKernelGGL(k_tsqr_leaf, dim3((unsigned)count), dim3(kBlock), shm, stream, it, ncols, N,
+                           Rbuf[0]);
+        check_launch();
+        int cur = 0;
+        int group = kQrRows / ncols;
+        while (count > 1) {
+            long long nxt = (count + group - 1) / group;
+            size_t shm2 = (size_t)group * ncols * ncols * sizeof(double);
+            hipLaunchKernelGGL(k_tsqr_node, dim3((unsigned)nxt), dim3(kBlock), shm2, stream,
+                               Rbuf[cur], (int)count, group, ncols, Rbuf[1 - cur]);
+            check_launch();
+            cur = 1 - cur;
+            count = nxt;
+        }
+        hipLaunchKernelGGL(k_extrap_coeffs, dim3(1), dim3(64), 0, stream, Rbuf[cur], ncols, method,
+                           coeffs);
+        check_launch();
+    }
+
+    IterPtrs iter_ptrs(int q) {
+        IterPtrs it{};
+        for (int j = 0; j <= q + 1; ++j) it.s[j] = S[j];
+        return it;
+    }
+
+    // One restart cycle (Algorithm 5 body) on the iterate buffers: S[0] holds
+    // s_0 on entry and t on exit; the residual norm of t goes to scal[0].
+    void restart_cycle(int method, int q) {
+        long long N = lv[L].N;
+        for (int j = 0; j <= q; ++j) {
+            copy(S[j], S[j + 1], N);
+            G(S[j + 1]);
+        }
+        IterPtrs it = iter_ptrs(q);
+        extrap_coeffs_async(it, q, method);
+        hipLaunchKernelGGL(k_extrap_combine, dim3(grid_for(N)), dim3(kBlock), 0, stream, it, q, N,
+                           (const ExtrapCoeffs*)coeffs, S[0]);
+        check_launch();
+        resnorm_async(S[0]);
+    }
+
+    void run_restart_cycle(int method, int q) {
+        if (!opt.use_graphs) {
+            restart_cycle(method, q);
+            return;
+        }
+        if (!graph_exec || graph_method != method || graph_q != q) {
+            if (graph_exec) {
+                (void)hipGraphExecDestroy(graph_exec);
+                graph_exec = nullptr;
+            }
+            if (graph) {
+                (void)hipGraphDestroy(graph);
+                graph = nullptr;
+            }
+            IGAMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            try {
+                restart_cycle(method, q);
+            } catch (...) {
+                hipGraph_t g;
+                (void)hipStreamEndCapture(stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            IGAMG_HIP(hipStreamEndCapture(stream, &graph));
+            IGAMG_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+            graph_method = method;
+            graph_q = q;
+        }
+        IGAMG_HIP(hipGraphLaunch(graph_exec, stream));
+    }
+
+    double read_scal() {
+        IGAMG_HIP(hipMemcpyAsync(host_scal, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
+        IGAMG_HIP(hipStreamSynchronize(stream));
+        return host_scal[0];
+    }
+    ExtrapCoeffs read_coeffs() {
+        IGAMG_HIP(hipMemcpyAsync(host_coeffs, coeffs, sizeof(ExtrapCoeffs), hipMemcpyDeviceToHost, stream));
+        IGAMG_HIP(hipStreamSynchronize(stream));
+        return *host_coeffs;
+    }
+    void sync() { IGAMG_HIP(hipStreamSynchronize(stream)); }
+
+    double vector_norm(const double* v, long long N) {
+        unsigned nb = std::min<long long>(grid_for(N), 1024);
+        hipLaunchKernelGGL(k_sumsq<double>, dim3(nb), dim3(kBlock), 0, stream, v, N, partial);
+        check_launch();
+        hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(kBlock), 0, stream, partial, (int)nb, 1.0,
+                           (const double*)nullptr, scal);
+        check_launch();
+        return read_scal();
+    }
+
+    void setup(const igamg_geometry& g, int degree, int levels);
+    void setup_levels(int n_el, int levels);
+    void setup_kron();
+    void setup_annulus();
+    void setup_coarse();
+    void set_rhs_field(const double* modes, int n_modes);
+};
+
+// ---------------------------------------------------------------------------
+// setup
+
+void igamg_ctx::setup_levels(int n_el, int levels) {
+    int nc0 = opt.n_el_coarsest;
+    if (nc0 < 1 || n_el < nc0 || n_el % nc0)
+        throw Error(IGAMG_EINVAL, "n_el must be n_el_coarsest * 2^k");
+    int k = 0;
+    for (int m = n_el / nc0; m > 1; m /= 2) {
+        if (m % 2) throw Error(IGAMG_EINVAL, "n_el must be n_el_coarsest * 2^k");
+        ++k;
+    }
+    int nlev = k + 1;
+    if (levels > 0) {
+        if (levels > nlev) throw Error(IGAMG_EINVAL, "too many levels for this grid");
+        nlev = levels;
+    }
+    L = nlev - 1;
+    {
+        long long nc = (n_el >> L) + p - 2, N0 = nc;
+        for (int d = 1; d < dim; ++d) N0 *= nc;
+        if (N0 > 4096) throw Error(IGAMG_EINVAL, "coarsest level too large for the dense direct solve");
+    }
+    lv.resize(nlev);
+    for (int l = 0; l <= L; ++l) {
+        Level& v = lv[l];
+        v.n_el = n_el >> (L - l);
+        v.n = v.n_el + p - 2;
+        if (v.n < 1) throw Error(IGAMG_EINVAL, "level with no interior unknowns");
+        v.N = 1;
+        for (int d = 0; d < dim; ++d) v.N *= v.n;
+        v.ncol = 1;
+        for (int d = 0; d < dim; ++d) v.ncol *= (p + 1);
+        int mx = 0;
+        for (int c = 0; c < v.ncol; ++c) mx = std::max(mx, colour_size_host(v.n, p, dim, c));
+        v.ncp = ((mx + kBlock - 1) / kBlock) * kBlock;
+    }
+    // transfer tables between l-1 and l by Boehm knot insertion
+    for (int l = 1; l <= L; ++l) {
+        Prolong1D P1 = prolongation_boehm(lv[l - 1].n_el, p);
+        TransferTables T = transfer_tables(P1);
+        if (T.nf != lv[l].n || T.nc != lv[l - 1].n) throw Error(IGAMG_EINVAL, "transfer size mismatch");
+        Level& v = lv[l];
+        v.RW = T.RW;
+        v.PW = T.PW;
+        v.r_start = upload(T.r_start);
+        v.p_start = upload(T.p_start);
+        v.r_w64 = upload(T.r_w);
+        v.p_w64 = upload(T.p_w);
+        std::vector<float> rw32(T.r_w.begin(), T.r_w.end()), pw32(T.p_w.begin(), T.p_w.end());
+        v.r_w32 = upload(rw32);
+        v.p_w32 = upload(pw32);
+    }
+}
+
+void igamg_ctx::setup_kron() {
+    // finest 1D bands by quadrature, coarser ones by the 1D Galerkin product
+    Band1D K, M;
+    stiffness_mass_bands(lv[L].n_el, p, K, M);
+    lv[L].Kh = K;
+    lv[L].Mh = M;
+    for (int l = L; l >= 1; --l) {
+        Prolong1D P1 = prolongation_boehm(lv[l - 1].n_el, p);
+        TransferTables T = transfer_tables(P1);
+        lv[l - 1].Kh = galerkin_band(lv[l].Kh, T, p);
+        lv[l - 1].Mh = galerkin_band(lv[l].Mh, T, p);
+    }
+    for (int l = 0; l <= L; ++l) {
+        Level& v = lv[l];
+        v.K64 = upload(v.Kh.v);
+        v.M64 = upload(v.Mh.v);
+        std::vector<float> k32(v.Kh.v.begin(), v.Kh.v.end()), m32(v.Mh.v.begin(), v.Mh.v.end());
+        v.K32 = upload(k32);
+        v.M32 = upload(m32);
+    }
+}
+
+void igamg_ctx::setup_annulus() {
+    const int W = 2 * p + 1, Sn = W * W;
+    Level& f = lv[L];
+    nq = p + 1;
+    ElementTables E = element_tables(f.n_el, p, nq);
+    tabV = upload(E.V);
+    tabD = upload(E.D);
+    tabPts = upload(E.pts);
+    tabWts = upload(E.wts);
+    const int NQ = f.n_el * nq;
+    long long nqp = (long long)NQ * NQ;
+    GeomQP G{};
+    G.D11 = alloc<double>(nqp);
+    G.D12 = alloc<double>(nqp);
+    G.D22 = alloc<double>(nqp);
+    G.wdet = alloc<double>(nqp);
+    G.X = alloc<double>(nqp);
+    G.Y = alloc<double>(nqp);
+    hipLaunchKernelGGL(k_geometry_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream, geom, NQ, tabPts,
+                       tabWts, G);
+    check_launch();
+    std::vector<double*> stage(L + 1, nullptr);
+    stage[L] = alloc<double>((size_t)f.N * Sn);
+    with_p([&](auto PC) {
+        constexpr int P = decltype(PC)::value;
+        hipLaunchKernelGGL(k_assemble_stencil<P>, dim3(grid_for(f.N * Sn)), dim3(kBlock), 0, stream,
+                           f.n_el, nq, tabV, tabD, G, stage[L]);
+    });
+    check_launch();
+    for (double* a : {G.D11, G.D12, G.D22, G.wdet, G.X, G.Y}) release(a);
+    // Galerkin coarse operators, separable: x pass then y pass
+    for (int l = L; l >= 1; --l) {
+        Level& fl = lv[l];
+        Level& cl = lv[l - 1];
+        double* Tm = alloc<double>((size_t)cl.n * fl.n * Sn);
+        stage[l - 1] = alloc<double>((size_t)cl.N * Sn);
+        with_p([&](auto PC) {
+            constexpr int P = decltype(PC)::value;
+            hipLaunchKernelGGL(k_rap_x<P>, dim3(grid_for((long long)cl.n * fl.n * Sn)), dim3(kBlock), 0,
+                               stream, stage[l], fl.n, cl.n, fl.r_start, fl.r_w64, fl.RW, Tm);
+            hipLaunchKernelGGL(k_rap_y<P>, dim3(grid_for(cl.N * Sn)), dim3(kBlock), 0, stream, Tm, fl.n,
+                               cl.n, fl.r_start, fl.r_w64, fl.RW, stage[l - 1]);
+        });
+        check_launch();
+        release(Tm);
+    }
+    for (int l = 0; l <= L; ++l) {
+        Level& v = lv[l];
+        size_t cnt = (size_t)v.ncol * Sn * v.ncp;
+        v.coef64 = alloc<double>(cnt);
+        v.coef32 = alloc<float>(cnt);
+        fill(v.coef64, (long long)cnt);
+        fill(v.coef32, (long long)cnt);
+        with_p([&](auto PC) {
+            constexpr int P = decltype(PC)::value;
+            hipLaunchKernelGGL(k_to_colour_blocked<P>, dim3(grid_for(v.N * Sn)), dim3(kBlock), 0, stream,
+                               stage[l], v.n, v.ncp, v.coef64, v.coef32);
+        });
+        check_launch();
+    }
+    // coarsest dense matrix from the natural stencil rows
+    Level& c = lv[0];
+    std::vector<double> st((size_t)c.N * Sn);
+    IGAMG_HIP(hipMemcpyAsync(st.data(), stage[0], st.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             stream));
+    sync();
+    for (int l = 0; l <= L; ++l) release(stage[l]);
+    n0 = (int)c.N;
+    std::vector<double> A((size_t)n0 * n0, 0.0);
+    for (int I = 0; I < n0; ++I) {
+        int j = I / c.n, i = I % c.n;
+        for (int o = 0; o < Sn; ++o) {
+            int i2 = i + o % W - p, j2 = j + o / W - p;
+            if (i2 < 0 || i2 >= c.n || j2 < 0 || j2 >= c.n) continue;
+            A[(size_t)I * n0 + i2 + c.n * j2] = st[(size_t)I * Sn + o];
+        }
+    }
+    if (!cholesky_inplace(A, n0)) throw Error(IGAMG_ENOTSPD, "coarsest operator is not SPD");
+    Ainv0 = upload(inverse_from_cholesky(A, n0));
+}
+
+void igamg_ctx::setup_coarse() {
+    // Kronecker coarsest operator expanded to a dense matrix
+    Level& c = lv[0];
+    n0 = (int)c.N;
+    std::vector<double> A((size_t)n0 * n0, 0.0);
+    const Band1D &K = c.Kh, &M = c.Mh;
+    int n = c.n;
+    for (int I = 0; I < n0; ++I) {
+        int i = I % n, j = (I / n) % n, k = (dim == 3) ? I / (n * n) : 0;
+        for (int J = 0; J < n0; ++J) {
+            int i2 = J % n, j2 = (J / n) % n, k2 = (dim == 3) ? J / (n * n) : 0;
+            int di = i2 - i, dj = j2 - j, dk = k2 - k;
+            if (std::abs(di) > p || std::abs(dj) > p || std::abs(dk) > p) continue;
+            double v;
+            if (dim == 2)
+                v = K.at(i, di) * M.at(j, dj) + M.at(i, di) * K.at(j, dj);
+            else
+                v = K.at(i, di) * M.at(j, dj) * M.at(k, dk) + M.at(i, di) * K.at(j, dj) * M.at(k, dk) +
+                    M.at(i, di) * M.at(j, dj) * K.at(k, dk);
+            A[(size_t)I * n0 + J] = v;
+        }
+    }
+    if (!cholesky_inplace(A, n0)) throw Error(IGAMG_ENOTSPD, "coarsest operator is not SPD");
+    Ainv0 = upload(inverse_from_cholesky(A, n0));
+}
+
+void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
+    auto t0 = std::chrono::steady_clock::now();
+    geom = g.kind;
+    p = degree;
+    if (geom == IGAMG_UNIT_SQUARE) {
+        kind = OP_KRON2D;
+        dim = 2;
+    } else if (geom == IGAMG_QUARTER_ANNULUS) {
+        kind = OP_STENCIL2D;
+        dim = 2;
+    } else if (geom == IGAMG_UNIT_CUBE) {
+        kind = OP_KRON3D;
+        dim = 3;
+    } else {
+        throw Error(IGAMG_EINVAL, "unknown geometry kind");
+    }
+    if (p < 1 || p > 5 || (dim == 3 && p > 3)) throw Error(IGAMG_EINVAL, "unsupported degree");
+    if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu1 + opt.nu2 == 0) throw Error(IGAMG_EINVAL, "bad nu1/nu2");
+    if (opt.smoother != IGAMG_SMOOTH_MCGS && opt.smoother != IGAMG_SMOOTH_JACOBI)
+        throw Error(IGAMG_EINVAL, "smoother not available in this build");
+    if (opt.precision != IGAMG_FP64 && opt.precision != IGAMG_FP32_IR)
+        throw Error(IGAMG_EINVAL, "bad precision");
+    if (opt.stream) {
+        stream = (hipStream_t)opt.stream;
+    } else {
+        IGAMG_HIP(hipStreamCreateWithFlags(&stream, hipStreamDefault));  // orders against the legacy stream
+        own_stream = true;
+    }
+    setup_levels(g.n_el, levels);
+    if (kind == OP_STENCIL2D) {
+        setup_annulus();
+    } else {
+        setup_kron();
+        setup_coarse();
+    }
+    for (int l = 0; l <= L; ++l) {
+        Level& v = lv[l];
+        v.x64 = alloc<double>(v.N);
+        v.b64 = alloc<double>(v.N);
+        v.r64 = alloc<double>(v.N);
+        v.x32 = alloc<float>(v.N);
+        v.b32 = alloc<float>(v.N);
+        v.r32 = alloc<float>(v.N);
+        fill(v.x64, v.N);
+        fill(v.b64, v.N);
+        fill(v.x32, v.N);
+        fill(v.b32, v.N);
+    }
+    b = alloc<double>(lv[L].N);
+    fill(b, lv[L].N);
+    npartial = std::max<long long>(residual_blocks(L), 1024);
+    partial = alloc<double>(npartial);
+    scal = alloc<double>(8);
+    coeffs = alloc<ExtrapCoeffs>(1);
+    IGAMG_HIP(hipHostMalloc((void**)&host_scal, 8 * sizeof(double), hipHostMallocDefault));
+    IGAMG_HIP(hipHostMalloc((void**)&host_coeffs, sizeof(ExtrapCoeffs), hipHostMallocDefault));
+    set_bnorm(0.0);
+    setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void igamg_ctx::set_rhs_field(const double* modes, int n_modes) {
+    Level& f = lv[L];
+    std::vector<double> md(modes, modes + (size_t)n_modes * (dim + 2));
+    for (double v : md)
+        if (!std::isfinite(v)) throw Error(IGAMG_ENONFINITE, "non-finite mode table");
+    double* dmodes = upload(md);
+    if (dim == 2) {
+        int q = p + 1;
+        ElementTables E = element_tables(f.n_el, p, q);
+        double* V = upload(E.V);
+        double* pts = upload(E.pts);
+        double* wts = upload(E.wts);
+        const int NQ = f.n_el * q;
+        long long nqp = (long long)NQ * NQ;
+        GeomQP G{};
+        G.D11 = alloc<double>(nqp);
+        G.D12 = alloc<double>(nqp);
+        G.D22 = alloc<double>(nqp);
+        G.wdet = alloc<double>(nqp);
+        G.X = alloc<double>(nqp);
+        G.Y = alloc<double>(nqp);
+        double* fq = alloc<double>(nqp);
+        hipLaunchKernelGGL(k_geometry_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream,
+                           geom == IGAMG_QUARTER_ANNULUS ? 1 : 0, NQ, pts, wts, G);
+        hipLaunchKernelGGL(k_load_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream, nqp, G, dmodes,
+                           n_modes, fq);
+        hipLaunchKernelGGL(k_assemble_load2d, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, f.n_el, p,
+                           q, V, fq, b);
+        check_launch();
+        sync();
+        for (double* a : {G.D11, G.D12, G.D22, G.wdet, G.X, G.Y, fq, V, pts, wts}) release(a);
+    } else {
+        int q = p + 1;
+        ElementTables E = element_tables(f.n_el, p, q);
+        double* V = upload(E.V);
+        double* pts = upload(E.pts);
+        double* wts = upload(E.wts);
+        hipLaunchKernelGGL(k_assemble_load3d, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, f.n_el, p,
+                           q, V, pts, wts, dmodes, n_modes, b);
+        check_launch();
+        sync();
+        for (double* a : {V, pts, wts}) release(a);
+    }
+    release(dmodes);
+    set_bnorm(vector_norm(b, f.N));
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+namespace {
+
+template <class F>
+igamg_status guarded(F&& f) {
+    try {
+        f();
+        g_last_error.clear();
+        return IGAMG_OK;
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return (igamg_status)e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return IGAMG_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return IGAMG_EINVAL;
+    }
+}
+
+void need(bool cond, const char* what) {
+    if (!cond) throw Error(IGAMG_EINVAL, what);
+}
+
+}  // namespace
+
+extern "C" {
+
+void igamg_options_default(igamg_options* opt) {
+    if (!opt) return;
+    opt->nu1 = 2;
+    opt->nu2 = 2;
+    opt->smoother = IGAMG_SMOOTH_MCGS;
+    opt->omega = 2.0 / 3.0;
+    opt->precision = IGAMG_FP64;
+    opt->n_el_coarsest = 4;
+    opt->use_graphs = 1;
+    opt->stream = nullptr;
+}
+
+const char* igamg_last_error(void) { return g_last_error.c_str(); }
+
+igamg_status igamg_setup(const igamg_geometry* geom, int degree, int levels,
+                         const igamg_options* opt, igamg_ctx** out) {
+    return guarded([&] {
+        need(geom && out, "null argument");
+        need(levels >= 0, "levels must be >= 0");
+        *out = nullptr;
+        std::unique_ptr<igamg_ctx> c(new igamg_ctx());
+        if (opt)
+            c->opt = *opt;
+        else
+            igamg_options_default(&c->opt);
+        c->setup(*geom, degree, levels);
+        *out = c.release();
+    });
+}
+
+void igamg_destroy(igamg_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+}
+
+igamg_status igamg_ndof(const igamg_ctx* ctx, long long* n) {
+    return guarded([&] {
+        need(ctx && n, "null argument");
+        *n = ctx->lv[ctx->L].N;
+    });
+}
+
+igamg_status igamg_num_levels(const igamg_ctx* ctx, int* nlevels) {
+    return guarded([&] {
+        need(ctx && nlevels, "null argument");
+        *nlevels = ctx->L + 1;
+    });
+}
+
+igamg_status igamg_level_ndof(const igamg_ctx* ctx, int level, long long* n) {
+    return guarded([&] {
+        need(ctx && n, "null argument");
+        need(level >= 0 && level <= ctx->L, "level out of range");
+        *n = ctx->lv[level].N;
+    });
+}
+
+igamg_status igamg_set_rhs(igamg_ctx* ctx, const double* bsrc, int on_device) {
+    return guarded([&] {
+        need(ctx && bsrc, "null argument");
+        long long N = ctx->lv[ctx->L].N;
+        IGAMG_HIP(hipMemcpyAsync(ctx->b, bsrc, N * sizeof(double),
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                 ctx->stream));
+        double nb = ctx->vector_norm(ctx->b, N);
+        if (!std::isfinite(nb)) throw Error(IGAMG_ENONFINITE, "right-hand side is not finite");
+        ctx->set_bnorm(nb);
+    });
+}
+
+igamg_status igamg_set_rhs_field(igamg_ctx* ctx, const double* modes, int n_modes) {
+    return guarded([&] {
+        need(ctx && modes && n_modes > 0, "bad mode table");
+        ctx->set_rhs_field(modes, n_modes);
+    });
+}
+
+igamg_status igamg_get_rhs(igamg_ctx* ctx, double* b_dev) {
+    return guarded([&] {
+        need(ctx && b_dev, "null argument");
+        ctx->copy(ctx->b, b_dev, ctx->lv[ctx->L].N);
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_vcycle(igamg_ctx* ctx, double* x_dev) {
+    return guarded([&] {
+        need(ctx && x_dev, "null argument");
+        ctx->G(x_dev);
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_residual(igamg_ctx* ctx, const double* x_dev, double* rel) {
+    return guarded([&] {
+        need(ctx && x_dev && rel, "null argument");
+        ctx->resnorm_async(x_dev);
+        *rel = ctx->read_scal();
+    });
+}
+
+igamg_status igamg_extrapolate(igamg_ctx* ctx, int method, int q, double* x_dev,
+                               double* iterates_dev, double* gamma) {
+    return guarded([&] {
+        need(ctx && x_dev, "null argument");
+        need(method == IGAMG_RRE || method == IGAMG_MPE, "method must be RRE or MPE");
+        need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
+        ctx->ensure_iterates(q);
+        long long N = ctx->lv[ctx->L].N;
+        ctx->copy(x_dev, ctx->S[0], N);
+        for (int j = 0; j <= q; ++j) {
+            ctx->copy(ctx->S[j], ctx->S[j + 1], N);
+            ctx->G(ctx->S[j + 1]);
+        }
+        if (iterates_dev)
+            for (int j = 0; j <= q + 1; ++j) ctx->copy(ctx->S[j], iterates_dev + (size_t)j * N, N);
+        IterPtrs it = ctx->iter_ptrs(q);
+        ctx->extrap_coeffs_async(it, q, method);
+        hipLaunchKernelGGL(k_extrap_combine, dim3(grid_for(N)), dim3(kBlock), 0, ctx->stream, it, q, N,
+                           (const ExtrapCoeffs*)ctx->coeffs, x_dev);
+        ctx->check_launch();
+        ExtrapCoeffs c = ctx->read_coeffs();
+        if (gamma)
+            for (int j = 0; j <= q; ++j) gamma[j] = c.gamma[j];
+        if (c.info == -2) throw Error(IGAMG_ENONFINITE, "non-finite iterates");
+        if (c.info == -1) throw Error(IGAMG_EBREAKDOWN, "extrapolation broke down (sum d = 0)");
+    });
+}
+
+igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int method, int q,
+                         double* x_dev, igamg_stats* stats) {
+    igamg_stats st{};
+    auto t0 = std::chrono::steady_clock::now();
+    bool converged = false;
+    igamg_status s = guarded([&] {
+        need(ctx && x_dev, "null argument");
+        need(tol > 0 && max_restarts > 0, "bad tolerance or max_restarts");
+        need(method == IGAMG_EXTRAP_NONE || method == IGAMG_RRE || method == IGAMG_MPE, "bad method");
+        st.setup_ms = ctx->setup_ms;
+        long long N = ctx->lv[ctx->L].N;
+        if (method == IGAMG_EXTRAP_NONE) {
+            for (int k = 0; k < max_restarts; ++k) {
+                ctx->G(x_dev);
+                ctx->resnorm_async(x_dev);
+                double rel = ctx->read_scal();
+                st.vcycles++;
+                st.restarts++;
+                st.rel_residual = rel;
+                if (!std::isfinite(rel)) throw Error(IGAMG_ENONFINITE, "non-finite residual");
+                if (rel <= tol) {
+                    converged = true;
+                    break;
+                }
+            }
+        } else {
+            need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
+            ctx->ensure_iterates(q);
+            ctx->copy(x_dev, ctx->S[0], N);
+            for (int k = 0; k < max_restarts; ++k) {
+                ctx->run_restart_cycle(method, q);
+                ExtrapCoeffs c;
+                double rel = ctx->read_cycle(c);
+                st.vcycles += q + 1;
+                st.restarts++;
+                if (c.info == -1) st.breakdowns++;
+                st.rel_residual = rel;
+                if (c.info == -2 || !std::isfinite(rel)) {
+                    throw Error(IGAMG_ENONFINITE, "non-finite iterate");
+                }
+                if (rel <= tol) {
+                    converged = true;
+                    break;
+                }
+            }
+            ctx->copy(ctx->S[0], x_dev, N);
+            ctx->sync();
+        }
+        if (!converged) throw Error(IGAMG_ENOCONV, "tolerance not reached within max_restarts");
+    });
+    st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return s;
+}
+
+igamg_status igamg_get_operator_rows(igamg_ctx* ctx, int level, const long long* rows, int nrows,
+                                     double* out) {
+    return guarded([&] {
+        need(ctx && rows && out && nrows >= 0, "null argument");
+        need(level >= 0 && level <= ctx->L, "level out of range");
+        Level& v = ctx->lv[level];
+        int p = ctx->p, W = 2 * p + 1;
+        int Sn = (ctx->dim == 2) ? W * W : W * W * W;
+        for (int r = 0; r < nrows; ++r) need(rows[r] >= 0 && rows[r] < v.N, "row out of range");
+        if (nrows == 0) return;
+        if (ctx->kind == OP_STENCIL2D) {
+            std::vector<long long> rv(rows, rows + nrows);
+            long long* drows = ctx->upload(rv);
+            double* dout = ctx->alloc<double>((size_t)nrows * Sn);
+            ctx->with_p([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                hipLaunchKernelGGL(k_gather_rows<P>, dim3(grid_for((long long)nrows * Sn)), dim3(kBlock),
+                                   0, ctx->stream, v.coef64, v.n, v.ncp, drows, nrows, dout);
+            });
+            ctx->check_launch();
+            IGAMG_HIP(hipMemcpyAsync(out, dout, (size_t)nrows * Sn * sizeof(double),
+                                     hipMemcpyDeviceToHost, ctx->stream));
+            ctx->sync();
+            ctx->release(drows);
+            ctx->release(dout);
+            return;
+        }
+        int n = v.n;
+        for (int r = 0; r < nrows; ++r) {
+            long long I = rows[r];
+            int i = (int)(I % n), j = (int)((I / n) % n), k = (ctx->dim == 3) ? (int)(I / ((long long)n * n)) : 0;
+            for (int o = 0; o < Sn; ++o) {
+                int di = o % W - p, dj = (o / W) % W - p, dk = (ctx->dim == 3) ? o / (W * W) - p : 0;
+                double val = 0.0;
+                if (i + di >= 0 && i + di < n && j + dj >= 0 && j + dj < n && k + dk >= 0 && k + dk < n) {
+                    const Band1D &K = v.Kh, &M = v.Mh;
+                    if (ctx->dim == 2)
+                        val = K.at(i, di) * M.at(j, dj) + M.at(i, di) * K.at(j, dj);
+                    else
+                        val = K.at(i, di) * M.at(j, dj) * M.at(k, dk) +
+                              M.at(i, di) * K.at(j, dj) * M.at(k, dk) +
+                              M.at(i, di) * M.at(j, dj) * K.at(k, dk);
+                }
+                out[(size_t)r * Sn + o] = val;
+            }
+        }
+    });
+}
+
+igamg_status igamg_apply(igamg_ctx* ctx, int level, const double* x_dev, double* y_dev) {
+    return guarded([&] {
+        need(ctx && x_dev && y_dev, "null argument");
+        need(level >= 0 && level <= ctx->L, "level out of range");
+        ctx->residual<double, double>(level, nullptr, x_dev, y_dev, 1, nullptr);
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_smooth(igamg_ctx* ctx, int level, const double* b_dev, double* x_dev, int nsweeps) {
+    return guarded([&] {
+        need(ctx && b_dev && x_dev && nsweeps >= 0, "bad argument");
+        need(level >= 1 && level <= ctx->L, "level out of range");
+        ctx->smooth<double>(level, b_dev, x_dev, nsweeps);
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_restrict(igamg_ctx* ctx, int level, const double* r_dev, double* rc_dev) {
+    return guarded([&] {
+        need(ctx && r_dev && rc_dev, "null argument");
+        need(level >= 1 && level <= ctx->L, "level out of range");
+        ctx->restrict_<double>(level, r_dev, rc_dev);
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_prolong_add(igamg_ctx* ctx, int level, const double* e_dev, double* x_dev) {
+    return guarded([&] {
+        need(ctx && e_dev && x_dev, "null argument");
+        need(level >= 1 && level <= ctx->L, "level out of range");
+        ctx->prolong_<double>(level, e_dev, x_dev);
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_coarse_solve(igamg_ctx* ctx, const double* b_dev, double* x_dev) {
+    return guarded([&] {
+        need(ctx && b_dev && x_dev, "null argument");
+        ctx->coarse<double>(b_dev, x_dev);
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q, const double* iterates_dev,
+                                 double* gamma, int* info) {
+    return guarded([&] {
+        need(ctx && iterates_dev && gamma, "null argument");
+        need(method == IGAMG_RRE || method == IGAMG_MPE, "method must be RRE or MPE");
+        need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
+        ctx->ensure_iterates(q);
+        long long N = ctx->lv[ctx->L].N;
+        IterPtrs it{};
+        for (int j = 0; j <= q + 1; ++j) it.s[j] = iterates_dev + (size_t)j * N;
+        ctx->extrap_coeffs_async(it, q, method);
+        ExtrapCoeffs c = ctx->read_coeffs();
+        for (int j = 0; j <= q; ++j) gamma[j] = c.gamma[j];
+        if (info) *info = c.info;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,303 @@
+"""Thin ctypes binding of libigamg.so (include/igamg.h, include/igamg_host.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device vectors are contiguous float64 torch tensors on the GPU; their data
+pointers are passed through.  The current torch stream is handed to the
+library at setup so that torch and the solver share one stream.
+
+The library must be built (paper_2412_20205_amd/build.py); loading fails loudly
+when it is missing -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libigamg.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EBREAKDOWN, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
+                -5: "EBREAKDOWN", -6: "ENOCONV", -7: "ENONFINITE"}
+UNIT_SQUARE, QUARTER_ANNULUS, UNIT_CUBE = 0, 1, 2
+SMOOTH_MCGS, SMOOTH_LEXGS, SMOOTH_JACOBI, SMOOTH_LEARNED = 0, 1, 2, 3
+EXTRAP_NONE, RRE, MPE = 0, 1, 2
+FP64, FP32_IR = 0, 1
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n_el", ctypes.c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("smoother", ctypes.c_int),
+                ("omega", ctypes.c_double), ("precision", ctypes.c_int),
+                ("n_el_coarsest", ctypes.c_int), ("use_graphs", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("restarts", ctypes.c_int), ("vcycles", ctypes.c_int),
+                ("breakdowns", ctypes.c_int), ("learned_fallbacks", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class IgamgError(RuntimeError):
+    def __init__(self, status, func, msg):
+        super().__init__("%s failed: %s (%s)" % (func, STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_ll = ctypes.c_longlong
+
+_SIGNATURES = {
+    "igamg_options_default": (None, [ctypes.POINTER(Options)]),
+    "igamg_setup": (_i, [ctypes.POINTER(Geometry), _i, _i, ctypes.POINTER(Options),
+                         ctypes.POINTER(_P)]),
+    "igamg_destroy": (None, [_P]),
+    "igamg_ndof": (_i, [_P, ctypes.POINTER(_ll)]),
+    "igamg_num_levels": (_i, [_P, ctypes.POINTER(_i)]),
+    "igamg_level_ndof": (_i, [_P, _i, ctypes.POINTER(_ll)]),
+    "igamg_set_rhs": (_i, [_P, _P, _i]),
+    "igamg_set_rhs_field": (_i, [_P, _P, _i]),
+    "igamg_get_rhs": (_i, [_P, _P]),
+    "igamg_vcycle": (_i, [_P, _P]),
+    "igamg_extrapolate": (_i, [_P, _i, _i, _P, _P, _P]),
+    "igamg_solve": (_i, [_P, _d, _i, _i, _i, _P, ctypes.POINTER(Stats)]),
+    "igamg_residual": (_i, [_P, _P, ctypes.POINTER(_d)]),
+    "igamg_get_operator_rows": (_i, [_P, _i, _P, _i, _P]),
+    "igamg_apply": (_i, [_P, _i, _P, _P]),
+    "igamg_smooth": (_i, [_P, _i, _P, _P, _i]),
+    "igamg_restrict": (_i, [_P, _i, _P, _P]),
+    "igamg_prolong_add": (_i, [_P, _i, _P, _P]),
+    "igamg_coarse_solve": (_i, [_P, _P, _P]),
+    "igamg_extrap_coeffs": (_i, [_P, _i, _i, _P, _P, ctypes.POINTER(_i)]),
+    "igamg_last_error": (ctypes.c_char_p, []),
+    "igamg_host_gauss_legendre": (_i, [_i, _P, _P]),
+    "igamg_host_basis": (_i, [_i, _i, _d, _P, _P, ctypes.POINTER(_i)]),
+    "igamg_host_prolongation_1d": (_i, [_i, _i, _P]),
+    "igamg_host_bands": (_i, [_i, _i, _i, _i, _P, _P]),
+}
+
+
+def lib():
+    """Load libigamg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libigamg.so is not built: run paper_2412_20205_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, func):
+    if status != OK:
+        raise IgamgError(status, func, lib().igamg_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64 CUDA tensor (or None).
+
+    Work already queued by torch on its current stream is completed first, so
+    the library's stream sees the tensor's final contents."""
+    if t is None:
+        return None
+    import torch
+    torch.cuda.current_stream().synchronize()
+    if not t.is_cuda or t.dtype.__repr__() != "torch.float64" or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_options(**kw):
+    o = Options()
+    lib().igamg_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Solver:
+    """One solver context (owns its device data; see include/igamg.h)."""
+
+    def __init__(self, geometry, n_el, degree, levels=0, stream=None, **opts):
+        import torch
+        if stream is None:
+            cs = torch.cuda.current_stream()
+            # the legacy default stream cannot be captured into graphs: let the
+            # library create its own (blocking) stream in that case
+            stream = None if cs.cuda_stream == 0 else cs.cuda_stream
+        o = default_options(**opts)
+        o.stream = stream
+        self._stream_ptr = stream
+        g = Geometry(geometry, n_el)
+        h = _P()
+        _check(lib().igamg_setup(ctypes.byref(g), degree, levels, ctypes.byref(o),
+                                 ctypes.byref(h)), "igamg_setup")
+        self._h = h
+        self.geometry, self.n_el, self.degree = geometry, n_el, degree
+        self.options = o
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().igamg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def ndof(self):
+        n = _ll()
+        _check(lib().igamg_ndof(self._h, ctypes.byref(n)), "igamg_ndof")
+        return n.value
+
+    @property
+    def num_levels(self):
+        n = _i()
+        _check(lib().igamg_num_levels(self._h, ctypes.byref(n)), "igamg_num_levels")
+        return n.value
+
+    def level_ndof(self, level):
+        n = _ll()
+        _check(lib().igamg_level_ndof(self._h, level, ctypes.byref(n)), "igamg_level_ndof")
+        return n.value
+
+    def set_rhs(self, b):
+        """b: float64 device tensor or host numpy array of ndof entries."""
+        if isinstance(b, np.ndarray):
+            b = np.ascontiguousarray(b, dtype=np.float64)
+            if b.size != self.ndof:
+                raise ValueError("wrong length")
+            _check(lib().igamg_set_rhs(self._h, _np_ptr(b), 0), "igamg_set_rhs")
+        else:
+            if b.numel() != self.ndof:
+                raise ValueError("wrong length")
+            _check(lib().igamg_set_rhs(self._h, _ptr(b), 1), "igamg_set_rhs")
+
+    def set_rhs_field(self, modes):
+        modes = np.ascontiguousarray(modes, dtype=np.float64)
+        _check(lib().igamg_set_rhs_field(self._h, _np_ptr(modes), modes.shape[0]),
+               "igamg_set_rhs_field")
+
+    def get_rhs(self, out):
+        _check(lib().igamg_get_rhs(self._h, _ptr(out)), "igamg_get_rhs")
+        return out
+
+    def vcycle(self, x):
+        _check(lib().igamg_vcycle(self._h, _ptr(x)), "igamg_vcycle")
+        return x
+
+    def extrapolate(self, method, q, x, iterates=None):
+        gamma = np.zeros(q + 1)
+        st = lib().igamg_extrapolate(self._h, method, q, _ptr(x), _ptr(iterates), _np_ptr(gamma))
+        _check(st, "igamg_extrapolate")
+        return gamma
+
+    def solve(self, x, tol=1e-10, max_restarts=100, method=RRE, q=5, check=True):
+        st = Stats()
+        status = lib().igamg_solve(self._h, tol, max_restarts, method, q, _ptr(x),
+                                   ctypes.byref(st))
+        if check:
+            _check(status, "igamg_solve")
+        return st, status
+
+    def residual(self, x):
+        r = _d()
+        _check(lib().igamg_residual(self._h, _ptr(x), ctypes.byref(r)), "igamg_residual")
+        return r.value
+
+    def operator_rows(self, level, rows):
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        W = 2 * self.degree + 1
+        S = W ** (3 if self.geometry == UNIT_CUBE else 2)
+        out = np.zeros((len(rows), S))
+        _check(lib().igamg_get_operator_rows(self._h, level, _np_ptr(rows), len(rows),
+                                             _np_ptr(out)), "igamg_get_operator_rows")
+        return out
+
+    def apply(self, level, x, y):
+        _check(lib().igamg_apply(self._h, level, _ptr(x), _ptr(y)), "igamg_apply")
+        return y
+
+    def smooth(self, level, b, x, nsweeps=1):
+        _check(lib().igamg_smooth(self._h, level, _ptr(b), _ptr(x), nsweeps), "igamg_smooth")
+        return x
+
+    def restrict(self, level, r, rc):
+        _check(lib().igamg_restrict(self._h, level, _ptr(r), _ptr(rc)), "igamg_restrict")
+        return rc
+
+    def prolong_add(self, level, e, x):
+        _check(lib().igamg_prolong_add(self._h, level, _ptr(e), _ptr(x)), "igamg_prolong_add")
+        return x
+
+    def coarse_solve(self, b, x):
+        _check(lib().igamg_coarse_solve(self._h, _ptr(b), _ptr(x)), "igamg_coarse_solve")
+        return x
+
+    def extrap_coeffs(self, method, q, iterates):
+        gamma = np.zeros(q + 1)
+        info = _i()
+        _check(lib().igamg_extrap_coeffs(self._h, method, q, _ptr(iterates), _np_ptr(gamma),
+                                         ctypes.byref(info)), "igamg_extrap_coeffs")
+        return gamma, info.value
+
+
+# ---- host-only helpers (no GPU needed)
+
+def host_gauss_legendre(m):
+    x, w = np.zeros(m), np.zeros(m)
+    if lib().igamg_host_gauss_legendre(m, _np_ptr(x), _np_ptr(w)) != 0:
+        raise ValueError("bad m")
+    return x, w
+
+
+def host_basis(ne, p, u):
+    N, D = np.zeros(p + 1), np.zeros(p + 1)
+    first = _i()
+    if lib().igamg_host_basis(ne, p, float(u), _np_ptr(N), _np_ptr(D), ctypes.byref(first)) != 0:
+        raise ValueError("bad arguments")
+    return first.value, N, D
+
+
+def host_prolongation_1d(ne_coarse, p):
+    out = np.zeros((2 * ne_coarse + p, ne_coarse + p))
+    if lib().igamg_host_prolongation_1d(ne_coarse, p, _np_ptr(out)) != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def host_bands(ne, ne_coarsest, level, p):
+    n = (ne_coarsest << level) + p - 2
+    K, M = np.zeros((n, 2 * p + 1)), np.zeros((n, 2 * p + 1))
+    if lib().igamg_host_bands(ne, ne_coarsest, level, p, _np_ptr(K), _np_ptr(M)) != 0:
+        raise ValueError("bad arguments")
+    return K, M

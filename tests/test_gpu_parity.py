@@ -1,0 +1,299 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
+
+Bars: integer/index work bit-exact; FP64 operator rows, transfers and the
+coarse solve to 1e-13 relative; FP64 multicolour iterates (V-cycles and
+extrapolated iterates) to 1e-12 relative per iterate; every solve to a final
+relative residual of 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import assemble, extrapolation as ex, multigrid as mg
+from paper_2412_20205_amd import igamg
+
+pytestmark = pytest.mark.gpu
+
+GEOM = {"square": igamg.UNIT_SQUARE, "annulus": igamg.QUARTER_ANNULUS, "cube": igamg.UNIT_CUBE}
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV).contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def oracle_rhs(geom, n_el, p, modes):
+    if geom == "cube":
+        return assemble.load_vector_3d(n_el, p, modes)
+    g = assemble.GEOM_ANNULUS if geom == "annulus" else assemble.GEOM_IDENTITY
+    return assemble.load_vector_2d(n_el, p, modes, geom=g)
+
+
+def modes_for(geom, seed):
+    if geom == "cube":
+        return synth.manufactured_sine_modes_3d()
+    return synth.random_field_modes(seed)
+
+
+_cache = {}
+
+
+def case(geom, n_el, p, **opts):
+    key = (geom, n_el, p, tuple(sorted(opts.items())))
+    if key not in _cache:
+        print("[case] %s n_el=%d p=%d %s" % (geom, n_el, p, opts), flush=True)
+        s = igamg.Solver(GEOM[geom], n_el, p, **opts)
+        H = mg.build_hierarchy(geom, n_el, p)
+        modes = modes_for(geom, 2000 + p)
+        s.set_rhs_field(modes)
+        b = oracle_rhs(geom, n_el, p, modes)
+        _cache[key] = (s, H, b)
+    return _cache[key]
+
+
+CASES_2D = [("annulus", 16, 2), ("annulus", 32, 3), ("annulus", 32, 4), ("annulus", 16, 5),
+            ("square", 32, 2), ("square", 16, 3), ("square", 8, 1)]
+CASES_ALL = CASES_2D + [("cube", 8, 2), ("cube", 8, 3)]
+
+
+def _offsets(p, dim):
+    W = 2 * p + 1
+    S = W ** dim
+    o = np.arange(S)
+    return o % W - p, (o // W) % W - p, (o // (W * W)) - p if dim == 3 else np.zeros(S, int)
+
+
+@pytest.mark.parametrize("geom,n_el,p", CASES_ALL)
+def test_operator_rows_every_level(geom, n_el, p):
+    s, H, _ = case(geom, n_el, p)
+    dim = 3 if geom == "cube" else 2
+    di, dj, dk = _offsets(p, dim)
+    assert s.num_levels == len(H.levels)
+    for l, lev in enumerate(H.levels):
+        n = lev.n
+        N = lev.A.shape[0]
+        assert s.level_ndof(l) == N
+        rows = np.arange(N)
+        got = s.operator_rows(l, rows)
+        A = lev.A.tocsr()
+        i, j, k = rows % n, (rows // n) % n, rows // (n * n) if dim == 3 else 0 * rows
+        scale = abs(A).max()
+        for o in range(got.shape[1]):
+            ii, jj, kk = i + di[o], j + dj[o], k + dk[o]
+            ok = (ii >= 0) & (ii < n) & (jj >= 0) & (jj < n) & (kk >= 0) & (kk < n)
+            J = ii + n * jj + (n * n * kk if dim == 3 else 0)
+            ref = np.zeros(N)
+            ref[ok] = np.asarray(A[rows[ok], J[ok]]).ravel()
+            assert np.all(got[~ok, o] == 0.0)
+            assert np.abs(got[:, o] - ref).max() <= 1e-13 * scale, (l, o)
+
+
+@pytest.mark.parametrize("geom,n_el,p", CASES_ALL)
+def test_rhs_apply_restrict_prolong_coarse(geom, n_el, p):
+    s, H, b = case(geom, n_el, p)
+    bd = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+    s.get_rhs(bd)
+    assert rel(host(bd), b) < 1e-13
+    L = len(H.levels) - 1
+    for l in range(L + 1):
+        lev = H.levels[l]
+        x = synth.random_vector(lev.A.shape[0], 10 + l)
+        y = torch.zeros(len(x), dtype=torch.float64, device=DEV)
+        s.apply(l, dev(x), y)
+        assert rel(host(y), lev.A @ x) < 1e-13
+        if l >= 1:
+            nc = H.levels[l - 1].A.shape[0]
+            rc = torch.zeros(nc, dtype=torch.float64, device=DEV)
+            s.restrict(l, dev(x), rc)
+            assert rel(host(rc), lev.P.T @ x) < 1e-14
+            e = synth.random_vector(nc, 20 + l)
+            xf = dev(x)
+            s.prolong_add(l, dev(e), xf)
+            assert rel(host(xf), x + lev.P @ e) < 1e-14
+    b0 = synth.random_vector(H.levels[0].A.shape[0], 30)
+    x0 = torch.zeros(len(b0), dtype=torch.float64, device=DEV)
+    s.coarse_solve(dev(b0), x0)
+    assert rel(host(x0), H.coarse_solve(b0)) < 1e-12
+
+
+@pytest.mark.parametrize("geom,n_el,p", CASES_ALL)
+def test_multicolour_sweeps(geom, n_el, p):
+    s, H, _ = case(geom, n_el, p)
+    for l in range(1, len(H.levels)):
+        lev = H.levels[l]
+        bl = synth.random_vector(lev.A.shape[0], 40 + l)
+        x0 = synth.random_vector(lev.A.shape[0], 50 + l)
+        xg = dev(x0)
+        s.smooth(l, dev(bl), xg, 2)
+        xr = mg.smooth(lev, bl, x0.copy(), mg.SMOOTH_MCGS, 2)
+        assert rel(host(xg), xr) < 1e-13
+
+
+@pytest.mark.parametrize("geom,n_el,p", CASES_ALL)
+def test_vcycle_iterates(geom, n_el, p):
+    s, H, b = case(geom, n_el, p)
+    N = len(b)
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    xr = np.zeros(N)
+    for it in range(6):
+        s.vcycle(xg)
+        xr = mg.vcycle(H, b, xr)
+        assert rel(host(xg), xr) < 1e-12, it
+
+
+@pytest.mark.parametrize("geom,n_el,p", [("annulus", 32, 3), ("annulus", 16, 5), ("square", 32, 2),
+                                         ("cube", 8, 3)])
+@pytest.mark.parametrize("method", [igamg.RRE, igamg.MPE])
+def test_extrapolated_iterates(geom, n_el, p, method):
+    s, H, b = case(geom, n_el, p)
+    N = len(b)
+    q = 5
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    its = torch.zeros((q + 2) * N, dtype=torch.float64, device=DEV)
+    x = np.zeros(N)
+    om = ex.RRE if method == igamg.RRE else ex.MPE
+    for cycle in range(2):
+        gam = s.extrapolate(method, q, xg, its)
+        S = [x]
+        for j in range(q + 1):
+            S.append(mg.vcycle(H, b, S[-1]))
+        Sg = host(its).reshape(q + 2, N)
+        for j in range(q + 2):
+            assert rel(Sg[j], S[j]) < 1e-12, (cycle, j)
+        t, gr, _ = ex.extrapolate(S, om)
+        assert rel(host(xg), t) < 1e-12, cycle
+        # gamma_j is only determined up to the size of its column: compare the
+        # contributions gamma_j * ||Delta s_j|| (t itself is compared above)
+        cn = np.linalg.norm(ex.differences(S), axis=0)
+        assert np.abs((gam - gr) * cn).max() < 1e-10 * cn.max()
+        x = t
+
+
+def _linear_sequence(N, q, seed):
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(0.3, 0.95, N)
+    c = rng.standard_normal(N)
+    S = [rng.standard_normal(N)]
+    for _ in range(q + 1):
+        S.append(lam * S[-1] + c)
+    return S
+
+
+@pytest.mark.parametrize("q", [1, 3, 5, 8])
+def test_tsqr_coefficients_tree(q):
+    """Tall-skinny QR over several tree levels (N = 1e6 + ragged tail)."""
+    if "tsqr" not in _cache:
+        print("[case] annulus n_el=1024 p=2 (extrapolation only)", flush=True)
+        _cache["tsqr"] = igamg.Solver(igamg.QUARTER_ANNULUS, 1024, 2)
+    s = _cache["tsqr"]
+    N = s.ndof
+    S = _linear_sequence(N, q, q)
+    its = dev(np.concatenate(S))
+    for method, om in ((igamg.RRE, ex.RRE), (igamg.MPE, ex.MPE)):
+        g, info = s.extrap_coeffs(method, q, its)
+        _, gr, _ = ex.extrapolate(S, om)
+        assert info == 0
+        assert np.abs(g - gr).max() < 1e-9 * np.abs(gr).max()
+
+
+def test_breakdown_rules():
+    s, _, _ = case("annulus", 16, 2)
+    N = s.ndof
+    v = synth.random_vector(N, 1)
+    drift = dev(np.concatenate([j * v for j in range(7)]))
+    for method in (igamg.RRE, igamg.MPE):
+        _, info = s.extrap_coeffs(method, 5, drift)
+        assert info == -1
+    xs = synth.random_vector(N, 2)
+    a, b2 = synth.random_vector(N, 3), synth.random_vector(N, 4)
+    lucky = [xs + a, xs + b2, xs, xs, xs, xs, xs]
+    for method, om in ((igamg.RRE, ex.RRE), (igamg.MPE, ex.MPE)):
+        g, info = s.extrap_coeffs(method, 5, dev(np.concatenate(lucky)))
+        _, gr, _ = ex.extrapolate(lucky, om)
+        assert info == 1
+        np.testing.assert_allclose(g, gr, atol=1e-12)
+
+
+@pytest.mark.parametrize("geom,n_el,p", [("annulus", 32, 3), ("annulus", 32, 5), ("square", 64, 2),
+                                         ("square", 32, 4), ("cube", 8, 2)])
+@pytest.mark.parametrize("method", [igamg.EXTRAP_NONE, igamg.RRE, igamg.MPE])
+def test_solve_matches_oracle(geom, n_el, p, method):
+    s, H, b = case(geom, n_el, p)
+    N = len(b)
+    A = H.fine.A
+    nb = np.linalg.norm(b)
+    G = lambda x: mg.vcycle(H, b, x)
+    rn = lambda x: np.linalg.norm(b - A @ x) / nb
+    om = {igamg.EXTRAP_NONE: None, igamg.RRE: ex.RRE, igamg.MPE: ex.MPE}[method]
+    xr, st_r, _ = ex.restarted_solve(G, rn, np.zeros(N), 5, om, tol=1e-10, max_restarts=600)
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    st, _ = s.solve(xg, tol=1e-10, max_restarts=600, method=method, q=5)
+    x = host(xg)
+    assert st.rel_residual <= 1e-10 and rn(x) <= 1.0000001e-10
+    assert st.vcycles == st_r.vcycles and st.restarts == st_r.restarts
+    assert rel(x, xr) < 1e-11
+
+
+@pytest.mark.parametrize("geom,n_el,p", [("annulus", 64, 3), ("annulus", 32, 5), ("square", 64, 2),
+                                         ("cube", 16, 3)])
+@pytest.mark.parametrize("method", [igamg.EXTRAP_NONE, igamg.RRE])
+def test_fp32_refinement_reaches_tolerance(geom, n_el, p, method):
+    """FP32 V-cycles inside FP64 refinement reach the FP64 tolerance; the error
+    against the oracle's exact discrete solution is stated and bounded."""
+    import scipy.sparse.linalg as spla
+    s, H, b = case(geom, n_el, p, precision=igamg.FP32_IR)
+    N = len(b)
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    st, _ = s.solve(xg, tol=1e-10, max_restarts=800, method=method, q=5)
+    x = host(xg)
+    A = H.fine.A
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1.0000001e-10
+    u = spla.spsolve(A.tocsc(), b)
+    err = rel(x, u)
+    print("[fp32-ir] %s n_el=%d p=%d method=%d vcycles=%d err_vs_exact=%.2e"
+          % (geom, n_el, p, method, st.vcycles, err))
+    assert err < 1e-6
+
+
+def test_error_paths():
+    with pytest.raises(igamg.IgamgError) as e:
+        igamg.Solver(igamg.QUARTER_ANNULUS, 12, 3)
+    assert e.value.status == igamg.EINVAL
+    with pytest.raises(igamg.IgamgError) as e:
+        igamg.Solver(igamg.UNIT_CUBE, 8, 4)
+    assert e.value.status == igamg.EINVAL
+    s, H, b = case("annulus", 32, 4)
+    N = len(b)
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    st, status = s.solve(xg, tol=1e-10, max_restarts=2, method=igamg.EXTRAP_NONE, check=False)
+    assert status == igamg.ENOCONV and st.vcycles == 2 and st.rel_residual > 1e-10
+    s2 = igamg.Solver(igamg.QUARTER_ANNULUS, 16, 2)
+    bad = np.ones(s2.ndof)
+    bad[3] = np.nan
+    with pytest.raises(igamg.IgamgError) as e:
+        s2.set_rhs(bad)
+    assert e.value.status == igamg.ENONFINITE
+    with pytest.raises(igamg.IgamgError) as e:
+        s.extrapolate(igamg.RRE, 9, xg)
+    assert e.value.status == igamg.EINVAL
+
+
+def test_single_level_is_direct_solve():
+    s = igamg.Solver(igamg.QUARTER_ANNULUS, 4, 3)
+    H = mg.build_hierarchy("annulus", 4, 3)
+    modes = synth.random_field_modes(7)
+    s.set_rhs_field(modes)
+    b = assemble.load_vector_2d(4, 3, modes)
+    xg = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+    s.vcycle(xg)
+    assert rel(host(xg), H.coarse_solve(b)) < 1e-12
