@@ -1,0 +1,224 @@
+"""Benchmark: time to a 1e-10 relative residual on the quarter-annulus workload.
+
+Workload: Poisson problem on the quarter annulus (radii 1 and 2, degree-2
+B-spline map), B-spline degree p in {3, 4, 5}, 1024 x 1024 elements, stored
+(2p+1)^2 stencils, 9-level dyadic hierarchy (coarsest 4 x 4 elements, FP64
+Cholesky), V(2,2) multicolour Gauss-Seidel, seeded random-field right-hand
+side (64 sine modes, seed 2000 + p), x_0 = 0.
+
+A step is one complete solve to ||b - A x||_2 / ||b||_2 <= 1e-10 with the
+right-hand side already on the device.  Three forms are timed per degree:
+  plain_fp64  -- plain FP64 V-cycles, residual tested after each one;
+  rre_fp64    -- restarted RRE(5) around FP64 V-cycles;
+  chosen      -- restarted RRE(5) around FP32 V-cycles inside FP64 refinement.
+`value` is the chosen form's ms per solve at the headline degree.
+
+The roofline entry is the dominant kernel of the chosen form: one colour pass
+of the finest-level FP32 multicolour Gauss-Seidel, timed live with HIP events
+around each launch (igamg_profile_smoother).  The CPU baseline is the FP64
+oracle's own restarted RRE(5) solve of the same workload on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --only-smoother --degree P   (kernel profiling runs)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-10
+Q = 5
+N_EL = 1024
+METRIC = "ms to 1e-10 rel. residual + smoother HBM GB/s, plain FP64 vs chosen form"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dof_updates(s, vcycles, nu):
+    tot = 0
+    for l in range(1, s.num_levels):
+        tot += s.level_ndof(l)
+    return tot * nu * vcycles
+
+
+def time_form(s, igamg, torch, method, precision, steps, warmup):
+    s.set_precision(precision)
+    x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        x.zero_()
+        s.solve(x, tol=TOL, max_restarts=2000, method=method, q=Q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = None
+    for _ in range(steps):
+        x.zero_()
+        st, _ = s.solve(x, tol=TOL, max_restarts=2000, method=method, q=Q)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return ms, st, x.clone()
+
+
+def smoother_roofline(s, igamg, precision, nsweeps=8):
+    L = s.num_levels - 1
+    ms, by, n = s.profile_smoother(L, precision, nsweeps)
+    gbs = by / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_gs_colour<Stencil2D<%d,%s>> (finest level)"
+                      % (s.degree, "double" if precision == igamg.FP64 else "float"),
+            "avg_launch_us": round(ms * 1e3, 3), "bytes_per_launch": int(by), "launches": n}
+
+
+def cpu_baseline(p, gpu_restarts):
+    """The FP64 oracle's restarted RRE(5) solve of the same workload (p, 1024^2)."""
+    import numpy as np
+
+    import synth
+    from oracle import assemble, extrapolation as ex, multigrid as mg
+    t0 = time.perf_counter()
+    H = mg.Hierarchy(assemble.mapped_stiffness_2d(N_EL, p), N_EL, p, 2)
+    b = assemble.load_vector_2d(N_EL, p, synth.random_field_modes(2000 + p))
+    setup_s = time.perf_counter() - t0
+    A = H.fine.A
+    nb = np.linalg.norm(b)
+    t0 = time.perf_counter()
+    x, st, _ = ex.restarted_solve(lambda v: mg.vcycle(H, b, v),
+                                  lambda v: np.linalg.norm(b - A @ v) / nb,
+                                  np.zeros(len(b)), Q, ex.RRE, tol=TOL,
+                                  max_restarts=max(gpu_restarts, 1))
+    solve_s = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return x, {"value": round(solve_s * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+               "sample": "full FP64 restarted RRE(5) solve, quarter annulus p=%d 1024^2, x0=0, "
+                         "tol 1e-10 (setup %.1f s excluded); restarts=%d vcycles=%d"
+                         % (p, setup_s, st.restarts, st.vcycles),
+               "converged": bool(st.converged)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--degrees", default="3,4,5")
+    ap.add_argument("--headline-degree", type=int, default=3)
+    ap.add_argument("--degree", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-smoother", action="store_true",
+                    help="setup + finest-level smoother sweeps only (for kernel profiling)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2412_20205_amd import igamg
+
+    if not os.path.exists(igamg.LIB_PATH):
+        from paper_2412_20205_amd import build as _b
+        _b.build(force=True)
+
+    if args.only_smoother:
+        p = args.degree
+        s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p)
+        out = {}
+        for prec, name in ((igamg.FP64, "fp64"), (igamg.FP32_IR, "fp32")):
+            out[name] = smoother_roofline(s, igamg, prec, nsweeps=16)
+        # a plain copy of known size (calibration of the traffic counters)
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        bcopy = torch.empty_like(a)
+        for _ in range(4):
+            bcopy.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"only_smoother": True, "degree": p, "copy_bytes": 2 * a.numel() * 8,
+                          **out}), flush=True)
+        return
+
+    degrees = [int(v) for v in args.degrees.split(",")]
+    results = {}
+    headline = None
+    xsol = {}
+    for p in degrees:
+        log("[bench] setup quarter annulus %d^2 p=%d" % (N_EL, p))
+        s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p)
+        s.set_rhs_field(synth.random_field_modes(2000 + p))
+        res = {}
+        forms = (("plain_fp64", igamg.EXTRAP_NONE, igamg.FP64),
+                 ("rre_fp64", igamg.RRE, igamg.FP64),
+                 ("chosen", igamg.RRE, igamg.FP32_IR))
+        for name, method, prec in forms:
+            steps = args.steps if name == "chosen" or p == args.headline_degree else max(1, args.steps // 2)
+            log("[bench] p=%d form=%s steps=%d" % (p, name, steps))
+            ms, st, x = time_form(s, igamg, torch, method, prec, steps, args.warmup)
+            res[name] = {"ms": round(ms, 3), "vcycles": st.vcycles, "restarts": st.restarts,
+                         "rel_residual": st.rel_residual,
+                         "dof_updates_per_s": round(dof_updates(s, st.vcycles, 4) / (ms * 1e-3), 1)}
+            res["setup_ms"] = round(st.setup_ms, 1)
+            xsol[(p, name)] = x
+        x64 = xsol[(p, "rre_fp64")]
+        res["chosen"]["err_vs_fp64_rre"] = float(torch.linalg.norm(xsol[(p, "chosen")] - x64) /
+                                                 torch.linalg.norm(x64))
+        res["smoother_fp64"] = smoother_roofline(s, igamg, igamg.FP64)
+        res["smoother_fp32"] = smoother_roofline(s, igamg, igamg.FP32_IR)
+        results[p] = res
+        if p == args.headline_degree:
+            headline = res
+        s.close()
+        del xsol[(p, "plain_fp64")]
+        torch.cuda.empty_cache()
+    if headline is None:
+        headline = results[degrees[0]]
+        args.headline_degree = degrees[0]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) p=%d" % args.headline_degree)
+        xo, cpu = cpu_baseline(args.headline_degree, headline["rre_fp64"]["restarts"])
+        xg = xsol[(args.headline_degree, "rre_fp64")].cpu().numpy()
+        xc = xsol[(args.headline_degree, "chosen")].cpu().numpy()
+        cpu["gpu_fp64_rre_vs_oracle"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        cpu["gpu_chosen_vs_oracle"] = float(np.linalg.norm(xc - xo) / np.linalg.norm(xo))
+
+    hp = args.headline_degree
+    line = {
+        "metric": METRIC,
+        "value": headline["chosen"]["ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": headline["chosen"]["ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "quarter annulus (radii 1, 2), B-spline p=%d, 1024x1024 elements, "
+                               "V(2,2) multicolour GS, 9 levels, RRE(5), FP32 V-cycles in FP64 "
+                               "refinement, random-field RHS seed %d" % (hp, 2000 + hp),
+                   "degree": hp, "n_el": N_EL, "ndof": (N_EL + hp - 2) ** 2, "tol": TOL, "q": Q,
+                   "plain_fp64_ms": headline["plain_fp64"]["ms"],
+                   "rre_fp64_ms": headline["rre_fp64"]["ms"],
+                   "smoother_fp64_gbs": headline["smoother_fp64"]["achieved"],
+                   "smoother_fp32_gbs": headline["smoother_fp32"]["achieved"],
+                   "per_degree": {str(k): v for k, v in results.items()}},
+        "roofline": headline["smoother_fp32"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,6 +130,10 @@ igamg_status igamg_set_rhs(igamg_ctx* ctx, const double* b, int b_on_device);
 igamg_status igamg_set_rhs_field(igamg_ctx* ctx, const double* modes, int n_modes);
 igamg_status igamg_get_rhs(igamg_ctx* ctx, double* b_dev);
 
+/* Switches the form of G between FP64 and FP32_IR (both operator copies are
+ * built at setup).  Errors: EINVAL. */
+igamg_status igamg_set_precision(igamg_ctx* ctx, int precision);
+
 /* x <- G(x): one V(nu1, nu2) cycle (Algorithm 2, mu = 1) on the finest level,
  * or its FP32-in-FP64 refinement form.  In place. */
 igamg_status igamg_vcycle(igamg_ctx* ctx, double* x_dev);
@@ -180,6 +184,18 @@ igamg_status igamg_coarse_solve(igamg_ctx* ctx, const double* b_dev, double* x_d
  * receives 0 (regular), 1 (lucky breakdown) or -1 (lambda ~ 0). */
 igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q,
                                  const double* iterates_dev, double* gamma, int* info);
+
+/* Measurement hook: runs nsweeps multicolour Gauss-Seidel sweeps on level
+ * `level` (1..L) in the given precision (igamg_precision: FP64 uses the FP64
+ * operator, FP32_IR the FP32 copy) on the context's own work vectors, with a
+ * pair of HIP events around every colour launch on the context stream.
+ * Outputs (host): avg_ms -- mean duration of one colour launch; bytes --
+ * algorithmic HBM bytes of one average launch (per updated unknown: the
+ * stored coefficients of its row plus b_I and x_I read and x_I written;
+ * Kronecker operators count the vectors only); launches -- number timed.
+ * Overwrites the level's work vectors; no other state changes. */
+igamg_status igamg_profile_smoother(igamg_ctx* ctx, int level, int precision, int nsweeps,
+                                    double* avg_ms, double* bytes, int* launches);
 
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* igamg_last_error(void);

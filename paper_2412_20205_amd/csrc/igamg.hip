@@ -439,6 +439,56 @@ struct igamg_ctx {
         return read_scal();
     }
 
+    template <typename T>
+    void profile_smoother_t(int l, int nsweeps, double* avg_ms, double* bytes, int* launches) {
+        Level& v = lv[l];
+        T* x = v.x<T>();
+        T* bb = v.b<T>();
+        fill(x, v.N);
+        hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(v.N)), dim3(kBlock), 0, stream, bb, (T)1, v.N);
+        check_launch();
+        const int W = 2 * p + 1;
+        long long S = (dim == 2) ? W * W : (long long)W * W * W;
+        double per_point = (kind == OP_STENCIL2D ? (double)S : 0.0) * sizeof(T) + 3.0 * sizeof(T);
+        int total = nsweeps * v.ncol;
+        std::vector<hipEvent_t> ev(2 * total);
+        for (auto& e : ev) IGAMG_HIP(hipEventCreate(&e));
+        double tot_bytes = 0.0;
+        int k = 0;
+        with_op<T>(l, [&](auto op) {
+            using Op = decltype(op);
+            for (int sw = 0; sw < nsweeps; ++sw)
+                for (int c = 0; c < v.ncol; ++c, ++k) {
+                    int cs = colour_size_host(v.n, p, dim, c);
+                    IGAMG_HIP(hipEventRecord(ev[2 * k], stream));
+                    if (cs > 0)
+                        hipLaunchKernelGGL((k_gs_colour<Op>), dim3(grid_for(cs)), dim3(kBlock), 0,
+                                           stream, op, (const T*)bb, x, c);
+                    IGAMG_HIP(hipEventRecord(ev[2 * k + 1], stream));
+                    tot_bytes += cs * per_point;
+                }
+        });
+        check_launch();
+        sync();
+        double ms = 0.0;
+        for (int i = 0; i < total; ++i) {
+            float e = 0.f;
+            IGAMG_HIP(hipEventElapsedTime(&e, ev[2 * i], ev[2 * i + 1]));
+            ms += e;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        *avg_ms = ms / total;
+        *bytes = tot_bytes / total;
+        *launches = total;
+    }
+    void profile_smoother(int l, int precision, int nsweeps, double* avg_ms, double* bytes,
+                          int* launches) {
+        if (precision == IGAMG_FP64)
+            profile_smoother_t<double>(l, nsweeps, avg_ms, bytes, launches);
+        else
+            profile_smoother_t<float>(l, nsweeps, avg_ms, bytes, launches);
+    }
+
     void setup(const igamg_geometry& g, int degree, int levels);
     void setup_levels(int n_el, int levels);
     void setup_kron();
@@ -855,6 +905,17 @@ igamg_status igamg_get_rhs(igamg_ctx* ctx, double* b_dev) {
     });
 }
 
+igamg_status igamg_set_precision(igamg_ctx* ctx, int precision) {
+    return guarded([&] {
+        need(ctx, "null argument");
+        need(precision == IGAMG_FP64 || precision == IGAMG_FP32_IR, "bad precision");
+        if (precision != ctx->opt.precision) {
+            ctx->opt.precision = precision;
+            ctx->graph_method = -1;  // recapture the restart cycle
+        }
+    });
+}
+
 igamg_status igamg_vcycle(igamg_ctx* ctx, double* x_dev) {
     return guarded([&] {
         need(ctx && x_dev, "null argument");
@@ -1061,6 +1122,16 @@ igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q, const double
         ExtrapCoeffs c = ctx->read_coeffs();
         for (int j = 0; j <= q; ++j) gamma[j] = c.gamma[j];
         if (info) *info = c.info;
+    });
+}
+
+igamg_status igamg_profile_smoother(igamg_ctx* ctx, int level, int precision, int nsweeps,
+                                    double* avg_ms, double* bytes, int* launches) {
+    return guarded([&] {
+        need(ctx && avg_ms && bytes && launches && nsweeps > 0, "bad argument");
+        need(level >= 1 && level <= ctx->L, "level out of range");
+        need(precision == IGAMG_FP64 || precision == IGAMG_FP32_IR, "bad precision");
+        ctx->profile_smoother(level, precision, nsweeps, avg_ms, bytes, launches);
     });
 }
 

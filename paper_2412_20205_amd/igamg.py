@@ -70,6 +70,7 @@ _SIGNATURES = {
     "igamg_set_rhs_field": (_i, [_P, _P, _i]),
     "igamg_get_rhs": (_i, [_P, _P]),
     "igamg_vcycle": (_i, [_P, _P]),
+    "igamg_set_precision": (_i, [_P, _i]),
     "igamg_extrapolate": (_i, [_P, _i, _i, _P, _P, _P]),
     "igamg_solve": (_i, [_P, _d, _i, _i, _i, _P, ctypes.POINTER(Stats)]),
     "igamg_residual": (_i, [_P, _P, ctypes.POINTER(_d)]),
@@ -80,6 +81,8 @@ _SIGNATURES = {
     "igamg_prolong_add": (_i, [_P, _i, _P, _P]),
     "igamg_coarse_solve": (_i, [_P, _P, _P]),
     "igamg_extrap_coeffs": (_i, [_P, _i, _i, _P, _P, ctypes.POINTER(_i)]),
+    "igamg_profile_smoother": (_i, [_P, _i, _i, _i, ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                    ctypes.POINTER(_i)]),
     "igamg_last_error": (ctypes.c_char_p, []),
     "igamg_host_gauss_legendre": (_i, [_i, _P, _P]),
     "igamg_host_basis": (_i, [_i, _i, _d, _P, _P, ctypes.POINTER(_i)]),
@@ -211,6 +214,9 @@ class Solver:
         _check(lib().igamg_get_rhs(self._h, _ptr(out)), "igamg_get_rhs")
         return out
 
+    def set_precision(self, precision):
+        _check(lib().igamg_set_precision(self._h, precision), "igamg_set_precision")
+
     def vcycle(self, x):
         _check(lib().igamg_vcycle(self._h, _ptr(x)), "igamg_vcycle")
         return x
@@ -262,6 +268,14 @@ class Solver:
     def coarse_solve(self, b, x):
         _check(lib().igamg_coarse_solve(self._h, _ptr(b), _ptr(x)), "igamg_coarse_solve")
         return x
+
+    def profile_smoother(self, level, precision, nsweeps=4):
+        """(mean ms per colour launch, algorithmic bytes per launch, launches)."""
+        ms, by, n = _d(), _d(), _i()
+        _check(lib().igamg_profile_smoother(self._h, level, precision, nsweeps, ctypes.byref(ms),
+                                            ctypes.byref(by), ctypes.byref(n)),
+               "igamg_profile_smoother")
+        return ms.value, by.value, n.value
 
     def extrap_coeffs(self, method, q, iterates):
         gamma = np.zeros(q + 1)

@@ -172,10 +172,9 @@ def test_extrapolated_iterates(geom, n_el, p, method):
             assert rel(Sg[j], S[j]) < 1e-12, (cycle, j)
         t, gr, _ = ex.extrapolate(S, om)
         assert rel(host(xg), t) < 1e-12, cycle
-        # gamma_j is only determined up to the size of its column: compare the
-        # contributions gamma_j * ||Delta s_j|| (t itself is compared above)
-        cn = np.linalg.norm(ex.differences(S), axis=0)
-        assert np.abs((gam - gr) * cn).max() < 1e-10 * cn.max()
+        # gamma itself is ill-determined when Delta S is ill-conditioned (strong
+        # contraction); t, compared above, is what the method fixes uniquely
+        assert abs(gam.sum() - 1.0) < 1e-12
         x = t
 
 
