@@ -31,6 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Counter-derived HBM traffic per launch of the finest-level colour pass (FETCH_SIZE x 2.0 +
+# WRITE_SIZE, calibrated on a 1 GiB copy), from profiles/gs_colour_annulus1024_p3.md.
+# Valid only for the kernel as profiled; entries are removed when the kernel changes.
+MEASURED_TRAFFIC = {(3, "double"): 38.52e6, (3, "float"): 19.31e6}
 TOL = 1e-10
 Q = 5
 N_EL = 1024
@@ -69,10 +73,11 @@ def smoother_roofline(s, igamg, precision, nsweeps=8):
     L = s.num_levels - 1
     ms, by, n = s.profile_smoother(L, precision, nsweeps)
     gbs = by / (ms * 1e-3) / 1e9
+    tname = "double" if precision == igamg.FP64 else "float"
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_gs_colour<Stencil2D<%d,%s>> (finest level)"
-                      % (s.degree, "double" if precision == igamg.FP64 else "float"),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": MEASURED_TRAFFIC.get((s.degree, tname)),
+            "kernel": "k_gs_colour_sliced<Stencil2D<%d,%s>> (finest level)" % (s.degree, tname),
             "avg_launch_us": round(ms * 1e3, 3), "bytes_per_launch": int(by), "launches": n}
 
 
@@ -111,6 +116,8 @@ def main():
     ap.add_argument("--headline-degree", type=int, default=3)
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tail-items", type=int, default=32,
+                    help="single-workgroup V-cycle threshold (0 = one launch per step everywhere)")
     ap.add_argument("--only-smoother", action="store_true",
                     help="setup + finest-level smoother sweeps only (for kernel profiling)")
     args = ap.parse_args()
@@ -152,7 +159,7 @@ def main():
     xsol = {}
     for p in degrees:
         log("[bench] setup quarter annulus %d^2 p=%d" % (N_EL, p))
-        s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p)
+        s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p, tail_items=args.tail_items)
         s.set_rhs_field(synth.random_field_modes(2000 + p))
         res = {}
         forms = (("plain_fp64", igamg.EXTRAP_NONE, igamg.FP64),

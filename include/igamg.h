@@ -87,6 +87,10 @@ typedef struct {
     int precision;       /* igamg_precision (default FP64)                    */
     int n_el_coarsest;   /* elements per direction on level 0 (default 4)     */
     int use_graphs;      /* capture restart cycles as HIP graphs (default 1)  */
+    int tail_items;      /* levels whose colour passes need at most this many
+                            64-point x slice work items run, with everything
+                            below them, in one single-workgroup kernel per
+                            V-cycle (default 32; 0 disables)                  */
     void* stream;        /* hipStream_t or NULL                               */
 } igamg_options;
 

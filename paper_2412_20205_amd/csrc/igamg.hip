@@ -97,6 +97,7 @@ struct igamg_ctx {
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_method = -1, graph_q = -1;
+    int tail_top = 0;  // levels 0..tail_top run in the single-workgroup kernel
 
     ~igamg_ctx() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -190,8 +191,8 @@ struct igamg_ctx {
 
     long long residual_blocks(int l) const {
         const Level& v = lv[l];
-        if (kind == OP_STENCIL2D) return (long long)v.ncol * ((v.ncp + kBlock - 1) / kBlock);
-        return (v.N + kBlock - 1) / kBlock;
+        if (kind == OP_STENCIL2D) return (long long)v.ncol * (v.ncp / 64);
+        return (v.N + 63) / 64;
     }
 
     // out = b - A x (mode 0), A x (mode 1), Jacobi step (mode 2)
@@ -200,8 +201,8 @@ struct igamg_ctx {
         long long nb = residual_blocks(l);
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
-            hipLaunchKernelGGL((k_residual<Op, Tout>), dim3((unsigned)nb), dim3(kBlock), 0, stream,
-                               op, bb, x, out, mode, opt.omega, lv[l].N, part);
+            hipLaunchKernelGGL((k_residual_sliced<Op, Tout>), dim3((unsigned)nb), dim3(64 * Op::NW), 0,
+                               stream, op, bb, x, out, mode, opt.omega, lv[l].N, part);
         });
         check_launch();
     }
@@ -220,24 +221,73 @@ struct igamg_ctx {
                 for (int c = 0; c < v.ncol; ++c) {
                     int cs = colour_size_host(v.n, p, dim, c);
                     if (cs == 0) continue;
-                    hipLaunchKernelGGL((k_gs_colour<Op>), dim3(grid_for(cs)), dim3(kBlock), 0, stream,
-                                       op, bb, x, c);
+                    hipLaunchKernelGGL((k_gs_colour_sliced<Op>), dim3((cs + 63) / 64), dim3(64 * Op::NW),
+                                       0, stream, op, bb, x, c);
                 }
             });
             check_launch();
         }
     }
 
+    // bc = R rf; xc (optional) zeroed in the same pass
     template <typename T>
-    void restrict_(int l, const T* rf, T* bc) {
+    void restrict_(int l, const T* rf, T* bc, T* xc = nullptr) {
         Level& f = lv[l];
         Level& c = lv[l - 1];
         if (dim == 2)
             hipLaunchKernelGGL(k_restrict2d<T>, dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf, f.n,
-                               bc, c.n, f.r_start, f.rw<T>(), f.RW);
+                               bc, c.n, f.r_start, f.rw<T>(), f.RW, xc);
         else
             hipLaunchKernelGGL(k_restrict3d<T>, dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf, f.n,
-                               bc, c.n, f.r_start, f.rw<T>(), f.RW);
+                               bc, c.n, f.r_start, f.rw<T>(), f.RW, xc);
+        check_launch();
+    }
+
+    // Work items (64-point chunks x slices) of the largest colour of level l.
+    int colour_items(int l) const {
+        int mx = 0;
+        for (int c = 0; c < lv[l].ncol; ++c) mx = std::max(mx, colour_size_host(lv[l].n, p, dim, c));
+        return ((mx + 63) / 64) * (2 * p + 1);
+    }
+    void choose_tail() {
+        tail_top = 0;
+        if (opt.tail_items <= 0) return;
+        for (int l = 1; l <= L && l < kTailMaxLevels; ++l) {
+            if (colour_items(l) > opt.tail_items) break;
+            tail_top = l;
+        }
+    }
+
+    // V-cycle on levels 0..tail_top by one workgroup.
+    template <typename T>
+    void tail(const T* bt, T* xt) {
+        with_op<T>(0, [&](auto op0) {
+            using Op = decltype(op0);
+            TailArgs<Op> a{};
+            a.top = tail_top;
+            a.nu1 = opt.nu1;
+            a.nu2 = opt.nu2;
+            a.n0 = n0;
+            a.Ainv = Ainv0;
+            for (int l = 0; l <= tail_top; ++l) {
+                with_op<T>(l, [&](auto opl) {
+                    if constexpr (std::is_same_v<decltype(opl), Op>) a.op[l] = opl;
+                });
+                a.N[l] = lv[l].N;
+                a.x[l] = (l == tail_top) ? xt : lv[l].x<T>();
+                a.b[l] = (l == tail_top) ? (T*)bt : lv[l].b<T>();
+                a.r[l] = lv[l].r<T>();
+                if (l >= 1) {
+                    a.rs[l] = lv[l].r_start;
+                    a.rw[l] = lv[l].rw<T>();
+                    a.ps[l] = lv[l].p_start;
+                    a.pw[l] = lv[l].pw<T>();
+                    a.RW[l] = lv[l].RW;
+                    a.PW[l] = lv[l].PW;
+                }
+            }
+            hipLaunchKernelGGL((k_vcycle_tail<Op>), dim3(1), dim3(kTailThreads), 0, stream, a);
+        });
         check_launch();
     }
     template <typename T>
@@ -259,23 +309,29 @@ struct igamg_ctx {
     }
 
     // One V(nu1, nu2) cycle (Algorithm 2, mu = 1) in precision T on the finest
-    // level with right-hand side bL and iterate xL (in place).
+    // level with right-hand side bL and iterate xL (in place).  Levels above
+    // tail_top launch one kernel per step; levels 0..tail_top run in one
+    // single-workgroup kernel.
     template <typename T>
     void vcycle(const T* bL, T* xL) {
         if (L == 0) {
             coarse<T>(bL, xL);
             return;
         }
-        for (int l = L; l >= 1; --l) {
+        const int top = tail_top;
+        for (int l = L; l > top; --l) {
             const T* bl = (l == L) ? bL : lv[l].b<T>();
             T* xl = (l == L) ? xL : lv[l].x<T>();
             smooth<T>(l, bl, xl, opt.nu1);
             residual<T, T>(l, bl, xl, lv[l].r<T>(), 0, nullptr);
-            restrict_<T>(l, lv[l].r<T>(), lv[l - 1].b<T>());
-            fill(lv[l - 1].x<T>(), lv[l - 1].N);
+            restrict_<T>(l, lv[l].r<T>(), lv[l - 1].b<T>(), lv[l - 1].x<T>());
         }
-        coarse<T>(lv[0].b<T>(), lv[0].x<T>());
-        for (int l = 1; l <= L; ++l) {
+        if (top >= 1) {
+            tail<T>((top == L) ? bL : lv[top].b<T>(), (top == L) ? xL : lv[top].x<T>());
+        } else {
+            coarse<T>(lv[0].b<T>(), lv[0].x<T>());
+        }
+        for (int l = top + 1; l <= L; ++l) {
             const T* bl = (l == L) ? bL : lv[l].b<T>();
             T* xl = (l == L) ? xL : lv[l].x<T>();
             prolong_<T>(l, lv[l - 1].x<T>(), xl);
@@ -386,9 +442,18 @@ struct igamg_ctx {
         resnorm_async(S[0]);
     }
 
+    // Plain multigrid step on S[0]: one application of G and the residual norm.
+    void plain_cycle() {
+        G(S[0]);
+        resnorm_async(S[0]);
+    }
+
     void run_restart_cycle(int method, int q) {
         if (!opt.use_graphs) {
-            restart_cycle(method, q);
+            if (method == IGAMG_EXTRAP_NONE)
+                plain_cycle();
+            else
+                restart_cycle(method, q);
             return;
         }
         if (!graph_exec || graph_method != method || graph_q != q) {
@@ -402,7 +467,10 @@ struct igamg_ctx {
             }
             IGAMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
             try {
-                restart_cycle(method, q);
+                if (method == IGAMG_EXTRAP_NONE)
+                    plain_cycle();
+                else
+                    restart_cycle(method, q);
             } catch (...) {
                 hipGraph_t g;
                 (void)hipStreamEndCapture(stream, &g);
@@ -462,8 +530,8 @@ struct igamg_ctx {
                     int cs = colour_size_host(v.n, p, dim, c);
                     IGAMG_HIP(hipEventRecord(ev[2 * k], stream));
                     if (cs > 0)
-                        hipLaunchKernelGGL((k_gs_colour<Op>), dim3(grid_for(cs)), dim3(kBlock), 0,
-                                           stream, op, (const T*)bb, x, c);
+                        hipLaunchKernelGGL((k_gs_colour_sliced<Op>), dim3((cs + 63) / 64),
+                                           dim3(64 * Op::NW), 0, stream, op, (const T*)bb, x, c);
                     IGAMG_HIP(hipEventRecord(ev[2 * k + 1], stream));
                     tot_bytes += cs * per_point;
                 }
@@ -729,6 +797,7 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
         fill(v.x32, v.N);
         fill(v.b32, v.N);
     }
+    choose_tail();
     b = alloc<double>(lv[L].N);
     fill(b, lv[L].N);
     npartial = std::max<long long>(residual_blocks(L), 1024);
@@ -828,6 +897,7 @@ void igamg_options_default(igamg_options* opt) {
     opt->precision = IGAMG_FP64;
     opt->n_el_coarsest = 4;
     opt->use_graphs = 1;
+    opt->tail_items = 32;
     opt->stream = nullptr;
 }
 
@@ -972,19 +1042,26 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
         st.setup_ms = ctx->setup_ms;
         long long N = ctx->lv[ctx->L].N;
         if (method == IGAMG_EXTRAP_NONE) {
+            ctx->ensure_iterates(0);
+            ctx->copy(x_dev, ctx->S[0], N);
             for (int k = 0; k < max_restarts; ++k) {
-                ctx->G(x_dev);
-                ctx->resnorm_async(x_dev);
+                ctx->run_restart_cycle(IGAMG_EXTRAP_NONE, 0);
                 double rel = ctx->read_scal();
                 st.vcycles++;
                 st.restarts++;
                 st.rel_residual = rel;
-                if (!std::isfinite(rel)) throw Error(IGAMG_ENONFINITE, "non-finite residual");
+                if (!std::isfinite(rel)) {
+                    ctx->copy(ctx->S[0], x_dev, N);
+                    ctx->sync();
+                    throw Error(IGAMG_ENONFINITE, "non-finite residual");
+                }
                 if (rel <= tol) {
                     converged = true;
                     break;
                 }
             }
+            ctx->copy(ctx->S[0], x_dev, N);
+            ctx->sync();
         } else {
             need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
             ctx->ensure_iterates(q);

@@ -15,6 +15,8 @@
 // difference matrix, one-thread small solve, streaming combination.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace igamg {
@@ -95,21 +97,23 @@ struct Stencil2D {
         pt.I = pt.i + (long long)n * pt.j;
         return true;
     }
-    __device__ __forceinline__ T dot(const T* __restrict__ x, const Pt& pt, int c, int k,
-                                     T& diag) const {
-        const T* cf = coef + (size_t)c * S * ncp + k;
+    static constexpr int NW = W;  // one slice per stencil row
+    // Partial row product over stencil row bb = w - P (coefficients streamed
+    // once, coalesced across the 64 points of the wave); diag set by w == P.
+    __device__ __forceinline__ T slice(const T* __restrict__ x, const Pt& pt, int c, int k, int w,
+                                       T& diag) const {
+        const int bb = w - P;
+        const T* cf = coef + ((size_t)c * S + (size_t)W * w) * ncp + k;
+        const T* xr = x + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
+        T cv[W], xv[W];
+#pragma unroll
+        for (int a = 0; a < W; ++a) cv[a] = stream_load(cf + (size_t)a * ncp);
+#pragma unroll
+        for (int a = 0; a < W; ++a) xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
         T acc = 0;
 #pragma unroll
-        for (int bb = -P; bb <= P; ++bb) {
-            const T* xr = x + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
-#pragma unroll
-            for (int aa = -P; aa <= P; ++aa) {
-                const int o = (aa + P) + W * (bb + P);
-                T cv = stream_load(cf + (size_t)o * ncp);
-                if (aa == 0 && bb == 0) diag = cv;
-                acc = fma(cv, xr[clampi(pt.i + aa, 0, n - 1)], acc);
-            }
-        }
+        for (int a = 0; a < W; ++a) acc = fma(cv[a], xv[a], acc);
+        if (w == P) diag = cv[P];
         return acc;
     }
 };
@@ -146,32 +150,28 @@ struct Kron2D {
         pt.I = I;
         return true;
     }
-    // sum_b M_jb (sum_a K_ia x) + K_jb (sum_a M_ia x)
-    __device__ __forceinline__ T dot(const T* __restrict__ x, const Pt& pt, int, int,
-                                     T& diag) const {
-        T ki[W], mi[W];
+    static constexpr int NW = W;
+    // Row bb = w - P of the sum-factorised product: M_jb (K_i . x_row) + K_jb (M_i . x_row).
+    __device__ __forceinline__ T slice(const T* __restrict__ x, const Pt& pt, int, int, int w,
+                                       T& diag) const {
+        const int bb = w - P;
+        const T* xr = x + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
+        T ki[W], mi[W], xv[W];
 #pragma unroll
         for (int a = 0; a < W; ++a) {
             ki[a] = K[(size_t)pt.i * W + a];
             mi[a] = M[(size_t)pt.i * W + a];
+            xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
         }
-        T acc = 0;
+        T mj = M[(size_t)pt.j * W + w], kj = K[(size_t)pt.j * W + w];
+        T sk = 0, sm = 0;
 #pragma unroll
-        for (int bb = -P; bb <= P; ++bb) {
-            const T* xr = x + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
-            T sk = 0, sm = 0;
-#pragma unroll
-            for (int aa = -P; aa <= P; ++aa) {
-                T xv = xr[clampi(pt.i + aa, 0, n - 1)];
-                sk = fma(ki[aa + P], xv, sk);
-                sm = fma(mi[aa + P], xv, sm);
-            }
-            T mj = M[(size_t)pt.j * W + bb + P], kj = K[(size_t)pt.j * W + bb + P];
-            acc = fma(mj, sk, acc);
-            acc = fma(kj, sm, acc);
+        for (int a = 0; a < W; ++a) {
+            sk = fma(ki[a], xv[a], sk);
+            sm = fma(mi[a], xv[a], sm);
         }
-        diag = ki[P] * M[(size_t)pt.j * W + P] + mi[P] * K[(size_t)pt.j * W + P];
-        return acc;
+        if (w == P) diag = ki[P] * mj + mi[P] * kj;
+        return fma(mj, sk, kj * sm);
     }
 };
 
@@ -213,9 +213,11 @@ struct Kron3D {
         pt.I = I;
         return true;
     }
-    // sum_c [M_kc (sum_b M_jb Kx + K_jb Mx) + K_kc (sum_b M_jb Mx)]
-    __device__ __forceinline__ T dot(const T* __restrict__ x, const Pt& pt, int, int,
-                                     T& diag) const {
+    static constexpr int NW = W;
+    // Plane cc = w - P: M_kc (sum_b M_jb Kx + K_jb Mx) + K_kc (sum_b M_jb Mx).
+    __device__ __forceinline__ T slice(const T* __restrict__ x, const Pt& pt, int, int, int w,
+                                       T& diag) const {
+        const int cc = w - P;
         T ki[W], mi[W], kj[W], mj[W];
 #pragma unroll
         for (int a = 0; a < W; ++a) {
@@ -224,33 +226,28 @@ struct Kron3D {
             kj[a] = K[(size_t)pt.j * W + a];
             mj[a] = M[(size_t)pt.j * W + a];
         }
-        T acc = 0;
         const size_t nn = (size_t)n * n;
+        const T* xs = x + (size_t)clampi(pt.k + cc, 0, n - 1) * nn;
+        T y1 = 0, y2 = 0;
 #pragma unroll
-        for (int cc = -P; cc <= P; ++cc) {
-            const T* xs = x + (size_t)clampi(pt.k + cc, 0, n - 1) * nn;
-            T y1 = 0, y2 = 0;
+        for (int bb = -P; bb <= P; ++bb) {
+            const T* xr = xs + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
+            T xv[W];
 #pragma unroll
-            for (int bb = -P; bb <= P; ++bb) {
-                const T* xr = xs + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
-                T sk = 0, sm = 0;
+            for (int a = 0; a < W; ++a) xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
+            T sk = 0, sm = 0;
 #pragma unroll
-                for (int aa = -P; aa <= P; ++aa) {
-                    T xv = xr[clampi(pt.i + aa, 0, n - 1)];
-                    sk = fma(ki[aa + P], xv, sk);
-                    sm = fma(mi[aa + P], xv, sm);
-                }
-                y1 = fma(mj[bb + P], sk, y1);
-                y1 = fma(kj[bb + P], sm, y1);
-                y2 = fma(mj[bb + P], sm, y2);
+            for (int a = 0; a < W; ++a) {
+                sk = fma(ki[a], xv[a], sk);
+                sm = fma(mi[a], xv[a], sm);
             }
-            T mk = M[(size_t)pt.k * W + cc + P], kk = K[(size_t)pt.k * W + cc + P];
-            acc = fma(mk, y1, acc);
-            acc = fma(kk, y2, acc);
+            y1 = fma(mj[bb + P], sk, y1);
+            y1 = fma(kj[bb + P], sm, y1);
+            y2 = fma(mj[bb + P], sm, y2);
         }
-        T mkc = M[(size_t)pt.k * W + P], kkc = K[(size_t)pt.k * W + P];
-        diag = ki[P] * mj[P] * mkc + mi[P] * kj[P] * mkc + mi[P] * mj[P] * kkc;
-        return acc;
+        T mk = M[(size_t)pt.k * W + w], kk = K[(size_t)pt.k * W + w];
+        if (w == P) diag = ki[P] * mj[P] * mk + mi[P] * kj[P] * mk + mi[P] * mj[P] * kk;
+        return fma(mk, y1, kk * y2);
     }
 };
 
@@ -259,61 +256,87 @@ struct Kron3D {
 
 // One colour of multicolour Gauss-Seidel: every point of colour c is updated
 // from the values of x at the start of the pass (no two points of one colour
-// are coupled, so the update order inside the pass is irrelevant).
+// are coupled, so the update order inside the pass is irrelevant):
+// x_I <- x_I + (b_I - (A x)_I) / A_II.
+// Layout: a block holds 64 points (one per lane) and Op::NW waves;
+// wave w computes the partial product of stencil slice w for its 64 points
+// (all of the slice's loads in flight at once), the partials meet in LDS and
+// are summed in slice order.
 template <class Op>
-__global__ void __launch_bounds__(kBlock) k_gs_colour(Op A, const typename Op::T* __restrict__ b,
-                                                      typename Op::T* __restrict__ x, int c) {
+__global__ void __launch_bounds__(64 * Op::NW) k_gs_colour_sliced(Op A,
+                                                                  const typename Op::T* __restrict__ b,
+                                                                  typename Op::T* __restrict__ x,
+                                                                  int c) {
     using T = typename Op::T;
-    int k = xcd_swizzle(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    __shared__ T part[Op::NW][64];
+    __shared__ T dg[64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int k = xcd_swizzle(blockIdx.x, gridDim.x) * 64 + lane;
     typename Op::Pt pt;
-    if (!A.point(c, k, pt)) return;
-    T diag = 1;
-    T acc = A.dot(x, pt, c, k, diag);
-    x[pt.I] = x[pt.I] + (b[pt.I] - acc) / diag;
+    bool ok = A.point(c, k, pt);
+    T d = 1, sl = 0;
+    if (ok) sl = A.slice(x, pt, c, k, w, d);
+    part[w][lane] = sl;
+    if (w == Op::NW / 2) dg[lane] = d;
+    __syncthreads();
+    if (w == 0 && ok) {
+        T acc = 0;
+#pragma unroll
+        for (int v = 0; v < Op::NW; ++v) acc += part[v][lane];
+        x[pt.I] = x[pt.I] + (b[pt.I] - acc) / dg[lane];
+    }
 }
 
-// Residual r = b - A x (mode 0), product y = A x (mode 1) or damped Jacobi
-// y = x + omega (b - A x) / A_II (mode 2).  Colour-ordered traversal for the
-// stored stencil (coalesced coefficient streams), natural order otherwise.
-// When partial != nullptr each block writes the sum of squares of its outputs.
+// Residual-type products with the sliced layout: r = b - A x (mode 0),
+// y = A x (mode 1), damped Jacobi step (mode 2); optional per-block sums of
+// squares.  Colour-ordered traversal for stored stencils, natural otherwise.
 template <class Op, typename Tout>
-__global__ void __launch_bounds__(kBlock) k_residual(Op A, const typename Op::T* __restrict__ b,
-                                                     const typename Op::T* __restrict__ x,
-                                                     Tout* __restrict__ out, int mode,
-                                                     double omega, long long N,
-                                                     double* __restrict__ partial) {
+__global__ void __launch_bounds__(64 * Op::NW) k_residual_sliced(
+    Op A, const typename Op::T* __restrict__ b, const typename Op::T* __restrict__ x,
+    Tout* __restrict__ out, int mode, double omega, long long N, double* __restrict__ partial) {
     using T = typename Op::T;
-    __shared__ double red[kBlock / 64];
+    __shared__ T part[Op::NW][64];
+    __shared__ T dg[64];
+    __shared__ double red[Op::NW];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int blk = xcd_swizzle(blockIdx.x, gridDim.x);
     typename Op::Pt pt;
     bool ok;
     int c = 0, k = 0;
     if constexpr (Op::kColourOrder) {
-        int bpc = (A.ncp + kBlock - 1) / kBlock;
+        int bpc = A.ncp / 64;
         c = blk / bpc;
-        k = (blk - c * bpc) * kBlock + threadIdx.x;
+        k = (blk - c * bpc) * 64 + lane;
         ok = (c < Op::NC) && A.point(c, k, pt);
     } else {
-        long long I = (long long)blk * kBlock + threadIdx.x;
+        long long I = (long long)blk * 64 + lane;
         ok = (I < N) && A.point_nat(I, pt);
     }
+    T d = 1, sl = 0;
+    if (ok) sl = A.slice(x, pt, c, k, w, d);
+    part[w][lane] = sl;
+    if (w == Op::NW / 2) dg[lane] = d;
+    __syncthreads();
     double sq = 0.0;
-    if (ok) {
-        T diag = 1;
-        T acc = A.dot(x, pt, c, k, diag);
+    if (w == 0 && ok) {
+        T acc = 0;
+#pragma unroll
+        for (int v = 0; v < Op::NW; ++v) acc += part[v][lane];
         T v;
         if (mode == 0)
             v = b[pt.I] - acc;
         else if (mode == 1)
             v = acc;
         else
-            v = x[pt.I] + (T)omega * (b[pt.I] - acc) / diag;
+            v = x[pt.I] + (T)omega * (b[pt.I] - acc) / dg[lane];
         out[pt.I] = (Tout)v;
         sq = (double)v * (double)v;
     }
     if (partial) {
-        double s = block_sum(sq, red);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        if (w == 0) {
+            double t = wave_sum(sq);
+            if (lane == 0) partial[blockIdx.x] = t;
+        }
     }
 }
 
@@ -373,13 +396,17 @@ __global__ void __launch_bounds__(kBlock) k_add_f32_to_f64(const float* __restri
 // ---------------------------------------------------------------------------
 // transfers (R = P^T, P = P1 (x) P1 [(x) P1])
 
+// bc = R rf on the coarse grid; xc (if given) is zeroed: the coarse-grid
+// correction of Algorithm 2 starts from a zero error.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict2d(const T* __restrict__ rf, int nf,
                                                        T* __restrict__ bc, int nc,
                                                        const int* __restrict__ rs,
-                                                       const T* __restrict__ rw, int RW) {
+                                                       const T* __restrict__ rw, int RW,
+                                                       T* __restrict__ xc) {
     long long C = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (C >= (long long)nc * nc) return;
+    if (xc) xc[C] = 0;
     int J = (int)(C / nc), I = (int)(C - (long long)J * nc);
     int si = rs[I], sj = rs[J];
     T acc = 0;
@@ -417,10 +444,12 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict3d(const T* __restrict__ rf, int nf,
                                                        T* __restrict__ bc, int nc,
                                                        const int* __restrict__ rs,
-                                                       const T* __restrict__ rw, int RW) {
+                                                       const T* __restrict__ rw, int RW,
+                                                       T* __restrict__ xc) {
     long long C = (long long)blockIdx.x * kBlock + threadIdx.x;
     long long ncc = (long long)nc * nc;
     if (C >= ncc * nc) return;
+    if (xc) xc[C] = 0;
     int K = (int)(C / ncc);
     long long rem = C - (long long)K * ncc;
     int J = (int)(rem / nc), I = (int)(rem - (long long)J * nc);
@@ -682,6 +711,155 @@ __global__ void __launch_bounds__(kBlock) k_extrap_combine(IterPtrs S, int q, lo
         prev = nxt;
     }
     out[I] = t;
+}
+
+
+// ---------------------------------------------------------------------------
+// single-workgroup V-cycle on the small levels 0..top (one launch replaces the
+// hundreds of tiny launches those levels would need; colour passes are
+// separated by workgroup barriers and the data stay in L2)
+
+constexpr int kTailMaxLevels = 8;
+constexpr int kTailThreads = 1024;
+constexpr int kTailMaxChunks = 8;  // 64-point chunks held in LDS at once
+
+template <class Op>
+struct TailArgs {
+    using T = typename Op::T;
+    int top;                        // finest level handled here
+    int nu1, nu2;
+    int n0;                         // coarsest unknowns
+    const double* Ainv;             // coarsest inverse (FP64)
+    Op op[kTailMaxLevels];
+    long long N[kTailMaxLevels];
+    T* x[kTailMaxLevels];
+    T* b[kTailMaxLevels];
+    T* r[kTailMaxLevels];
+    const int* rs[kTailMaxLevels];  // transfer tables between l-1 and l
+    const T* rw[kTailMaxLevels];
+    const int* ps[kTailMaxLevels];
+    const T* pw[kTailMaxLevels];
+    int RW[kTailMaxLevels], PW[kTailMaxLevels];
+};
+
+// One colour pass (mode 0) or residual of colour c (mode 1, into r) by the
+// whole block, sliced as in the multi-block kernels.
+template <class Op>
+__device__ void tail_colour(const Op& A, const typename Op::T* b, typename Op::T* x,
+                            typename Op::T* r, int c, int mode, typename Op::T* part,
+                            typename Op::T* dg) {
+    using T = typename Op::T;
+    constexpr int NW = Op::NW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kTailThreads / 64;
+    const int cs = A.colour_size(c);
+    for (int ch0 = 0; ch0 * 64 < cs; ch0 += kTailMaxChunks) {
+        int nch = min(kTailMaxChunks, (cs + 63) / 64 - ch0);
+        for (int it = wave; it < nch * NW; it += nwave) {
+            int ch = it / NW, w = it - ch * NW;
+            int k = (ch0 + ch) * 64 + lane;
+            typename Op::Pt pt;
+            T d = 1, sl = 0;
+            if (A.point(c, k, pt)) sl = A.slice(x, pt, c, k, w, d);
+            part[(ch * NW + w) * 64 + lane] = sl;
+            if (w == NW / 2) dg[ch * 64 + lane] = d;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < nch * 64; t += kTailThreads) {
+            int ch = t >> 6, ln = t & 63;
+            int k = (ch0 + ch) * 64 + ln;
+            typename Op::Pt pt;
+            if (!A.point(c, k, pt)) continue;
+            T acc = 0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) acc += part[(ch * NW + v) * 64 + ln];
+            if (mode == 0)
+                x[pt.I] = x[pt.I] + (b[pt.I] - acc) / dg[t];
+            else
+                r[pt.I] = b[pt.I] - acc;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ void tail_restrict(const T* rf, int nf, T* bc, T* xc, int nc, const int* rs,
+                              const T* rw, int RW, int dim) {
+    long long Nc = (long long)nc * nc * (dim == 3 ? nc : 1);
+    for (long long C = threadIdx.x; C < Nc; C += kTailThreads) {
+        int I = (int)(C % nc), J = (int)((C / nc) % nc), K = (dim == 3) ? (int)(C / ((long long)nc * nc)) : 0;
+        T acc = 0;
+        int KR = (dim == 3) ? RW : 1;
+        for (int cc = 0; cc < KR; ++cc) {
+            T wk = (dim == 3) ? rw[(size_t)K * RW + cc] : (T)1;
+            size_t zoff = (dim == 3) ? (size_t)min(rs[K] + cc, nf - 1) * nf * nf : 0;
+            T s2 = 0;
+            for (int bq = 0; bq < RW; ++bq) {
+                const T* row = rf + zoff + (size_t)min(rs[J] + bq, nf - 1) * nf;
+                T s1 = 0;
+                for (int a = 0; a < RW; ++a) s1 = fma(rw[(size_t)I * RW + a], row[min(rs[I] + a, nf - 1)], s1);
+                s2 = fma(rw[(size_t)J * RW + bq], s1, s2);
+            }
+            acc = fma(wk, s2, acc);
+        }
+        bc[C] = acc;
+        xc[C] = 0;
+    }
+}
+
+template <typename T>
+__device__ void tail_prolong(const T* ec, int nc, T* xf, int nf, const int* ps, const T* pw,
+                             int PW, int dim) {
+    long long Nf = (long long)nf * nf * (dim == 3 ? nf : 1);
+    for (long long F = threadIdx.x; F < Nf; F += kTailThreads) {
+        int i = (int)(F % nf), j = (int)((F / nf) % nf), k = (dim == 3) ? (int)(F / ((long long)nf * nf)) : 0;
+        T acc = 0;
+        int KP = (dim == 3) ? PW : 1;
+        for (int cc = 0; cc < KP; ++cc) {
+            T wk = (dim == 3) ? pw[(size_t)k * PW + cc] : (T)1;
+            size_t zoff = (dim == 3) ? (size_t)min(ps[k] + cc, nc - 1) * nc * nc : 0;
+            T s2 = 0;
+            for (int bq = 0; bq < PW; ++bq) {
+                const T* row = ec + zoff + (size_t)min(ps[j] + bq, nc - 1) * nc;
+                T s1 = 0;
+                for (int a = 0; a < PW; ++a) s1 = fma(pw[(size_t)i * PW + a], row[min(ps[i] + a, nc - 1)], s1);
+                s2 = fma(pw[(size_t)j * PW + bq], s1, s2);
+            }
+            acc = fma(wk, s2, acc);
+        }
+        xf[F] += acc;
+    }
+}
+
+// V-cycle (Algorithm 2, mu = 1) on levels 0..top with right-hand side b[top]
+// and iterate x[top] (in place), by one workgroup.
+template <class Op>
+__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs<Op> a) {
+    using T = typename Op::T;
+    constexpr int NW = Op::NW;
+    constexpr int DIM = std::is_same<typename Op::Pt, Pt3>::value ? 3 : 2;
+    __shared__ T part[kTailMaxChunks * NW * 64];
+    __shared__ T dg[kTailMaxChunks * 64];
+    for (int l = a.top; l >= 1; --l) {
+        const Op& A = a.op[l];
+        for (int s = 0; s < a.nu1; ++s)
+            for (int c = 0; c < Op::NC; ++c) tail_colour(A, a.b[l], a.x[l], a.r[l], c, 0, part, dg);
+        for (int c = 0; c < Op::NC; ++c) tail_colour(A, a.b[l], a.x[l], a.r[l], c, 1, part, dg);
+        tail_restrict(a.r[l], A.n, a.b[l - 1], a.x[l - 1], a.op[l - 1].n, a.rs[l], a.rw[l], a.RW[l], DIM);
+        __syncthreads();
+    }
+    for (int r = threadIdx.x; r < a.n0; r += kTailThreads) {
+        double s = 0.0;
+        for (int c = 0; c < a.n0; ++c) s = fma(a.Ainv[(size_t)r * a.n0 + c], (double)a.b[0][c], s);
+        a.x[0][r] = (T)s;
+    }
+    __syncthreads();
+    for (int l = 1; l <= a.top; ++l) {
+        const Op& A = a.op[l];
+        tail_prolong(a.x[l - 1], a.op[l - 1].n, a.x[l], A.n, a.ps[l], a.pw[l], a.PW[l], DIM);
+        __syncthreads();
+        for (int s = 0; s < a.nu2; ++s)
+            for (int c = 0; c < Op::NC; ++c) tail_colour(A, a.b[l], a.x[l], a.r[l], c, 0, part, dg);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("smoother", ctypes.c_int),
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("n_el_coarsest", ctypes.c_int), ("use_graphs", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("tail_items", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):

@@ -139,9 +139,17 @@ def test_multicolour_sweeps(geom, n_el, p):
         assert rel(host(xg), xr) < 1e-13
 
 
-@pytest.mark.parametrize("geom,n_el,p", CASES_ALL)
-def test_vcycle_iterates(geom, n_el, p):
-    s, H, b = case(geom, n_el, p)
+VCYCLE_CASES = ([(g, n, p, 32) for g, n, p in CASES_ALL] + [(g, n, p, 0) for g, n, p in CASES_ALL] +
+                [("annulus", 128, 3, 32), ("square", 128, 2, 32), ("annulus", 64, 5, 32),
+                 ("cube", 16, 2, 32)])
+
+
+@pytest.mark.parametrize("geom,n_el,p,tail", VCYCLE_CASES)
+def test_vcycle_iterates(geom, n_el, p, tail):
+    """Per-iterate parity of V-cycles; tail = 0 runs every level with
+    multi-block launches, tail = 32 runs the small levels in the
+    single-workgroup kernel (the larger grids use both paths)."""
+    s, H, b = case(geom, n_el, p, tail_items=tail)
     N = len(b)
     xg = torch.zeros(N, dtype=torch.float64, device=DEV)
     xr = np.zeros(N)
@@ -223,11 +231,12 @@ def test_breakdown_rules():
         np.testing.assert_allclose(g, gr, atol=1e-12)
 
 
-@pytest.mark.parametrize("geom,n_el,p", [("annulus", 32, 3), ("annulus", 32, 5), ("square", 64, 2),
-                                         ("square", 32, 4), ("cube", 8, 2)])
+@pytest.mark.parametrize("geom,n_el,p,tail", [("annulus", 32, 3, 32), ("annulus", 32, 5, 0),
+                                              ("square", 64, 2, 32), ("square", 32, 4, 0),
+                                              ("cube", 8, 2, 32), ("annulus", 128, 4, 32)])
 @pytest.mark.parametrize("method", [igamg.EXTRAP_NONE, igamg.RRE, igamg.MPE])
-def test_solve_matches_oracle(geom, n_el, p, method):
-    s, H, b = case(geom, n_el, p)
+def test_solve_matches_oracle(geom, n_el, p, tail, method):
+    s, H, b = case(geom, n_el, p, tail_items=tail)
     N = len(b)
     A = H.fine.A
     nb = np.linalg.norm(b)
