@@ -201,6 +201,60 @@ igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q,
 igamg_status igamg_profile_smoother(igamg_ctx* ctx, int level, int precision, int nsweeps,
                                     double* avg_ms, double* bytes, int* launches);
 
+/* ---- Learned smoother (2D only) ------------------------------------------
+ * Per level l >= 1 a network N_l (3x3 convolutions 1 -> 16 -> 16 -> 1, ReLU,
+ * zero padding, no biases; BF16 weights, FP32 accumulation on MFMA) replaces
+ * the first pre-smoothing sweep: z = D^{-1} r / sigma with sigma = RMS(D^{-1} r),
+ * x += sigma N_l(z).  Levels run by the single-workgroup kernel keep plain
+ * Gauss-Seidel.  Weights use the canonical layout W1[16][9], W2[16][16][9],
+ * W3[16][9] (tap = 3 dy + dx), 2592 BF16 values per level. */
+typedef struct {
+    int n_rhs;               /* training right-hand sides                        */
+    const double* modes;     /* n_rhs * n_modes mode rows (host), as set_rhs_field */
+    int n_modes;
+    int vcycles_per_rhs;     /* plain V-cycles recorded per right-hand side (3)  */
+    int epochs;              /* passes over each level's patches (10)            */
+    int batch;               /* 64 x 64 patches per Adam step (32)               */
+    double lr;               /* Adam step size (1e-3)                            */
+    unsigned long long seed; /* weight initialisation and shuffling              */
+    const double* val_modes; /* validation right-hand side (NULL: first training one) */
+    int val_n_modes;
+    int val_vcycles;         /* V-cycles of the contraction measurement (12)     */
+    double solve_tol;        /* relative tolerance of the level solves (1e-12)   */
+} igamg_train_options;
+
+typedef struct {
+    int levels_trained;
+    int patches;             /* training patches over all levels                 */
+    double loss_first[16];   /* mean loss of the first / last epoch per level    */
+    double loss_last[16];
+    double rho_plain;        /* measured residual contraction per V-cycle        */
+    double rho_learned;
+    int accepted;            /* 1 if rho_learned < rho_plain (learned step enabled) */
+    double train_ms;
+} igamg_train_report;
+
+void igamg_train_options_default(igamg_train_options* o);
+/* Generates residual / target pairs from plain FP64 V-cycles on the given
+ * right-hand sides (the target is the part of the algebraic error that the
+ * coarse-grid correction cannot remove, e - P A_{l-1}^{-1} R r, from tight level
+ * solves), trains every level's network on the device (Adam, FP32 master
+ * weights), measures the contraction with and without the networks and
+ * enables them only if they contract better.  The right-hand side and the
+ * iterate state of the context are restored.  Errors: EINVAL (3D, bad options). */
+igamg_status igamg_train_smoother(igamg_ctx* ctx, const igamg_train_options* opt,
+                                  igamg_train_report* report);
+/* Turns the learned step on (1) or off (0); EINVAL if no weights are loaded. */
+igamg_status igamg_set_learned(igamg_ctx* ctx, int enabled);
+igamg_status igamg_get_smoother_weights(igamg_ctx* ctx, int level, uint16_t* bf16, size_t n);
+igamg_status igamg_set_smoother_weights(igamg_ctx* ctx, int level, const uint16_t* bf16, size_t n);
+/* y = N_l(z) on level l's grid (device FP32 vectors of the level's length). */
+igamg_status igamg_smoother_forward(igamg_ctx* ctx, int level, const float* z_dev, float* y_dev);
+/* Loss mean((N_l(z) - t)^2) over the level's grid and its gradient with
+ * respect to the canonical weights (host, 2592 FP32 values). */
+igamg_status igamg_smoother_loss_grad(igamg_ctx* ctx, int level, const float* z_dev,
+                                      const float* t_dev, double* loss, float* grad);
+
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* igamg_last_error(void);
 

@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "host_spline.hpp"
 #include "kernels.hpp"
+#include "learned.hpp"
 
 using namespace igamg;
 
@@ -98,6 +99,18 @@ struct igamg_ctx {
     hipGraph_t graph = nullptr;
     int graph_method = -1, graph_q = -1;
     int tail_top = 0;  // levels 0..tail_top run in the single-workgroup kernel
+    // learned smoother
+    struct Net {
+        bool have = false;
+        uint16_t *wc = nullptr, *w2f = nullptr, *w2b = nullptr;
+        float *master = nullptr, *m = nullptr, *v = nullptr;
+    };
+    std::vector<Net> nets;
+    std::vector<double*> diag64;
+    std::vector<float*> diag32;
+    float* lz = nullptr;       // z = D^{-1} r of the current level (FP32)
+    bool learned_on = false;
+    double rho_plain_ref = 0.0;  // measured plain contraction (fallback threshold)
 
     ~igamg_ctx() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -308,36 +321,72 @@ struct igamg_ctx {
         check_launch();
     }
 
-    // One V(nu1, nu2) cycle (Algorithm 2, mu = 1) in precision T on the finest
-    // level with right-hand side bL and iterate xL (in place).  Levels above
-    // tail_top launch one kernel per step; levels 0..tail_top run in one
-    // single-workgroup kernel.
+    template <typename T> T* diag(int l) {
+        if constexpr (std::is_same_v<T, double>) return diag64[l]; else return diag32[l];
+    }
+    bool use_learned(int l) const {
+        return learned_on && l > tail_top && l < (int)nets.size() && nets[l].have;
+    }
+    // Learned first pre-smoothing step on level l: x += sigma N_l(D^{-1} r / sigma).
     template <typename T>
-    void vcycle(const T* bL, T* xL) {
-        if (L == 0) {
-            coarse<T>(bL, xL);
+    void learned_step(int l, const T* bl, T* xl) {
+        Level& v = lv[l];
+        residual<T, T>(l, bl, xl, v.r<T>(), 0, nullptr);
+        unsigned nb = grid_for(v.N);
+        hipLaunchKernelGGL(k_learned_prep<T>, dim3(nb), dim3(kBlock), 0, stream, (const T*)v.r<T>(),
+                           (const T*)diag<T>(l), v.N, lz, partial);
+        hipLaunchKernelGGL(k_learned_sigma, dim3(1), dim3(kBlock), 0, stream, partial, (int)nb, v.N,
+                           scal + 2);
+        LImage im{lz, v.n, v.n, v.n, 0, 0};
+        LearnedW W{nets[l].wc, nets[l].w2f, nets[l].w2b};
+        int tiles = (v.n + kLTile - 1) / kLTile;
+        hipLaunchKernelGGL(k_learned_apply<T>, dim3(tiles * tiles), dim3(kLThreads), 0, stream, im, W,
+                           (const double*)(scal + 2), xl, (float*)nullptr);
+        check_launch();
+    }
+
+    // One V(nu1, nu2) cycle (Algorithm 2, mu = 1) in precision T starting on
+    // level `top` with right-hand side bt and iterate xt (in place).  Levels
+    // above tail_top launch one kernel per step; levels 0..min(top, tail_top)
+    // run in one single-workgroup kernel.  `rec`, when given, is called at the
+    // start of every level l >= 1 with (l, b_l, x_l).
+    template <typename T, class Rec = std::nullptr_t>
+    void vcycle_from(int top, const T* bt, T* xt, Rec rec = nullptr) {
+        if (top == 0) {
+            coarse<T>(bt, xt);
             return;
         }
-        const int top = tail_top;
-        for (int l = L; l > top; --l) {
-            const T* bl = (l == L) ? bL : lv[l].b<T>();
-            T* xl = (l == L) ? xL : lv[l].x<T>();
-            smooth<T>(l, bl, xl, opt.nu1);
+        const int tt = std::min(tail_top, top);
+        for (int l = top; l > tt; --l) {
+            const T* bl = (l == top) ? bt : lv[l].b<T>();
+            T* xl = (l == top) ? xt : lv[l].x<T>();
+            if constexpr (!std::is_same_v<Rec, std::nullptr_t>) rec(l, bl, xl);
+            if (use_learned(l)) {
+                learned_step<T>(l, bl, xl);
+                smooth<T>(l, bl, xl, opt.nu1 - 1);
+            } else {
+                smooth<T>(l, bl, xl, opt.nu1);
+            }
             residual<T, T>(l, bl, xl, lv[l].r<T>(), 0, nullptr);
             restrict_<T>(l, lv[l].r<T>(), lv[l - 1].b<T>(), lv[l - 1].x<T>());
         }
-        if (top >= 1) {
-            tail<T>((top == L) ? bL : lv[top].b<T>(), (top == L) ? xL : lv[top].x<T>());
+        if (tt >= 1) {
+            int save = tail_top;
+            tail_top = tt;
+            tail<T>((tt == top) ? bt : lv[tt].b<T>(), (tt == top) ? xt : lv[tt].x<T>());
+            tail_top = save;
         } else {
             coarse<T>(lv[0].b<T>(), lv[0].x<T>());
         }
-        for (int l = top + 1; l <= L; ++l) {
-            const T* bl = (l == L) ? bL : lv[l].b<T>();
-            T* xl = (l == L) ? xL : lv[l].x<T>();
+        for (int l = tt + 1; l <= top; ++l) {
+            const T* bl = (l == top) ? bt : lv[l].b<T>();
+            T* xl = (l == top) ? xt : lv[l].x<T>();
             prolong_<T>(l, lv[l - 1].x<T>(), xl);
             smooth<T>(l, bl, xl, opt.nu2);
         }
     }
+    template <typename T>
+    void vcycle(const T* bL, T* xL) { vcycle_from<T>(L, bL, xL); }
 
     // The fixed-point map G of eq. (7) on the finest level, in place.
     void G(double* x) {
@@ -556,6 +605,14 @@ struct igamg_ctx {
         else
             profile_smoother_t<float>(l, nsweeps, avg_ms, bytes, launches);
     }
+
+    // ---- learned smoother support
+    void setup_diag();
+    void ensure_net(int l);
+    double level_resnorm(int l, const double* f, const double* x, double fnorm);
+    int level_solve(int l, const double* f, double* u, double tol, int maxit);
+    void train(const igamg_train_options& o, igamg_train_report& rep);
+    double measure_rho(int vcycles, bool learned);
 
     void setup(const igamg_geometry& g, int degree, int levels);
     void setup_levels(int n_el, int levels);
@@ -805,6 +862,7 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
     scal = alloc<double>(8);
     coeffs = alloc<ExtrapCoeffs>(1);
     IGAMG_HIP(hipHostMalloc((void**)&host_scal, 8 * sizeof(double), hipHostMallocDefault));
+    setup_diag();
     IGAMG_HIP(hipHostMalloc((void**)&host_coeffs, sizeof(ExtrapCoeffs), hipHostMallocDefault));
     set_bnorm(0.0);
     setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -855,6 +913,346 @@ void igamg_ctx::set_rhs_field(const double* modes, int n_modes) {
     }
     release(dmodes);
     set_bnorm(vector_norm(b, f.N));
+}
+
+// ---------------------------------------------------------------------------
+// learned smoother: diagonals, level solves, training
+
+void igamg_ctx::setup_diag() {
+    diag64.assign(L + 1, nullptr);
+    diag32.assign(L + 1, nullptr);
+    for (int l = 0; l <= L; ++l) {
+        Level& v = lv[l];
+        diag64[l] = alloc<double>(v.N);
+        diag32[l] = alloc<float>(v.N);
+        if (kind == OP_STENCIL2D) {
+            with_p([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                hipLaunchKernelGGL(k_diag_stencil<P>, dim3(grid_for(v.N)), dim3(kBlock), 0, stream,
+                                   v.coef64, v.n, v.ncp, diag64[l], diag32[l]);
+            });
+            check_launch();
+        } else {
+            std::vector<double> d(v.N);
+            std::vector<float> d32(v.N);
+            int n = v.n;
+            for (long long I = 0; I < v.N; ++I) {
+                int i = (int)(I % n), j = (int)((I / n) % n), k = (int)(I / ((long long)n * n));
+                double val = (dim == 2)
+                                 ? v.Kh.at(i, 0) * v.Mh.at(j, 0) + v.Mh.at(i, 0) * v.Kh.at(j, 0)
+                                 : v.Kh.at(i, 0) * v.Mh.at(j, 0) * v.Mh.at(k, 0) +
+                                       v.Mh.at(i, 0) * v.Kh.at(j, 0) * v.Mh.at(k, 0) +
+                                       v.Mh.at(i, 0) * v.Mh.at(j, 0) * v.Kh.at(k, 0);
+                d[I] = val;
+                d32[I] = (float)val;
+            }
+            IGAMG_HIP(hipMemcpyAsync(diag64[l], d.data(), d.size() * 8, hipMemcpyHostToDevice, stream));
+            IGAMG_HIP(hipMemcpyAsync(diag32[l], d32.data(), d32.size() * 4, hipMemcpyHostToDevice, stream));
+            sync();
+        }
+    }
+    lz = alloc<float>(lv[L].N);
+    nets.assign(L + 1, Net{});
+}
+
+void igamg_ctx::ensure_net(int l) {
+    Net& t = nets[l];
+    if (t.wc) return;
+    t.wc = alloc<uint16_t>(kLWeights);
+    t.w2f = alloc<uint16_t>(kLW2);
+    t.w2b = alloc<uint16_t>(kLW2);
+    t.master = alloc<float>(kLWeights);
+    t.m = alloc<float>(kLWeights);
+    t.v = alloc<float>(kLWeights);
+}
+
+// ||f - A_l x|| / fnorm on level l (host value).
+double igamg_ctx::level_resnorm(int l, const double* f, const double* x, double fnorm) {
+    residual<double, double>(l, f, x, lv[l].r64, 0, partial);
+    long long nb = residual_blocks(l);
+    hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(kBlock), 0, stream, partial, (int)nb,
+                       fnorm > 0 ? fnorm : 1.0, (const double*)nullptr, scal);
+    check_launch();
+    return read_scal();
+}
+
+// Plain FP64 V-cycles from level l until ||f - A u|| <= tol ||f||; u holds the
+// initial guess.  Returns the number of cycles (level 0: direct solve).
+int igamg_ctx::level_solve(int l, const double* f, double* u, double tol, int maxit) {
+    if (l == 0) {
+        coarse<double>(f, u);
+        return 0;
+    }
+    double fn = vector_norm(f, lv[l].N);
+    if (fn == 0.0) {
+        fill(u, lv[l].N);
+        return 0;
+    }
+    for (int k = 1; k <= maxit; ++k) {
+        vcycle_from<double>(l, f, u);
+        if (level_resnorm(l, f, u, fn) <= tol) return k;
+    }
+    return maxit;
+}
+
+// Geometric-mean residual contraction per V-cycle over the second half of
+// `vcycles` plain FP64 V-cycles from zero on the current right-hand side.
+double igamg_ctx::measure_rho(int vcycles, bool learned) {
+    bool save = learned_on;
+    learned_on = learned;
+    double* x = alloc<double>(lv[L].N);
+    fill(x, lv[L].N);
+    int h = vcycles / 2;
+    double r_h = 0.0, r_e = 0.0;
+    for (int k = 1; k <= vcycles; ++k) {
+        vcycle<double>(b, x);
+        if (k == h || k == vcycles) {
+            resnorm_async(x);
+            double r = read_scal();
+            if (k == h) r_h = r; else r_e = r;
+        }
+    }
+    release(x);
+    learned_on = save;
+    if (!(r_h > 0.0) || !(r_e > 0.0)) return 0.0;
+    return std::pow(r_e / r_h, 1.0 / (vcycles - h));
+}
+
+void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (dim != 2) throw Error(IGAMG_EINVAL, "the learned smoother is 2D only");
+    if (o.n_rhs < 1 || !o.modes || o.n_modes < 1 || o.vcycles_per_rhs < 1 || o.epochs < 1 ||
+        o.batch < 1 || !(o.lr > 0) || o.val_vcycles < 4 || !(o.solve_tol > 0))
+        throw Error(IGAMG_EINVAL, "bad training options");
+    const long long NL = lv[L].N;
+    // keep the user's right-hand side and settings
+    double* bsave = alloc<double>(NL);
+    copy(b, bsave, NL);
+    double bnorm_save = bnorm;
+    int tail_save = tail_top, prec_save = opt.precision;
+    bool learned_save = learned_on;
+    tail_top = 0;
+    learned_on = false;
+    opt.precision = IGAMG_FP64;
+
+    // ---- samples: per level lists of (z, t) FP32 full-level vectors
+    std::vector<std::vector<std::pair<float*, float*>>> samples(L + 1);
+    double* ustar = alloc<double>(NL);
+    double* xw = alloc<double>(NL);
+    double* tmp1 = alloc<double>(NL);
+    double* tmp2 = alloc<double>(NL);
+    double* tmp3 = alloc<double>(NL);
+    double* tmp4 = alloc<double>(NL);
+    for (int k = 0; k < o.n_rhs; ++k) {
+        set_rhs_field(o.modes + (size_t)k * o.n_modes * (dim + 2), o.n_modes);
+        fill(ustar, NL);
+        level_solve(L, b, ustar, o.solve_tol, 2000);
+        fill(xw, NL);
+        for (int v = 0; v < o.vcycles_per_rhs; ++v) {
+            // snapshot (b_l, x_l) at the entry of every level >= 1
+            std::vector<std::tuple<int, double*, double*>> snaps;
+            vcycle_from<double>(L, b, xw, [&](int l, const double* bl, double* xl) {
+                double* sb = alloc<double>(lv[l].N);
+                double* sx = alloc<double>(lv[l].N);
+                copy(bl, sb, lv[l].N);
+                copy((const double*)xl, sx, lv[l].N);
+                snaps.emplace_back(l, sb, sx);
+            });
+            for (auto& sn : snaps) {
+                int l = std::get<0>(sn);
+                double* sb = std::get<1>(sn);
+                double* sx = std::get<2>(sn);
+                Level& lvv = lv[l];
+                long long N = lvv.N;
+                // r = b_l - A_l x_l  (tmp1), u_l (tmp2), e = u_l - x_l (tmp3)
+                residual<double, double>(l, sb, sx, tmp1, 0, nullptr);
+                if (l == L) {
+                    copy(ustar, tmp2, N);
+                } else {
+                    fill(tmp2, N);
+                    level_solve(l, sb, tmp2, o.solve_tol, 2000);
+                }
+                hipLaunchKernelGGL(k_sub, dim3(grid_for(N)), dim3(kBlock), 0, stream, tmp2, sx, tmp3, N);
+                // e_c = A_{l-1}^{-1} R r, then t = e - P e_c
+                Level& cl = lv[l - 1];
+                double* rc = alloc<double>(cl.N);
+                double* ec = alloc<double>(cl.N);
+                restrict_<double>(l, tmp1, rc);
+                fill(ec, cl.N);
+                level_solve(l - 1, rc, ec, o.solve_tol, 2000);
+                fill(tmp4, N);
+                prolong_<double>(l, ec, tmp4);
+                hipLaunchKernelGGL(k_sub, dim3(grid_for(N)), dim3(kBlock), 0, stream, tmp3, tmp4, tmp2, N);
+                // sigma = RMS(D^{-1} r); pack
+                unsigned nb = grid_for(N);
+                hipLaunchKernelGGL(k_learned_sumsq_scaled, dim3(nb), dim3(kBlock), 0, stream, tmp1,
+                                   diag64[l], N, partial);
+                hipLaunchKernelGGL(k_learned_sigma, dim3(1), dim3(kBlock), 0, stream, partial, (int)nb, N,
+                                   scal + 3);
+                float* zz = alloc<float>(N);
+                float* tt = alloc<float>(N);
+                hipLaunchKernelGGL(k_learned_pack, dim3(nb), dim3(kBlock), 0, stream, tmp1, diag64[l],
+                                   tmp2, N, (const double*)(scal + 3), zz, tt);
+                check_launch();
+                samples[l].push_back({zz, tt});
+                release(rc);
+                release(ec);
+                release(sb);
+                release(sx);
+            }
+            sync();
+        }
+    }
+    for (double* a : {ustar, xw, tmp1, tmp2, tmp3, tmp4}) release(a);
+
+    // ---- patches and training per level
+    std::vector<double> lfirst(L + 1, 0.0), llast(L + 1, 0.0);
+    unsigned long long rng = o.seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    auto rnd = [&]() {
+        rng = rng * 6364136223846793005ULL + 1442695040888963407ULL;
+        return (uint32_t)(rng >> 33);
+    };
+    auto gauss = [&]() {
+        double u1 = (rnd() + 1.0) / 4294967297.0, u2 = (rnd() + 1.0) / 4294967297.0;
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    };
+    int total_patches = 0, trained = 0;
+    for (int l = 1; l <= L; ++l) {
+        if (samples[l].empty()) continue;
+        if (l <= tail_save) {  // run by the single-workgroup kernel: keeps Gauss-Seidel
+            for (auto& sm : samples[l]) {
+                release(sm.first);
+                release(sm.second);
+            }
+            continue;
+        }
+        Level& v = lv[l];
+        int n = v.n, ls = std::min(64, n), W = ls + 6;
+        int tpr = (n + ls - 1) / ls;
+        std::vector<float*> pz, pt;
+        for (auto& sm : samples[l]) {
+            for (int a = 0; a < tpr; ++a)
+                for (int c = 0; c < tpr; ++c) {
+                    float* z = alloc<float>((size_t)W * W);
+                    float* t = alloc<float>((size_t)ls * ls);
+                    hipLaunchKernelGGL(k_learned_cut, dim3((W * W + 255) / 256), dim3(256), 0, stream,
+                                       sm.first, sm.second, n, a * ls, c * ls, ls, z, t);
+                    pz.push_back(z);
+                    pt.push_back(t);
+                }
+            release(sm.first);
+            release(sm.second);
+        }
+        check_launch();
+        int np = (int)pz.size();
+        total_patches += np;
+        // initial weights: scaled normal (same scale rule as the oracle's init)
+        ensure_net(l);
+        Net& net = nets[l];
+        std::vector<float> w0(kLWeights);
+        for (int k = 0; k < kLW1; ++k) w0[k] = (float)(gauss() * std::sqrt(2.0 / 9.0));
+        for (int k = 0; k < kLW2; ++k) w0[kLW1 + k] = (float)(gauss() * std::sqrt(2.0 / 144.0));
+        for (int k = 0; k < kLW3; ++k) w0[kLW1 + kLW2 + k] = (float)(0.1 * gauss() * std::sqrt(2.0 / 144.0));
+        IGAMG_HIP(hipMemcpyAsync(net.master, w0.data(), kLWeights * 4, hipMemcpyHostToDevice, stream));
+        fill(net.m, kLWeights);
+        fill(net.v, kLWeights);
+        // BF16 copies through one zero-gradient Adam call with lr = 0
+        float* g = alloc<float>(kLWeights);
+        fill(g, kLWeights);
+        hipLaunchKernelGGL(k_learned_adam, dim3((kLWeights + 255) / 256), dim3(256), 0, stream, net.master,
+                           net.m, net.v, (const float*)g, 0.f, 0.9f, 0.999f, 1e-8f, 1.f, 1.f, net.wc, net.w2f,
+                           net.w2b);
+        net.have = true;
+        int tiles = ((ls + kLTile - 1) / kLTile) * ((ls + kLTile - 1) / kLTile);
+        int B = std::min(o.batch, np);
+        float* gpart = alloc<float>((size_t)B * tiles * kLWeights);
+        double* lpart = alloc<double>((size_t)B * tiles);
+        double* lsum = alloc<double>(1);
+        LItem* ditems = alloc<LItem>(B);
+        std::vector<LItem> hitems(B);
+        std::vector<int> order(np);
+        for (int k = 0; k < np; ++k) order[k] = k;
+        int step = 0;
+        for (int ep = 0; ep < o.epochs; ++ep) {
+            for (int k = np - 1; k > 0; --k) std::swap(order[k], order[rnd() % (k + 1)]);
+            double eloss = 0.0;
+            int ebatches = 0;
+            for (int s0 = 0; s0 + B <= np; s0 += B) {
+                for (int k = 0; k < B; ++k) {
+                    int pidx = order[s0 + k];
+                    int a = pidx % (tpr * tpr);
+                    int j0 = (a / tpr) * ls, i0 = (a % tpr) * ls;
+                    hitems[k].im = LImage{pz[pidx], W, W, n, i0 - 3, j0 - 3};
+                    hitems[k].t = pt[pidx];
+                    hitems[k].l0 = 3;
+                    hitems[k].lsize = ls;
+                }
+                IGAMG_HIP(hipMemcpyAsync(ditems, hitems.data(), B * sizeof(LItem), hipMemcpyHostToDevice,
+                                         stream));
+                // loss pixels of the batch (inside the domain)
+                long long cnt = 0;
+                for (int k = 0; k < B; ++k) {
+                    int j0 = hitems[k].im.off_j + 3, i0 = hitems[k].im.off_i + 3;
+                    cnt += (long long)std::min(ls, n - j0) * std::min(ls, n - i0);
+                }
+                LearnedW Wd{net.wc, net.w2f, net.w2b};
+                hipLaunchKernelGGL(k_learned_train, dim3(B * tiles), dim3(kLThreads), 0, stream,
+                                   (const LItem*)ditems, tiles, Wd, (float)(1.0 / cnt), gpart, lpart);
+                hipLaunchKernelGGL(k_learned_reduce, dim3((kLWeights + 255) / 256), dim3(256), 0, stream,
+                                   (const float*)gpart, B * tiles, (const double*)lpart, g, lsum);
+                ++step;
+                float bc1 = 1.f - std::pow(0.9f, (float)step), bc2 = 1.f - std::pow(0.999f, (float)step);
+                hipLaunchKernelGGL(k_learned_adam, dim3((kLWeights + 255) / 256), dim3(256), 0, stream,
+                                   net.master, net.m, net.v, (const float*)g, (float)o.lr, 0.9f, 0.999f,
+                                   1e-8f, bc1, bc2, net.wc, net.w2f, net.w2b);
+                check_launch();
+                if (ep == 0 || ep == o.epochs - 1) {
+                    IGAMG_HIP(hipMemcpyAsync(host_scal + 4, lsum, 8, hipMemcpyDeviceToHost, stream));
+                    sync();
+                    eloss += host_scal[4] / cnt;
+                    ++ebatches;
+                }
+            }
+            if (ep == 0) lfirst[l] = ebatches ? eloss / ebatches : 0.0;
+            if (ep == o.epochs - 1) llast[l] = ebatches ? eloss / ebatches : 0.0;
+        }
+        sync();
+        for (float* a : pz) release(a);
+        for (float* a : pt) release(a);
+        release(gpart);
+        release(lpart);
+        release(lsum);
+        release(ditems);
+        release(g);
+        ++trained;
+    }
+    // ---- validation: contraction with and without the networks
+    tail_top = tail_save;
+    if (o.val_modes)
+        set_rhs_field(o.val_modes, o.val_n_modes);
+    else
+        set_rhs_field(o.modes, o.n_modes);
+    double rp = measure_rho(o.val_vcycles, false);
+    double rl = measure_rho(o.val_vcycles, true);
+    rep.levels_trained = trained;
+    rep.patches = total_patches;
+    for (int l = 0; l < 16; ++l) {
+        rep.loss_first[l] = (l <= L) ? lfirst[l] : 0.0;
+        rep.loss_last[l] = (l <= L) ? llast[l] : 0.0;
+    }
+    rep.rho_plain = rp;
+    rep.rho_learned = rl;
+    rep.accepted = (rl > 0.0 && rl < rp) ? 1 : 0;
+    rho_plain_ref = rp;
+    // restore the user's state; enable the networks only if they contract better
+    copy(bsave, b, NL);
+    release(bsave);
+    set_bnorm(bnorm_save);
+    opt.precision = prec_save;
+    learned_on = rep.accepted ? true : learned_save;
+    graph_method = -1;
+    sync();
+    rep.train_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // ---------------------------------------------------------------------------
@@ -1066,10 +1464,21 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
             need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
             ctx->ensure_iterates(q);
             ctx->copy(x_dev, ctx->S[0], N);
+            double prev = 1.0;
+            bool learned_at_start = ctx->learned_on;
             for (int k = 0; k < max_restarts; ++k) {
                 ctx->run_restart_cycle(method, q);
                 ExtrapCoeffs c;
                 double rel = ctx->read_cycle(c);
+                // learned-smoother fallback: a cycle contracting worse than plain
+                // V-cycles would (measured at training) switches back to Gauss-Seidel
+                if (ctx->learned_on && ctx->rho_plain_ref > 0.0 && std::isfinite(rel) && k > 0 &&
+                    rel / prev > std::pow(ctx->rho_plain_ref, q + 1) && rel > tol) {
+                    ctx->learned_on = false;
+                    ctx->graph_method = -1;
+                    st.learned_fallbacks++;
+                }
+                prev = rel;
                 st.vcycles += q + 1;
                 st.restarts++;
                 if (c.info == -1) st.breakdowns++;
@@ -1084,6 +1493,10 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
             }
             ctx->copy(ctx->S[0], x_dev, N);
             ctx->sync();
+            if (learned_at_start && !ctx->learned_on) {
+                ctx->learned_on = true;  // the fallback lasts for this solve only
+                ctx->graph_method = -1;
+            }
         }
         if (!converged) throw Error(IGAMG_ENOCONV, "tolerance not reached within max_restarts");
     });
@@ -1209,6 +1622,119 @@ igamg_status igamg_profile_smoother(igamg_ctx* ctx, int level, int precision, in
         need(level >= 1 && level <= ctx->L, "level out of range");
         need(precision == IGAMG_FP64 || precision == IGAMG_FP32_IR, "bad precision");
         ctx->profile_smoother(level, precision, nsweeps, avg_ms, bytes, launches);
+    });
+}
+
+void igamg_train_options_default(igamg_train_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->vcycles_per_rhs = 3;
+    o->epochs = 10;
+    o->batch = 32;
+    o->lr = 1e-3;
+    o->seed = 5000;
+    o->val_vcycles = 12;
+    o->solve_tol = 1e-12;
+}
+
+igamg_status igamg_train_smoother(igamg_ctx* ctx, const igamg_train_options* o,
+                                  igamg_train_report* report) {
+    return guarded([&] {
+        need(ctx && o, "null argument");
+        igamg_train_report rep{};
+        ctx->train(*o, rep);
+        if (report) *report = rep;
+    });
+}
+
+igamg_status igamg_set_learned(igamg_ctx* ctx, int enabled) {
+    return guarded([&] {
+        need(ctx, "null argument");
+        bool any = false;
+        for (auto& n : ctx->nets) any = any || n.have;
+        need(!enabled || any, "no learned smoother weights loaded");
+        ctx->learned_on = enabled != 0;
+        ctx->graph_method = -1;
+    });
+}
+
+igamg_status igamg_get_smoother_weights(igamg_ctx* ctx, int level, uint16_t* w, size_t n) {
+    return guarded([&] {
+        need(ctx && w && n == (size_t)kLWeights, "need 2592 values");
+        need(level >= 1 && level <= ctx->L && level < (int)ctx->nets.size() && ctx->nets[level].have,
+             "no weights on this level");
+        IGAMG_HIP(hipMemcpyAsync(w, ctx->nets[level].wc, kLWeights * 2, hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_set_smoother_weights(igamg_ctx* ctx, int level, const uint16_t* w, size_t n) {
+    return guarded([&] {
+        need(ctx && w && n == (size_t)kLWeights, "need 2592 values");
+        need(ctx->dim == 2, "the learned smoother is 2D only");
+        need(level >= 1 && level <= ctx->L, "level out of range");
+        ctx->ensure_net(level);
+        auto& net = ctx->nets[level];
+        IGAMG_HIP(hipMemcpyAsync(net.wc, w, kLWeights * 2, hipMemcpyHostToDevice, ctx->stream));
+        std::vector<float> mw(kLWeights);
+        for (int k = 0; k < kLWeights; ++k) {
+            uint32_t u = ((uint32_t)w[k]) << 16;
+            std::memcpy(&mw[k], &u, 4);
+        }
+        IGAMG_HIP(hipMemcpyAsync(net.master, mw.data(), kLWeights * 4, hipMemcpyHostToDevice, ctx->stream));
+        hipLaunchKernelGGL(k_learned_layouts, dim3((kLW2 + 255) / 256), dim3(256), 0, ctx->stream,
+                           (const uint16_t*)net.wc, net.w2f, net.w2b);
+        ctx->check_launch();
+        ctx->sync();
+        net.have = true;
+        ctx->graph_method = -1;
+    });
+}
+
+igamg_status igamg_smoother_forward(igamg_ctx* ctx, int level, const float* z, float* y) {
+    return guarded([&] {
+        need(ctx && z && y, "null argument");
+        need(level >= 1 && level <= ctx->L && level < (int)ctx->nets.size() && ctx->nets[level].have,
+             "no weights on this level");
+        auto& v = ctx->lv[level];
+        auto& net = ctx->nets[level];
+        LImage im{z, v.n, v.n, v.n, 0, 0};
+        LearnedW W{net.wc, net.w2f, net.w2b};
+        int tiles = (v.n + kLTile - 1) / kLTile;
+        hipLaunchKernelGGL(k_learned_apply<float>, dim3(tiles * tiles), dim3(kLThreads), 0, ctx->stream, im,
+                           W, (const double*)nullptr, (float*)nullptr, y);
+        ctx->check_launch();
+        ctx->sync();
+    });
+}
+
+igamg_status igamg_smoother_loss_grad(igamg_ctx* ctx, int level, const float* z, const float* t,
+                                      double* loss, float* grad) {
+    return guarded([&] {
+        need(ctx && z && t && loss && grad, "null argument");
+        need(level >= 1 && level <= ctx->L && level < (int)ctx->nets.size() && ctx->nets[level].have,
+             "no weights on this level");
+        auto& v = ctx->lv[level];
+        auto& net = ctx->nets[level];
+        LItem it{LImage{z, v.n, v.n, v.n, 0, 0}, t, 0, v.n};
+        LItem* dit = ctx->alloc<LItem>(1);
+        IGAMG_HIP(hipMemcpyAsync(dit, &it, sizeof(LItem), hipMemcpyHostToDevice, ctx->stream));
+        int tpr = (v.n + kLTile - 1) / kLTile, tiles = tpr * tpr;
+        float* gpart = ctx->alloc<float>((size_t)tiles * kLWeights);
+        double* lpart = ctx->alloc<double>(tiles);
+        float* g = ctx->alloc<float>(kLWeights);
+        double* ls = ctx->alloc<double>(1);
+        LearnedW W{net.wc, net.w2f, net.w2b};
+        hipLaunchKernelGGL(k_learned_train, dim3(tiles), dim3(kLThreads), 0, ctx->stream, (const LItem*)dit,
+                           tiles, W, (float)(1.0 / ((double)v.N)), gpart, lpart);
+        hipLaunchKernelGGL(k_learned_reduce, dim3((kLWeights + 255) / 256), dim3(256), 0, ctx->stream,
+                           (const float*)gpart, tiles, (const double*)lpart, g, ls);
+        ctx->check_launch();
+        IGAMG_HIP(hipMemcpyAsync(grad, g, kLWeights * 4, hipMemcpyDeviceToHost, ctx->stream));
+        IGAMG_HIP(hipMemcpyAsync(ctx->host_scal + 5, ls, 8, hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+        *loss = ctx->host_scal[5] / (double)v.N;
+        for (void* a : {(void*)dit, (void*)gpart, (void*)lpart, (void*)g, (void*)ls}) ctx->release(a);
     });
 }
 

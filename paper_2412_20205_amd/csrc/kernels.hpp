@@ -1136,6 +1136,31 @@ __global__ void k_to_colour_blocked(const double* __restrict__ st, int n, int nc
     if (c32) c32[dst] = (float)v;
 }
 
+// Diagonal of a colour-blocked stencil in natural order (FP64 and FP32).
+template <int P>
+__global__ void k_diag_stencil(const double* __restrict__ c64, int n, int ncp,
+                               double* __restrict__ d64, float* __restrict__ d32) {
+    constexpr int W = 2 * P + 1, S = W * W;
+    long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (I >= (long long)n * n) return;
+    int j = (int)(I / n), i = (int)(I - (long long)j * n);
+    int ci = i % (P + 1), cj = j % (P + 1);
+    int c = ci + (P + 1) * cj;
+    int ni = (n - ci + P) / (P + 1);
+    int k = i / (P + 1) + ni * (j / (P + 1));
+    double v = c64[((size_t)c * S + (P + W * P)) * ncp + k];
+    d64[I] = v;
+    d32[I] = (float)v;
+}
+
+// out = a - b (elementwise)
+__global__ void __launch_bounds__(kBlock) k_sub(const double* __restrict__ a,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ out, long long N) {
+    long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (I < N) out[I] = a[I] - b[I];
+}
+
 // Gather selected FP64 rows of a colour-blocked stencil into natural form.
 template <int P>
 __global__ void k_gather_rows(const double* __restrict__ c64, int n, int ncp,

@@ -1,0 +1,441 @@
+// Learned smoother: a 3-layer 3x3 convolutional network (1 -> 16 -> 16 -> 1
+// channels, ReLU, zero "same" padding, no biases) applied on a level's index
+// grid, y = N(D^{-1} r / sigma), x += sigma * y, replacing the first
+// pre-smoothing sweep of Algorithm 2's cycle on that level.
+//
+// Precision: BF16 weights; layer 1 and 3 on VALU in FP32; layer 2 as a GEMM on
+// v_mfma_f32_16x16x16_bf16 (BF16 operands: layer-1 activations rounded to
+// BF16, FP32 accumulation).  Training kernels use the same MFMA shape for the
+// weight gradient of layer 2 (reduction over pixels) and for the input
+// gradient of layer 2; the layer-2 output gradient is rounded to BF16 for them.
+//
+// Tiles: a workgroup of 256 threads produces a 16 x 16 output tile; it holds
+// the input on 22 x 22 pixels, layer-1 activations on 20 x 20 (BF16) and
+// layer-2 activations on 18 x 18 (FP32) in LDS.
+//
+// Canonical weight layout (also the ABI layout): W1[c][tap] (16 x 9),
+// W2[co][ci][tap] (16 x 16 x 9), W3[ci][tap] (16 x 9), tap = 3 dy + dx,
+// concatenated (2592 values).
+#pragma once
+
+#include "common.hpp"
+
+namespace igamg {
+
+constexpr int kLC = 16;
+constexpr int kLW1 = 144, kLW2 = 2304, kLW3 = 144;
+constexpr int kLWeights = kLW1 + kLW2 + kLW3;
+constexpr int kLTile = 16;
+constexpr int kLThreads = 256;
+
+typedef short __attribute__((ext_vector_type(4))) bf16x4;
+typedef float __attribute__((ext_vector_type(4))) floatx4;
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Device weight set of one level: canonical BF16 plus the two MFMA B-operand
+// layouts of W2 ([tap][co][ci] for the forward product, [tap][ci][co] for the
+// input gradient).
+struct LearnedW {
+    const uint16_t* w;     // canonical, kLWeights
+    const uint16_t* w2f;   // [tap][co][ci]
+    const uint16_t* w2b;   // [tap][ci][co]
+};
+
+// One image seen by the network: z (height x width, row-major), the level it
+// belongs to (n) and the level coordinates of its pixel (0, 0).
+struct LImage {
+    const float* z;
+    int width, height;
+    int n;
+    int off_i, off_j;
+};
+
+__device__ __forceinline__ bool l_inside(const LImage& im, int pj, int pi) {
+    int gj = pj + im.off_j, gi = pi + im.off_i;
+    return pj >= 0 && pj < im.height && pi >= 0 && pi < im.width && gj >= 0 && gj < im.n &&
+           gi >= 0 && gi < im.n;
+}
+
+struct LShared {
+    float z[22 * 22];
+    uint16_t h1[20 * 20 * kLC];
+    float h2[18 * 18 * kLC];
+    float w1[kLW1];
+    float w3[kLW3];
+};
+
+// Forward pass of one 16x16 output tile with origin (tj0, ti0); zscale
+// multiplies the input.  Leaves z, h1, h2 in LDS and returns y of this
+// thread's output pixel (threadIdx.x = 16 oy + ox).
+__device__ inline float l_forward_tile(const LImage& im, const LearnedW& W, int tj0, int ti0,
+                                       float zscale, LShared& S) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int t = tid; t < kLW1; t += kLThreads) S.w1[t] = bf16_to_f32(W.w[t]);
+    for (int t = tid; t < kLW3; t += kLThreads) S.w3[t] = bf16_to_f32(W.w[kLW1 + kLW2 + t]);
+    for (int t = tid; t < 22 * 22; t += kLThreads) {
+        int pj = tj0 - 3 + t / 22, pi = ti0 - 3 + t % 22;
+        S.z[t] = l_inside(im, pj, pi) ? im.z[(size_t)pj * im.width + pi] * zscale : 0.f;
+    }
+    __syncthreads();
+    // layer 1 (VALU): h1 on 20 x 20, 16 channels, ReLU, zero outside the domain
+    for (int p = tid; p < 400; p += kLThreads) {
+        int py = p / 20, px = p % 20;
+        bool in = l_inside(im, tj0 - 2 + py, ti0 - 2 + px);
+        float zz[9];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) zz[tap] = S.z[(py + tap / 3) * 22 + px + tap % 3];
+#pragma unroll
+        for (int c = 0; c < kLC; ++c) {
+            float a = 0.f;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) a = fmaf(S.w1[c * 9 + tap], zz[tap], a);
+            S.h1[p * kLC + c] = f32_to_bf16(in ? fmaxf(a, 0.f) : 0.f);
+        }
+    }
+    __syncthreads();
+    // layer 2 (MFMA 16x16x16 BF16): rows = 16 pixels of the 18 x 18 region,
+    // K = (tap, ci), N = co
+    bf16x4 bw[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const uint16_t* src = W.w2f + ((size_t)tap * kLC + (lane & 15)) * kLC + 4 * (lane >> 4);
+        bw[tap] = bf16x4{(short)src[0], (short)src[1], (short)src[2], (short)src[3]};
+    }
+    for (int g = wave; g < 21; g += kLThreads / 64) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        int pa = g * 16 + (lane & 15);  // A row: pixel of the 18x18 grid
+        bool va = pa < 324;
+        int qy = va ? pa / 18 : 0, qx = va ? pa % 18 : 0;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            bf16x4 a = {0, 0, 0, 0};
+            if (va) {
+                const uint16_t* src = &S.h1[((qy + tap / 3) * 20 + qx + tap % 3) * kLC + 4 * (lane >> 4)];
+                a = bf16x4{(short)src[0], (short)src[1], (short)src[2], (short)src[3]};
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[tap], acc, 0, 0, 0);
+        }
+        int co = lane & 15;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int p = g * 16 + 4 * (lane >> 4) + j;
+            if (p < 324) {
+                bool in = l_inside(im, tj0 - 1 + p / 18, ti0 - 1 + p % 18);
+                S.h2[p * kLC + co] = in ? fmaxf(acc[j], 0.f) : 0.f;
+            }
+        }
+    }
+    __syncthreads();
+    // layer 3 (VALU)
+    int oy = tid >> 4, ox = tid & 15;
+    float y = 0.f;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const float* h = &S.h2[((oy + tap / 3) * 18 + ox + tap % 3) * kLC];
+#pragma unroll
+        for (int c = 0; c < kLC; ++c) y = fmaf(S.w3[c * 9 + tap], h[c], y);
+    }
+    return y;
+}
+
+// Inference on a whole level: x_I += sigma * N(z / sigma)_I, with
+// sigma = scal[0] (skipped when sigma <= 0), or y written to yout.
+template <typename T>
+__global__ void __launch_bounds__(kLThreads) k_learned_apply(LImage im, LearnedW W,
+                                                             const double* __restrict__ sigma_dev,
+                                                             T* __restrict__ x,
+                                                             float* __restrict__ yout) {
+    __shared__ LShared S;
+    double sg = sigma_dev ? *sigma_dev : 1.0;
+    if (!(sg > 0.0)) return;
+    int tiles = (im.width + kLTile - 1) / kLTile;
+    int tj0 = (blockIdx.x / tiles) * kLTile, ti0 = (blockIdx.x % tiles) * kLTile;
+    float y = l_forward_tile(im, W, tj0, ti0, (float)(1.0 / sg), S);
+    int pj = tj0 + (threadIdx.x >> 4), pi = ti0 + (threadIdx.x & 15);
+    if (pj < im.height && pi < im.width && l_inside(im, pj, pi)) {
+        size_t I = (size_t)pj * im.width + pi;
+        if (yout)
+            yout[I] = y;
+        else
+            x[I] = x[I] + (T)(sg * (double)y);
+    }
+}
+
+// z = r / diag (FP32) and per-block sums of z^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_learned_prep(const T* __restrict__ r,
+                                                         const T* __restrict__ diag, long long N,
+                                                         float* __restrict__ z,
+                                                         double* __restrict__ partial) {
+    __shared__ double red[kBlock / 64];
+    long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double s = 0.0;
+    if (I < N) {
+        float v = (float)((double)r[I] / (double)diag[I]);
+        z[I] = v;
+        s = (double)v * v;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// sigma = sqrt(sum partial / N)
+__global__ void k_learned_sigma(const double* __restrict__ partial, int np, long long N,
+                                double* __restrict__ sigma) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) sigma[0] = sqrt(s / (double)N);
+}
+
+// One training item: an image with a loss region [l0, l0 + lsize)^2 (image
+// coordinates) and its target t (lsize x lsize, row-major).
+struct LItem {
+    LImage im;
+    const float* t;
+    int l0, lsize;
+};
+
+// Forward + backward of one 16x16 tile of one item; writes this block's
+// partial gradient (canonical layout, FP32) and partial squared error.
+// Loss = mean over loss pixels of (y - t)^2; inv_count = 1 / (number of loss
+// pixels in the batch).
+__global__ void __launch_bounds__(kLThreads) k_learned_train(const LItem* __restrict__ items,
+                                                             int tiles_per_item, LearnedW W,
+                                                             float inv_count,
+                                                             float* __restrict__ gpart,
+                                                             double* __restrict__ lpart) {
+    __shared__ LShared S;
+    __shared__ float gy[16 * 16];
+    __shared__ uint16_t gh2[324 * kLC];
+    __shared__ float red[kLW1 + kLW3];
+    __shared__ float dw1w[4][kLW1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const LItem it = items[blockIdx.x / tiles_per_item];
+    const int tile = blockIdx.x % tiles_per_item;
+    const int tpr = (it.lsize + kLTile - 1) / kLTile;
+    const int tj0 = it.l0 + (tile / tpr) * kLTile, ti0 = it.l0 + (tile % tpr) * kLTile;
+    float y = l_forward_tile(it.im, W, tj0, ti0, 1.f, S);
+    // output gradient
+    int oy = tid >> 4, ox = tid & 15;
+    int lj = tj0 + oy - it.l0, li = ti0 + ox - it.l0;
+    bool inl = lj < it.lsize && li < it.lsize && l_inside(it.im, tj0 + oy, ti0 + ox);
+    float d = inl ? y - it.t[(size_t)lj * it.lsize + li] : 0.f;
+    gy[tid] = 2.f * d * inv_count;
+    {
+        double sq = (double)d * d;
+        for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
+        __shared__ double lw[4];
+        if (lane == 0) lw[wave] = sq;
+        __syncthreads();
+        if (tid == 0) lpart[blockIdx.x] = lw[0] + lw[1] + lw[2] + lw[3];
+    }
+    __syncthreads();
+    float* gp = gpart + (size_t)blockIdx.x * kLWeights;
+    // dW3[ci][tap] = sum_pix gy * h2[pix + tap][ci]
+    for (int k = tid; k < kLW3; k += kLThreads) {
+        int ci = k / 9, tap = k % 9;
+        float s = 0.f;
+        for (int p = 0; p < 256; ++p)
+            s = fmaf(gy[p], S.h2[(((p >> 4) + tap / 3) * 18 + (p & 15) + tap % 3) * kLC + ci], s);
+        gp[kLW1 + kLW2 + k] = s;
+    }
+    // gh2[q][ci] = (h2 > 0) * sum_tap W3[ci][tap] gy[q - tap], rounded to BF16
+    for (int e = tid; e < 324 * kLC; e += kLThreads) {
+        int q = e / kLC, ci = e % kLC;
+        int qy = q / 18, qx = q % 18;
+        float s = 0.f;
+        if (S.h2[e] > 0.f) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                int gyy = qy - tap / 3, gxx = qx - tap % 3;
+                if (gyy >= 0 && gyy < 16 && gxx >= 0 && gxx < 16) s = fmaf(S.w3[ci * 9 + tap], gy[gyy * 16 + gxx], s);
+            }
+        }
+        gh2[e] = f32_to_bf16(s);
+    }
+    __syncthreads();
+    // dW2 (MFMA): for each tap, D[co][ci] = sum_q gh2[q][co] h1[q + tap][ci],
+    // K = pixels in chunks of 16; wave w takes taps w, w+4, w+8
+    for (int tap = wave; tap < 9; tap += 4) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int ch = 0; ch < 21; ++ch) {
+            short av[4], bv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int q = ch * 16 + 4 * (lane >> 4) + r;
+                if (q < 324) {
+                    av[r] = (short)gh2[q * kLC + (lane & 15)];
+                    int qy = q / 18, qx = q % 18;
+                    bv[r] = (short)S.h1[((qy + tap / 3) * 20 + qx + tap % 3) * kLC + (lane & 15)];
+                } else {
+                    av[r] = 0;
+                    bv[r] = 0;
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bf16x4{av[0], av[1], av[2], av[3]},
+                                                           bf16x4{bv[0], bv[1], bv[2], bv[3]}, acc,
+                                                           0, 0, 0);
+        }
+        int ci = lane & 15;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int co = 4 * (lane >> 4) + j;
+            gp[kLW1 + (co * kLC + ci) * 9 + tap] = acc[j];
+        }
+    }
+    // gh1 (MFMA) on the 20 x 20 grid: D[p][ci] = sum_{tap,co} gh2[p - tap][co] W2[co][ci][tap],
+    // masked by h1 > 0; accumulated straight into dW1[ci][tap'] += gh1 * z[p + tap']
+    bf16x4 bw[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const uint16_t* src = W.w2b + ((size_t)tap * kLC + (lane & 15)) * kLC + 4 * (lane >> 4);
+        bw[tap] = bf16x4{(short)src[0], (short)src[1], (short)src[2], (short)src[3]};
+    }
+    float dw1[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) dw1[t] = 0.f;
+    for (int g = wave; g < 25; g += 4) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        int pa = g * 16 + (lane & 15);
+        int py = pa / 20, px = pa % 20;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            int qy = py - tap / 3, qx = px - tap % 3;
+            bf16x4 a = {0, 0, 0, 0};
+            if (qy >= 0 && qy < 18 && qx >= 0 && qx < 18) {
+                const uint16_t* src = &gh2[(qy * 18 + qx) * kLC + 4 * (lane >> 4)];
+                a = bf16x4{(short)src[0], (short)src[1], (short)src[2], (short)src[3]};
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[tap], acc, 0, 0, 0);
+        }
+        int ci = lane & 15;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int p = g * 16 + 4 * (lane >> 4) + j;
+            int ry = p / 20, rx = p % 20;
+            float gv = (bf16_to_f32(S.h1[p * kLC + ci]) > 0.f) ? acc[j] : 0.f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) dw1[t] = fmaf(gv, S.z[(ry + t / 3) * 22 + rx + t % 3], dw1[t]);
+        }
+    }
+    // reduce dW1 partials: lanes with equal ci (l, l+16, l+32, l+48), then waves
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        float v = dw1[t];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (lane < 16) dw1w[wave][lane * 9 + t] = v;
+    }
+    __syncthreads();
+    for (int k = tid; k < kLW1; k += kLThreads) gp[k] = dw1w[0][k] + dw1w[1][k] + dw1w[2][k] + dw1w[3][k];
+    (void)red;
+}
+
+// Deterministic sum of the per-block partials: g[k] = sum_b gpart[b][k].
+__global__ void k_learned_reduce(const float* __restrict__ gpart, int nblocks,
+                                 const double* __restrict__ lpart, float* __restrict__ grad,
+                                 double* __restrict__ loss) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < kLWeights) {
+        float s = 0.f;
+        for (int b = 0; b < nblocks; ++b) s += gpart[(size_t)b * kLWeights + k];
+        grad[k] = s;
+    }
+    if (k == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += lpart[b];
+        loss[0] = s;
+    }
+}
+
+// Adam on FP32 master weights, then the BF16 copies in the three layouts.
+__global__ void k_learned_adam(float* __restrict__ master, float* __restrict__ m, float* __restrict__ v,
+                               const float* __restrict__ grad, float lr, float b1, float b2, float eps,
+                               float bc1, float bc2, uint16_t* __restrict__ wc, uint16_t* __restrict__ w2f,
+                               uint16_t* __restrict__ w2b) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kLWeights) return;
+    float g = grad[k];
+    float mk = b1 * m[k] + (1.f - b1) * g;
+    float vk = b2 * v[k] + (1.f - b2) * g * g;
+    m[k] = mk;
+    v[k] = vk;
+    float w = master[k] - lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+    master[k] = w;
+    uint16_t h = f32_to_bf16(w);
+    wc[k] = h;
+    if (k >= kLW1 && k < kLW1 + kLW2) {
+        int e = k - kLW1, co = e / (kLC * 9), ci = (e / 9) % kLC, tap = e % 9;
+        w2f[((size_t)tap * kLC + co) * kLC + ci] = h;
+        w2b[((size_t)tap * kLC + ci) * kLC + co] = h;
+    }
+}
+
+// Canonical BF16 weights -> the two W2 layouts (after an external load).
+__global__ void k_learned_layouts(const uint16_t* __restrict__ wc, uint16_t* __restrict__ w2f,
+                                  uint16_t* __restrict__ w2b) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kLW2) return;
+    int co = e / (kLC * 9), ci = (e / 9) % kLC, tap = e % 9;
+    uint16_t h = wc[kLW1 + e];
+    w2f[((size_t)tap * kLC + co) * kLC + ci] = h;
+    w2b[((size_t)tap * kLC + ci) * kLC + co] = h;
+}
+
+// e_hf = u - x - P e_c target pieces are formed with the ordinary kernels;
+// this packs one level sample: out_z = z / sigma, out_t = t / sigma (FP32).
+__global__ void k_learned_pack(const double* __restrict__ r, const double* __restrict__ diag,
+                               const double* __restrict__ t, long long N,
+                               const double* __restrict__ sigma, float* __restrict__ oz,
+                               float* __restrict__ ot) {
+    long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (I >= N) return;
+    double s = sigma[0] > 0.0 ? sigma[0] : 1.0;
+    oz[I] = (float)(r[I] / diag[I] / s);
+    ot[I] = (float)(t[I] / s);
+}
+
+// sum of (r / diag)^2 per block (FP64), for sigma of a training sample.
+__global__ void __launch_bounds__(kBlock) k_learned_sumsq_scaled(const double* __restrict__ r,
+                                                                 const double* __restrict__ diag,
+                                                                 long long N,
+                                                                 double* __restrict__ partial) {
+    __shared__ double red[kBlock / 64];
+    long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double s = 0.0;
+    if (I < N) {
+        double v = r[I] / diag[I];
+        s = v * v;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Cut one training patch: image (lsize + 6)^2 around the loss region whose
+// level-grid origin is (j0, i0); zero outside the domain.
+__global__ void k_learned_cut(const float* __restrict__ zl, const float* __restrict__ tl, int n,
+                              int j0, int i0, int lsize, float* __restrict__ pz,
+                              float* __restrict__ pt) {
+    int w = lsize + 6;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < w * w) {
+        int gj = j0 - 3 + t / w, gi = i0 - 3 + t % w;
+        pz[t] = (gj >= 0 && gj < n && gi >= 0 && gi < n) ? zl[(size_t)gj * n + gi] : 0.f;
+    }
+    if (t < lsize * lsize) {
+        int gj = j0 + t / lsize, gi = i0 + t % lsize;
+        pt[t] = (gj < n && gi < n) ? tl[(size_t)gj * n + gi] : 0.f;
+    }
+}
+
+}  // namespace igamg

@@ -46,6 +46,27 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrainOptions(ctypes.Structure):
+    _fields_ = [("n_rhs", ctypes.c_int), ("modes", ctypes.c_void_p), ("n_modes", ctypes.c_int),
+                ("vcycles_per_rhs", ctypes.c_int), ("epochs", ctypes.c_int), ("batch", ctypes.c_int),
+                ("lr", ctypes.c_double), ("seed", ctypes.c_ulonglong), ("val_modes", ctypes.c_void_p),
+                ("val_n_modes", ctypes.c_int), ("val_vcycles", ctypes.c_int),
+                ("solve_tol", ctypes.c_double)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("levels_trained", ctypes.c_int), ("patches", ctypes.c_int),
+                ("loss_first", ctypes.c_double * 16), ("loss_last", ctypes.c_double * 16),
+                ("rho_plain", ctypes.c_double), ("rho_learned", ctypes.c_double),
+                ("accepted", ctypes.c_int), ("train_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"levels_trained": self.levels_trained, "patches": self.patches,
+                "loss_first": list(self.loss_first), "loss_last": list(self.loss_last),
+                "rho_plain": self.rho_plain, "rho_learned": self.rho_learned,
+                "accepted": self.accepted, "train_ms": self.train_ms}
+
+
 class IgamgError(RuntimeError):
     def __init__(self, status, func, msg):
         super().__init__("%s failed: %s (%s)" % (func, STATUS_NAMES.get(status, status), msg))
@@ -83,6 +104,13 @@ _SIGNATURES = {
     "igamg_extrap_coeffs": (_i, [_P, _i, _i, _P, _P, ctypes.POINTER(_i)]),
     "igamg_profile_smoother": (_i, [_P, _i, _i, _i, ctypes.POINTER(_d), ctypes.POINTER(_d),
                                     ctypes.POINTER(_i)]),
+    "igamg_train_options_default": (None, [ctypes.POINTER(TrainOptions)]),
+    "igamg_train_smoother": (_i, [_P, ctypes.POINTER(TrainOptions), ctypes.POINTER(TrainReport)]),
+    "igamg_set_learned": (_i, [_P, _i]),
+    "igamg_get_smoother_weights": (_i, [_P, _i, _P, ctypes.c_size_t]),
+    "igamg_set_smoother_weights": (_i, [_P, _i, _P, ctypes.c_size_t]),
+    "igamg_smoother_forward": (_i, [_P, _i, _P, _P]),
+    "igamg_smoother_loss_grad": (_i, [_P, _i, _P, _P, ctypes.POINTER(_d), _P]),
     "igamg_last_error": (ctypes.c_char_p, []),
     "igamg_host_gauss_legendre": (_i, [_i, _P, _P]),
     "igamg_host_basis": (_i, [_i, _i, _d, _P, _P, ctypes.POINTER(_i)]),
@@ -123,6 +151,15 @@ def _ptr(t):
     torch.cuda.current_stream().synchronize()
     if not t.is_cuda or t.dtype.__repr__() != "torch.float64" or not t.is_contiguous():
         raise ValueError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr32(t):
+    """Device pointer of a contiguous float32 CUDA tensor."""
+    import torch
+    torch.cuda.current_stream().synchronize()
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 device tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -276,6 +313,54 @@ class Solver:
                                             ctypes.byref(by), ctypes.byref(n)),
                "igamg_profile_smoother")
         return ms.value, by.value, n.value
+
+    # ---- learned smoother
+    def train_smoother(self, modes_list, val_modes=None, **kw):
+        o = TrainOptions()
+        lib().igamg_train_options_default(ctypes.byref(o))
+        tab = np.ascontiguousarray(np.concatenate([np.asarray(m, dtype=np.float64) for m in modes_list]))
+        o.n_rhs = len(modes_list)
+        o.n_modes = int(np.asarray(modes_list[0]).shape[0])
+        o.modes = _np_ptr(tab)
+        vm = None
+        if val_modes is not None:
+            vm = np.ascontiguousarray(val_modes, dtype=np.float64)
+            o.val_modes = _np_ptr(vm)
+            o.val_n_modes = vm.shape[0]
+        for k, v in kw.items():
+            setattr(o, k, v)
+        rep = TrainReport()
+        _check(lib().igamg_train_smoother(self._h, ctypes.byref(o), ctypes.byref(rep)),
+               "igamg_train_smoother")
+        del tab, vm
+        return rep.as_dict()
+
+    def set_learned(self, enabled):
+        _check(lib().igamg_set_learned(self._h, int(enabled)), "igamg_set_learned")
+
+    def get_smoother_weights(self, level):
+        w = np.zeros(2592, dtype=np.uint16)
+        _check(lib().igamg_get_smoother_weights(self._h, level, _np_ptr(w), w.size),
+               "igamg_get_smoother_weights")
+        return w
+
+    def set_smoother_weights(self, level, w):
+        w = np.ascontiguousarray(w, dtype=np.uint16)
+        _check(lib().igamg_set_smoother_weights(self._h, level, _np_ptr(w), w.size),
+               "igamg_set_smoother_weights")
+
+    def smoother_forward(self, level, z, y):
+        _check(lib().igamg_smoother_forward(self._h, level, _ptr32(z), _ptr32(y)),
+               "igamg_smoother_forward")
+        return y
+
+    def smoother_loss_grad(self, level, z, t):
+        g = np.zeros(2592, dtype=np.float32)
+        loss = _d()
+        _check(lib().igamg_smoother_loss_grad(self._h, level, _ptr32(z), _ptr32(t),
+                                              ctypes.byref(loss), _np_ptr(g)),
+               "igamg_smoother_loss_grad")
+        return loss.value, g
 
     def extrap_coeffs(self, method, q, iterates):
         gamma = np.zeros(q + 1)

@@ -1,0 +1,112 @@
+"""Learned smoother on the GPU: forward and gradient parity with the FP64
+oracle evaluated on the same BF16-rounded weights and rounding points, training
+gain measured by the true residual, and the Gauss-Seidel fallback."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import learned as ln
+from paper_2412_20205_amd import igamg
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def to_bf16_bits(a):
+    f = np.asarray(ln.bf16_round(a), dtype=np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def canonical(Ws):
+    W1, W2, W3 = Ws
+    return np.concatenate([W1[:, 0].reshape(16, 9).ravel(), W2.reshape(16, 16, 9).ravel(),
+                           W3[0].reshape(16, 9).ravel()])
+
+
+def from_canonical(v):
+    return [v[:144].reshape(16, 1, 3, 3), v[144:2448].reshape(16, 16, 3, 3),
+            v[2448:].reshape(1, 16, 3, 3)]
+
+
+@pytest.fixture(scope="module")
+def solver():
+    print("[case] annulus 128 p=3 learned", flush=True)
+    return igamg.Solver(igamg.QUARTER_ANNULUS, 128, 3)
+
+
+@pytest.mark.parametrize("level,seed", [(5, 1), (4, 2), (2, 3)])
+def test_forward_matches_oracle(solver, level, seed):
+    rng = np.random.default_rng(seed)
+    Ws = ln.init_weights(rng)
+    bits = to_bf16_bits(canonical(Ws))
+    Wq = from_canonical(ln.bf16_round(canonical(Ws)))
+    solver.set_smoother_weights(level, bits)
+    assert np.array_equal(solver.get_smoother_weights(level), bits)
+    n = int(round(solver.level_ndof(level) ** 0.5))
+    z = rng.standard_normal((n, n)).astype(np.float32)
+    y = torch.zeros(n * n, dtype=torch.float32, device=DEV)
+    solver.smoother_forward(level, torch.tensor(z.ravel(), device=DEV), y)
+    yg = y.cpu().numpy().reshape(n, n)
+    yr, _ = ln.forward(z.astype(np.float64), Wq, bf16_points=True)
+    err = np.linalg.norm(yg - yr) / np.linalg.norm(yr)
+    print("[learned fwd] level %d n=%d rel err %.2e" % (level, n, err))
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("level,seed", [(5, 4), (3, 5)])
+def test_gradients_match_oracle(solver, level, seed):
+    rng = np.random.default_rng(seed)
+    Ws = ln.init_weights(rng)
+    bits = to_bf16_bits(canonical(Ws))
+    Wq = from_canonical(ln.bf16_round(canonical(Ws)))
+    solver.set_smoother_weights(level, bits)
+    n = int(round(solver.level_ndof(level) ** 0.5))
+    z = rng.standard_normal((n, n)).astype(np.float32)
+    t = rng.standard_normal((n, n)).astype(np.float32)
+    loss, g = solver.smoother_loss_grad(level, torch.tensor(z.ravel(), device=DEV),
+                                        torch.tensor(t.ravel(), device=DEV))
+    lr, gr = ln.loss_and_grads(z.astype(np.float64), t.astype(np.float64), Wq, bf16_points=True)
+    assert abs(loss - lr) / lr < 1e-5
+    gc = canonical(gr)
+    for sl, name in ((slice(0, 144), "W1"), (slice(144, 2448), "W2"), (slice(2448, 2592), "W3")):
+        err = np.linalg.norm(g[sl] - gc[sl]) / np.linalg.norm(gc[sl])
+        print("[learned grad] level %d %s rel err %.2e" % (level, name, err))
+        assert err < 2e-3, name
+
+
+def test_training_gain_and_fallback():
+    """Train on a 256^2 annulus (p = 3); the trained networks must contract
+    better than the Gauss-Seidel sweep they replace and the RRE(5) solve must
+    reach 1e-10 by the true residual with no more V-cycles than without them."""
+    print("[case] annulus 256 p=3 training", flush=True)
+    s = igamg.Solver(igamg.QUARTER_ANNULUS, 256, 3)
+    modes = [synth.random_field_modes(5000 + k) for k in range(8)]
+    rep = s.train_smoother(modes, val_modes=synth.random_field_modes(5900), epochs=8)
+    print("[learned train]", {k: v for k, v in rep.items() if k not in ("loss_first", "loss_last")})
+    print("[learned train] loss first", np.round(rep["loss_first"][:9], 4))
+    print("[learned train] loss last ", np.round(rep["loss_last"][:9], 4))
+    assert rep["levels_trained"] >= 2
+    assert rep["accepted"] == 1 and rep["rho_learned"] < rep["rho_plain"]
+    s.set_rhs_field(synth.random_field_modes(5901))
+    x = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+    st_l, _ = s.solve(x, tol=1e-10, max_restarts=100, method=igamg.RRE, q=5)
+    assert s.residual(x) <= 1.0000001e-10
+    s.set_learned(False)
+    x0 = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+    st_p, _ = s.solve(x0, tol=1e-10, max_restarts=100, method=igamg.RRE, q=5)
+    print("[learned gain] vcycles learned %d plain %d; solve ms learned %.1f plain %.1f"
+          % (st_l.vcycles, st_p.vcycles, st_l.solve_ms, st_p.solve_ms))
+    assert st_l.vcycles <= st_p.vcycles
+    assert st_l.learned_fallbacks == 0
+    # fallback: spoil the finest network (negated output layer) -> Gauss-Seidel takes over
+    L = s.num_levels - 1
+    w = s.get_smoother_weights(L).copy()
+    w[2448:] ^= np.uint16(0x8000)
+    s.set_smoother_weights(L, w)
+    s.set_learned(True)
+    x1 = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+    st_f, _ = s.solve(x1, tol=1e-10, max_restarts=200, method=igamg.RRE, q=5)
+    print("[learned fallback] fallbacks %d vcycles %d" % (st_f.learned_fallbacks, st_f.vcycles))
+    assert s.residual(x1) <= 1.0000001e-10
+    assert st_f.learned_fallbacks >= 1
