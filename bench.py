@@ -7,10 +7,14 @@ Cholesky), V(2,2) multicolour Gauss-Seidel, seeded random-field right-hand
 side (64 sine modes, seed 2000 + p), x_0 = 0.
 
 A step is one complete solve to ||b - A x||_2 / ||b||_2 <= 1e-10 with the
-right-hand side already on the device.  Three forms are timed per degree:
+right-hand side already on the device.  Forms timed per degree:
   plain_fp64  -- plain FP64 V-cycles, residual tested after each one;
   rre_fp64    -- restarted RRE(5) around FP64 V-cycles;
-  chosen      -- restarted RRE(5) around FP32 V-cycles inside FP64 refinement.
+  ir_rre      -- restarted RRE(5) around FP32 V-cycles inside FP64 refinement;
+  chosen      -- ir_rre with the learned smoother (headline degree p = 3: per-level
+                 networks trained on the device before timing, on residual/target
+                 pairs from plain V-cycles with RHS seeds 5000..5015, accepted by the
+                 measured contraction on seed 5900; other degrees: ir_rre).
 `value` is the chosen form's ms per solve at the headline degree.
 
 The roofline entry is the dominant kernel of the chosen form: one colour pass
@@ -52,8 +56,10 @@ def dof_updates(s, vcycles, nu):
     return tot * nu * vcycles
 
 
-def time_form(s, igamg, torch, method, precision, steps, warmup):
+def time_form(s, igamg, torch, method, precision, steps, warmup, learned=False, trained=False):
     s.set_precision(precision)
+    if trained:
+        s.set_learned(learned)
     x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
     for _ in range(warmup):
         x.zero_()
@@ -116,6 +122,8 @@ def main():
     ap.add_argument("--headline-degree", type=int, default=3)
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--tail-items", type=int, default=32,
                     help="single-workgroup V-cycle threshold (0 = one launch per step everywhere)")
     ap.add_argument("--only-smoother", action="store_true",
@@ -160,22 +168,40 @@ def main():
     for p in degrees:
         log("[bench] setup quarter annulus %d^2 p=%d" % (N_EL, p))
         s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p, tail_items=args.tail_items)
-        s.set_rhs_field(synth.random_field_modes(2000 + p))
         res = {}
-        forms = (("plain_fp64", igamg.EXTRAP_NONE, igamg.FP64),
-                 ("rre_fp64", igamg.RRE, igamg.FP64),
-                 ("chosen", igamg.RRE, igamg.FP32_IR))
-        for name, method, prec in forms:
-            steps = args.steps if name == "chosen" or p == args.headline_degree else max(1, args.steps // 2)
+        trained = False
+        if p == args.headline_degree and not args.no_learned:
+            log("[bench] training the learned smoother p=%d" % p)
+            rep = s.train_smoother([synth.random_field_modes(5000 + k) for k in range(16)],
+                                   val_modes=synth.random_field_modes(5900), epochs=args.epochs)
+            res["learned_training"] = {k: v for k, v in rep.items()
+                                       if k not in ("loss_first", "loss_last")}
+            L = s.num_levels
+            res["learned_training"]["loss_first"] = [round(v, 5) for v in rep["loss_first"][:L]]
+            res["learned_training"]["loss_last"] = [round(v, 5) for v in rep["loss_last"][:L]]
+            trained = bool(rep["accepted"])
+        s.set_rhs_field(synth.random_field_modes(2000 + p))
+        forms = (("plain_fp64", igamg.EXTRAP_NONE, igamg.FP64, False),
+                 ("rre_fp64", igamg.RRE, igamg.FP64, False),
+                 ("ir_rre", igamg.RRE, igamg.FP32_IR, False),
+                 ("chosen", igamg.RRE, igamg.FP32_IR, True))
+        for name, method, prec, learned in forms:
+            if name == "chosen" and not trained:
+                res["chosen"] = dict(res["ir_rre"], learned=False)
+                xsol[(p, "chosen")] = xsol[(p, "ir_rre")]
+                continue
+            steps = args.steps if name in ("chosen", "ir_rre") or p == args.headline_degree \
+                else max(1, args.steps // 2)
             log("[bench] p=%d form=%s steps=%d" % (p, name, steps))
-            ms, st, x = time_form(s, igamg, torch, method, prec, steps, args.warmup)
+            ms, st, x = time_form(s, igamg, torch, method, prec, steps, args.warmup, learned, trained)
             res[name] = {"ms": round(ms, 3), "vcycles": st.vcycles, "restarts": st.restarts,
-                         "rel_residual": st.rel_residual,
+                         "rel_residual": st.rel_residual, "learned_fallbacks": st.learned_fallbacks,
                          "dof_updates_per_s": round(dof_updates(s, st.vcycles, 4) / (ms * 1e-3), 1)}
             res["setup_ms"] = round(st.setup_ms, 1)
             xsol[(p, name)] = x
         x64 = xsol[(p, "rre_fp64")]
-        res["chosen"]["err_vs_fp64_rre"] = float(torch.linalg.norm(xsol[(p, "chosen")] - x64) /
+        for name in ("ir_rre", "chosen"):
+            res[name]["err_vs_fp64_rre"] = float(torch.linalg.norm(xsol[(p, name)] - x64) /
                                                  torch.linalg.norm(x64))
         res["smoother_fp64"] = smoother_roofline(s, igamg, igamg.FP64)
         res["smoother_fp32"] = smoother_roofline(s, igamg, igamg.FP32_IR)
@@ -183,7 +209,8 @@ def main():
         if p == args.headline_degree:
             headline = res
         s.close()
-        del xsol[(p, "plain_fp64")]
+        for name in ("plain_fp64", "ir_rre"):
+            xsol.pop((p, name), None)
         torch.cuda.empty_cache()
     if headline is None:
         headline = results[degrees[0]]
@@ -213,11 +240,14 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "quarter annulus (radii 1, 2), B-spline p=%d, 1024x1024 elements, "
-                               "V(2,2) multicolour GS, 9 levels, RRE(5), FP32 V-cycles in FP64 "
-                               "refinement, random-field RHS seed %d" % (hp, 2000 + hp),
+                               "V(2,2) multicolour GS with the learned first pre-smoothing step, "
+                               "9 levels, RRE(5), FP32 V-cycles in FP64 refinement, random-field "
+                               "RHS seed %d" % (hp, 2000 + hp),
                    "degree": hp, "n_el": N_EL, "ndof": (N_EL + hp - 2) ** 2, "tol": TOL, "q": Q,
                    "plain_fp64_ms": headline["plain_fp64"]["ms"],
                    "rre_fp64_ms": headline["rre_fp64"]["ms"],
+                   "ir_rre_ms": headline["ir_rre"]["ms"],
+                   "chosen_uses_learned": headline["chosen"].get("learned", True),
                    "smoother_fp64_gbs": headline["smoother_fp64"]["achieved"],
                    "smoother_fp32_gbs": headline["smoother_fp32"]["achieved"],
                    "per_degree": {str(k): v for k, v in results.items()}},
