@@ -87,6 +87,60 @@ def smoother_roofline(s, igamg, precision, nsweeps=8):
             "avg_launch_us": round(ms * 1e3, 3), "bytes_per_launch": int(by), "launches": n}
 
 
+def batch_measure(igamg, torch, synth, steps, warmup):
+    """96 independent 2D problems (seeded sizes 32^2..512^2, p in 2..5, square or
+    annulus, RHS seed 4000 + i) solved by one batch, RRE(5) around FP32 V-cycles
+    in FP64 refinement; the same problems solved one after another beside it."""
+    probs = synth.batch_instances(96, 4)
+    geo = {0: igamg.UNIT_SQUARE, 1: igamg.QUARTER_ANNULUS}
+    t0 = time.perf_counter()
+    B = igamg.Batch([(geo[g], ne, p) for ne, p, g, _ in probs])
+    setup_s = time.perf_counter() - t0
+    xs = []
+    ndof = 0
+    for i, (ne, p, g, seed) in enumerate(probs):
+        B.instances[i].set_rhs_field(synth.random_field_modes(seed))
+        xs.append(torch.zeros(B.instances[i].ndof, dtype=torch.float64, device="cuda:0"))
+        ndof += B.instances[i].ndof
+    for _ in range(warmup):
+        for x in xs:
+            x.zero_()
+        B.solve(xs, tol=TOL, max_restarts=200, q=Q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for x in xs:
+            x.zero_()
+        stats, _ = B.solve(xs, tol=TOL, max_restarts=200, q=Q)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    worst = max(B.instances[i].residual(xs[i]) for i in range(len(xs)))
+    upd = 0
+    for i, st in enumerate(stats):
+        inst = B.instances[i]
+        upd += sum(inst.level_ndof(l) for l in range(1, inst.num_levels)) * 4 * st.vcycles
+    B.close()
+    # the same problems one by one (default single-problem path)
+    seq_ms = 0.0
+    for i, (ne, p, g, seed) in enumerate(probs):
+        s = igamg.Solver(geo[g], ne, p, precision=igamg.FP32_IR, n_el_coarsest=0)
+        s.set_rhs_field(synth.random_field_modes(seed))
+        x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
+        s.solve(x, tol=TOL, max_restarts=200, method=igamg.RRE, q=Q)
+        x.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.solve(x, tol=TOL, max_restarts=200, method=igamg.RRE, q=Q)
+        torch.cuda.synchronize()
+        seq_ms += (time.perf_counter() - t1) * 1e3
+        s.close()
+    return {"problems": len(probs), "ndof": ndof, "batch_ms": round(ms, 2),
+            "sequential_ms": round(seq_ms, 2), "speedup": round(seq_ms / ms, 2),
+            "dof_updates_per_s": round(upd / (ms * 1e-3), 1),
+            "max_restarts": max(s.restarts for s in stats), "worst_rel_residual": worst,
+            "setup_s": round(setup_s, 2)}
+
+
 def cpu_baseline(p, gpu_restarts):
     """The FP64 oracle's restarted RRE(5) solve of the same workload (p, 1024^2)."""
     import numpy as np
@@ -123,6 +177,8 @@ def main():
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--only-batch", action="store_true")
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--tail-items", type=int, default=32,
                     help="single-workgroup V-cycle threshold (0 = one launch per step everywhere)")
@@ -159,6 +215,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only_smoother": True, "degree": p, "copy_bytes": 2 * a.numel() * 8,
                           **out}), flush=True)
+        return
+
+    if args.only_batch:
+        print(json.dumps({"batch": batch_measure(igamg, torch, synth, args.steps, args.warmup)}),
+              flush=True)
         return
 
     degrees = [int(v) for v in args.degrees.split(",")]
@@ -216,6 +277,11 @@ def main():
         headline = results[degrees[0]]
         args.headline_degree = degrees[0]
 
+    batch = None
+    if not args.no_batch:
+        log("[bench] batch of 96 problems")
+        batch = batch_measure(igamg, torch, synth, max(1, args.steps // 2), args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) p=%d" % args.headline_degree)
@@ -250,7 +316,8 @@ def main():
                    "chosen_uses_learned": headline["chosen"].get("learned", True),
                    "smoother_fp64_gbs": headline["smoother_fp64"]["achieved"],
                    "smoother_fp32_gbs": headline["smoother_fp32"]["achieved"],
-                   "per_degree": {str(k): v for k, v in results.items()}},
+                   "per_degree": {str(k): v for k, v in results.items()},
+                   "batch": batch},
         "roofline": headline["smoother_fp32"],
         "cpu_baseline": cpu,
     }

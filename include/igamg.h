@@ -91,6 +91,8 @@ typedef struct {
                             64-point x slice work items run, with everything
                             below them, in one single-workgroup kernel per
                             V-cycle (default 32; 0 disables)                  */
+    int stored_stencil;  /* unit square: store (2p+1)^2 stencils (expanded from
+                            the Kronecker factors) instead of the factors (0) */
     void* stream;        /* hipStream_t or NULL                               */
 } igamg_options;
 
@@ -104,7 +106,8 @@ typedef struct {
     double solve_ms;     /* wall time of the solve call                       */
 } igamg_stats;
 
-/* Fills the defaults listed above. */
+/* Fills the defaults listed above.  n_el_coarsest <= 0 selects, per grid, the
+ * coarsest size m in 4..7 with n_el = m 2^k. */
 void igamg_options_default(igamg_options* opt);
 
 /* Builds the hierarchy (Section 2): knots and Gauss rules, the finest
@@ -254,6 +257,28 @@ igamg_status igamg_smoother_forward(igamg_ctx* ctx, int level, const float* z_de
  * respect to the canonical weights (host, 2592 FP32 values). */
 igamg_status igamg_smoother_loss_grad(igamg_ctx* ctx, int level, const float* z_dev,
                                       const float* t_dev, double* loss, float* grad);
+
+/* ---- Batches of independent 2D problems ---------------------------------
+ * A batch holds `count` problems of any 2D geometry, degree (1..5) and size
+ * (coarsest grid chosen per problem as for n_el_coarsest <= 0), all solved by
+ * restarted RRE(q) around FP32 V-cycles inside FP64 refinement (the precision
+ * and smoother fields of opt are ignored).  Every V-cycle step is one launch
+ * per degree group covering all unconverged problems of that degree; the
+ * degree groups run as parallel branches of one captured graph per restart
+ * cycle; extrapolation and the accuracy test are per problem.  All work is on
+ * opt->stream (or a stream the batch creates). */
+typedef struct igamg_batch igamg_batch;
+igamg_status igamg_setup_batch(int count, const igamg_geometry* geoms, const int* degrees,
+                               const igamg_options* opt, igamg_batch** out);
+void igamg_destroy_batch(igamg_batch* batch);
+/* Problem i of the batch as a context (owned by the batch): ndof, set_rhs,
+ * set_rhs_field, residual and the other single-problem calls apply to it. */
+igamg_status igamg_batch_instance(igamg_batch* batch, int i, igamg_ctx** ctx);
+/* Solves every problem from the initial guesses x_dev[i] until its relative
+ * residual is <= tol (per problem); stats[i] per problem (may be NULL).
+ * Returns ENOCONV if any problem did not converge within max_restarts. */
+igamg_status igamg_solve_batch(igamg_batch* batch, double tol, int max_restarts, int q,
+                               double* const* x_dev, igamg_stats* stats);
 
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* igamg_last_error(void);

@@ -21,6 +21,7 @@
 #include "host_spline.hpp"
 #include "kernels.hpp"
 #include "learned.hpp"
+#include "batch.hpp"
 
 using namespace igamg;
 
@@ -269,6 +270,36 @@ struct igamg_ctx {
             if (colour_items(l) > opt.tail_items) break;
             tail_top = l;
         }
+    }
+
+    // Arguments of the single-workgroup V-cycle on levels 0..tail_top.
+    template <class Op>
+    TailArgs<Op> tail_args(const typename Op::T* bt, typename Op::T* xt) {
+        using T = typename Op::T;
+        TailArgs<Op> a{};
+        a.top = tail_top;
+        a.nu1 = opt.nu1;
+        a.nu2 = opt.nu2;
+        a.n0 = n0;
+        a.Ainv = Ainv0;
+        for (int l = 0; l <= tail_top; ++l) {
+            with_op<T>(l, [&](auto opl) {
+                if constexpr (std::is_same_v<decltype(opl), Op>) a.op[l] = opl;
+            });
+            a.N[l] = lv[l].N;
+            a.x[l] = (l == tail_top) ? xt : lv[l].x<T>();
+            a.b[l] = (l == tail_top) ? (T*)bt : lv[l].b<T>();
+            a.r[l] = lv[l].r<T>();
+            if (l >= 1) {
+                a.rs[l] = lv[l].r_start;
+                a.rw[l] = lv[l].rw<T>();
+                a.ps[l] = lv[l].p_start;
+                a.pw[l] = lv[l].pw<T>();
+                a.RW[l] = lv[l].RW;
+                a.PW[l] = lv[l].PW;
+            }
+        }
+        return a;
     }
 
     // V-cycle on levels 0..tail_top by one workgroup.
@@ -619,6 +650,7 @@ struct igamg_ctx {
     void setup_kron();
     void setup_annulus();
     void setup_coarse();
+    void setup_kron_stencils();
     void set_rhs_field(const double* modes, int n_modes);
 };
 
@@ -626,6 +658,13 @@ struct igamg_ctx {
 // setup
 
 void igamg_ctx::setup_levels(int n_el, int levels) {
+    if (opt.n_el_coarsest <= 0) {
+        int m = n_el;
+        while (m > 7 && m % 2 == 0) m /= 2;
+        while (m < 4 && m > 0) m *= 2;
+        if (m < 4 || m > 7 || n_el % m) throw Error(IGAMG_EINVAL, "n_el is not m 2^k with m in 4..7");
+        opt.n_el_coarsest = m;
+    }
     int nc0 = opt.n_el_coarsest;
     if (nc0 < 1 || n_el < nc0 || n_el % nc0)
         throw Error(IGAMG_EINVAL, "n_el must be n_el_coarsest * 2^k");
@@ -806,6 +845,27 @@ void igamg_ctx::setup_coarse() {
     Ainv0 = upload(inverse_from_cholesky(A, n0));
 }
 
+// Unit square with stored stencils: every level's (2p+1)^2 rows written out
+// from its Kronecker factors (the same operator, one operator type for all 2D
+// problems of a batch).
+void igamg_ctx::setup_kron_stencils() {
+    const int W = 2 * p + 1, Sn = W * W;
+    for (int l = 0; l <= L; ++l) {
+        Level& v = lv[l];
+        size_t cnt = (size_t)v.ncol * Sn * v.ncp;
+        v.coef64 = alloc<double>(cnt);
+        v.coef32 = alloc<float>(cnt);
+        fill(v.coef64, (long long)cnt);
+        fill(v.coef32, (long long)cnt);
+        with_p([&](auto PC) {
+            constexpr int P = decltype(PC)::value;
+            hipLaunchKernelGGL(k_kron_to_stencil<P>, dim3(grid_for(v.N * Sn)), dim3(kBlock), 0, stream,
+                               (const double*)v.K64, (const double*)v.M64, v.n, v.ncp, v.coef64, v.coef32);
+        });
+        check_launch();
+    }
+}
+
 void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
     auto t0 = std::chrono::steady_clock::now();
     geom = g.kind;
@@ -834,12 +894,14 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
         IGAMG_HIP(hipStreamCreateWithFlags(&stream, hipStreamDefault));  // orders against the legacy stream
         own_stream = true;
     }
+    if (kind == OP_KRON2D && opt.stored_stencil) kind = OP_STENCIL2D;
     setup_levels(g.n_el, levels);
-    if (kind == OP_STENCIL2D) {
+    if (geom == IGAMG_QUARTER_ANNULUS) {
         setup_annulus();
     } else {
         setup_kron();
         setup_coarse();
+        if (kind == OP_STENCIL2D) setup_kron_stencils();
     }
     for (int l = 0; l <= L; ++l) {
         Level& v = lv[l];
@@ -1256,6 +1318,299 @@ void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
 }
 
 // ---------------------------------------------------------------------------
+// batches of independent 2D problems
+
+#define BLAUNCH(...) do { if (!preparing) hipLaunchKernelGGL(__VA_ARGS__); } while (0)
+
+struct igamg_batch {
+    std::vector<igamg_ctx*> inst;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<hipStream_t> side;  // one per degree group (graph branches)
+    std::vector<hipEvent_t> ev;
+    std::vector<void*> plan_allocs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int> plan_active;
+    int plan_q = -1;
+    double* rel_dev = nullptr;
+    double* rel_host = nullptr;
+    const double** scal_ptrs = nullptr;
+
+    ~igamg_batch() {
+        clear_plan();
+        for (auto* c : inst) delete c;
+        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto st : side) (void)hipStreamDestroy(st);
+        if (rel_host) (void)hipHostFree(rel_host);
+        if (rel_dev) (void)hipFree(rel_dev);
+        if (scal_ptrs) (void)hipFree((void*)scal_ptrs);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+    void clear_plan() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        for (void* a : plan_allocs) (void)hipFree(a);
+        plan_allocs.clear();
+        plan_active.clear();
+        plan_q = -1;
+    }
+    // Tables are built in a prepare pass (allocated and uploaded, nothing
+    // launched) and reused, in the same order, by the capture pass.
+    bool preparing = false;
+    size_t cursor = 0;
+    template <typename E>
+    const E* up(const std::vector<E>& v) {
+        if (!preparing) return (const E*)plan_allocs.at(cursor++);
+        void* d = nullptr;
+        IGAMG_HIP(hipMalloc(&d, std::max<size_t>(1, v.size()) * sizeof(E)));
+        plan_allocs.push_back(d);
+        IGAMG_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice));
+        return (const E*)d;
+    }
+    // prefix offsets of per-entry block counts
+    const int* offsets(const std::vector<int>& counts, int& total) {
+        std::vector<int> o(counts.size() + 1, 0);
+        for (size_t i = 0; i < counts.size(); ++i) o[i + 1] = o[i] + counts[i];
+        total = o.back();
+        return up(o);
+    }
+
+    // One launch per step of the FP32-in-FP64 map G for all `mem` problems of
+    // degree P on stream st: G(W) = W + V32(round32(b - A64 W)), W = lv[L].x64.
+    template <int P>
+    void group_G(const std::vector<int>& mem, hipStream_t st) {
+        using Op64 = Stencil2D<P, double>;
+        using Op32 = Stencil2D<P, float>;
+        constexpr int NC = Op32::NC;
+        const int ne = (int)mem.size();
+        int D = 0;
+        for (int i : mem) D = std::max(D, inst[i]->L);
+        // fine-level FP64 residual into b32, zero x32
+        {
+            std::vector<BRes<Op64, float>> E;
+            std::vector<int> cnt;
+            std::vector<BVec> Z;
+            std::vector<int> zc;
+            for (int i : mem) {
+                igamg_ctx* c = inst[i];
+                Level& f = c->lv[c->L];
+                E.push_back({Op64{f.coef64, f.n, f.ncp}, c->b, f.x64, f.b32, f.N});
+                cnt.push_back(NC * (f.ncp / 64));
+                Z.push_back({nullptr, nullptr, f.x32, f.N});
+                zc.push_back((int)grid_for(f.N));
+            }
+            int tot, ztot;
+            const int* o = offsets(cnt, tot);
+            const int* zo = offsets(zc, ztot);
+            auto tb_E_1 = up(E);
+            BLAUNCH((k_b_res<Op64, float>), dim3(tot), dim3(64 * Op64::NW), 0, st, tb_E_1, o, ne);
+            auto tb_Z_2 = up(Z);
+            BLAUNCH(k_b_vec, dim3(ztot), dim3(kBlock), 0, st, tb_Z_2, zo, ne, 0);
+        }
+        // per depth: smoothing tables (shared by descent and ascent)
+        auto gs_tables = [&](int d, std::vector<int>& sel) {
+            std::vector<BGs<Op32>> E;
+            std::vector<int> offs((size_t)NC * 0);
+            sel.clear();
+            for (int k = 0; k < ne; ++k) {
+                igamg_ctx* c = inst[mem[k]];
+                int l = c->L - d;
+                if (l <= c->tail_top) continue;
+                sel.push_back(k);
+                Level& v = c->lv[l];
+                E.push_back({Op32{v.coef32, v.n, v.ncp}, v.b32, v.x32});
+            }
+            return E;
+        };
+        auto launch_sweeps = [&](int d, int nsweeps) {
+            std::vector<int> sel;
+            auto E = gs_tables(d, sel);
+            if (E.empty() || nsweeps == 0) return;
+            int nsel = (int)sel.size();
+            std::vector<int> offs((size_t)NC * (nsel + 1), 0);
+            std::vector<int> tot(NC, 0);
+            for (int c = 0; c < NC; ++c) {
+                for (int k = 0; k < nsel; ++k) {
+                    igamg_ctx* cx = inst[mem[sel[k]]];
+                    int cs = colour_size_host(cx->lv[cx->L - d].n, P, 2, c);
+                    offs[(size_t)c * (nsel + 1) + k + 1] = offs[(size_t)c * (nsel + 1) + k] + (cs + 63) / 64;
+                }
+                tot[c] = offs[(size_t)c * (nsel + 1) + nsel];
+            }
+            const BGs<Op32>* dE = up(E);
+            const int* dO = up(offs);
+            for (int s2 = 0; s2 < nsweeps; ++s2)
+                for (int c = 0; c < NC; ++c)
+                    if (tot[c] > 0)
+                        BLAUNCH((k_b_gs<Op32>), dim3(tot[c]), dim3(64 * Op32::NW), 0, st, dE, dO,
+                                           nsel, c);
+        };
+        for (int d = 0; d < D; ++d) {
+            launch_sweeps(d, inst[mem[0]]->opt.nu1);
+            std::vector<BRes<Op32, float>> R;
+            std::vector<int> rc;
+            std::vector<BTr<float>> T;
+            std::vector<int> tc;
+            for (int i : mem) {
+                igamg_ctx* c = inst[i];
+                int l = c->L - d;
+                if (l <= c->tail_top) continue;
+                Level& v = c->lv[l];
+                Level& w = c->lv[l - 1];
+                R.push_back({Op32{v.coef32, v.n, v.ncp}, v.b32, v.x32, v.r32, v.N});
+                rc.push_back(NC * (v.ncp / 64));
+                T.push_back({v.r32, w.b32, w.x32, v.n, w.n, v.r_start, v.r_w32, v.RW});
+                tc.push_back((int)grid_for(w.N));
+            }
+            if (R.empty()) continue;
+            int rt, tt;
+            const int* ro = offsets(rc, rt);
+            const int* to = offsets(tc, tt);
+            auto tR = up(R);
+            auto tT = up(T);
+            BLAUNCH((k_b_res<Op32, float>), dim3(rt), dim3(64 * Op32::NW), 0, st, tR, ro, (int)R.size());
+            BLAUNCH(k_b_restrict<float>, dim3(tt), dim3(kBlock), 0, st, tT, to, (int)T.size());
+        }
+        {
+            // every problem's small levels (and its coarsest solve): one workgroup each
+            std::vector<TailArgs<Op32>> TA;
+            for (int i : mem) {
+                igamg_ctx* c = inst[i];
+                int t = c->tail_top;
+                TA.push_back(c->tail_args<Op32>(c->lv[t].b32, c->lv[t].x32));
+            }
+            auto tTA = up(TA);
+            BLAUNCH((k_b_tail<Op32>), dim3(ne), dim3(kTailThreads), 0, st, tTA);
+        }
+        for (int d = D - 1; d >= 0; --d) {
+            std::vector<BTr<float>> T;
+            std::vector<int> tc;
+            for (int i : mem) {
+                igamg_ctx* c = inst[i];
+                int l = c->L - d;
+                if (l <= c->tail_top) continue;
+                Level& v = c->lv[l];
+                Level& w = c->lv[l - 1];
+                T.push_back({w.x32, v.x32, nullptr, v.n, w.n, v.p_start, v.p_w32, v.PW});
+                tc.push_back((int)grid_for(v.N));
+            }
+            if (T.empty()) continue;
+            int tt;
+            const int* to = offsets(tc, tt);
+            auto tb_T_6 = up(T);
+            BLAUNCH(k_b_prolong<float>, dim3(tt), dim3(kBlock), 0, st, tb_T_6, to, (int)T.size());
+            launch_sweeps(d, inst[mem[0]]->opt.nu2);
+        }
+        // W += x32
+        {
+            std::vector<BVec> A;
+            std::vector<int> ac;
+            for (int i : mem) {
+                igamg_ctx* c = inst[i];
+                Level& f = c->lv[c->L];
+                A.push_back({nullptr, f.x64, f.x32, f.N});
+                ac.push_back((int)grid_for(f.N));
+            }
+            int at;
+            const int* ao = offsets(ac, at);
+            auto tb_A_7 = up(A);
+            BLAUNCH(k_b_vec, dim3(at), dim3(kBlock), 0, st, tb_A_7, ao, ne, 2);
+        }
+    }
+
+    // copies between each active problem's iterate buffers: mode 1, b64 = a64
+    void copies(const std::vector<int>& act, int from, int to_) {
+        std::vector<BVec> E;
+        std::vector<int> c;
+        for (int i : act) {
+            igamg_ctx* x = inst[i];
+            Level& f = x->lv[x->L];
+            double* src = from < 0 ? f.x64 : x->S[from];
+            double* dst = to_ < 0 ? f.x64 : x->S[to_];
+            E.push_back({src, dst, nullptr, f.N});
+            c.push_back((int)grid_for(f.N));
+        }
+        int tot;
+        const int* o = offsets(c, tot);
+        auto tb_E_8 = up(E);
+        BLAUNCH(k_b_vec, dim3(tot), dim3(kBlock), 0, stream, tb_E_8, o, (int)act.size(), 1);
+    }
+
+    // Enqueue one restart cycle of every active problem.
+    void restart_round(const std::vector<int>& act, int q) {
+        std::vector<std::vector<int>> byp(6);
+        for (int i : act) byp[inst[i]->p].push_back(i);
+        copies(act, 0, -1);
+        for (int j = 0; j <= q; ++j) {
+            // fork: one branch per degree group
+            int g = 0;
+            if (!preparing) IGAMG_HIP(hipEventRecord(ev[0], stream));
+            for (int pp = 1; pp <= 5; ++pp) {
+                if (byp[pp].empty()) continue;
+                hipStream_t st = side[g];
+                if (!preparing) IGAMG_HIP(hipStreamWaitEvent(st, ev[0], 0));
+                switch (pp) {
+                    case 1: group_G<1>(byp[pp], st); break;
+                    case 2: group_G<2>(byp[pp], st); break;
+                    case 3: group_G<3>(byp[pp], st); break;
+                    case 4: group_G<4>(byp[pp], st); break;
+                    case 5: group_G<5>(byp[pp], st); break;
+                }
+                if (!preparing) IGAMG_HIP(hipEventRecord(ev[1 + g], st));
+                ++g;
+            }
+            for (int k = 0; k < g && !preparing; ++k) IGAMG_HIP(hipStreamWaitEvent(stream, ev[1 + k], 0));
+            copies(act, -1, j + 1);
+        }
+        for (int i : act) {
+            if (preparing) break;
+            igamg_ctx* c = inst[i];
+            IterPtrs it = c->iter_ptrs(q);
+            c->extrap_coeffs_async(it, q, IGAMG_RRE);
+            long long N = c->lv[c->L].N;
+            BLAUNCH(k_extrap_combine, dim3(grid_for(N)), dim3(kBlock), 0, stream, it, q, N,
+                               (const ExtrapCoeffs*)c->coeffs, c->S[0]);
+            c->resnorm_async(c->S[0]);
+        }
+        BLAUNCH(k_b_gather, dim3(((int)inst.size() + 127) / 128), dim3(128), 0, stream, scal_ptrs,
+                (int)inst.size(), rel_dev);
+        if (!preparing) IGAMG_HIP(hipGetLastError());
+    }
+
+    void run_round(const std::vector<int>& act, int q) {
+        if (act != plan_active || q != plan_q) {
+            clear_plan();
+            preparing = true;
+            restart_round(act, q);
+            preparing = false;
+            cursor = 0;
+            IGAMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            try {
+                restart_round(act, q);
+            } catch (...) {
+                hipGraph_t gg = nullptr;
+                (void)hipStreamEndCapture(stream, &gg);
+                if (gg) (void)hipGraphDestroy(gg);
+                throw;
+            }
+            IGAMG_HIP(hipStreamEndCapture(stream, &graph));
+            IGAMG_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            plan_active = act;
+            plan_q = q;
+        }
+        IGAMG_HIP(hipGraphLaunch(gexec, stream));
+        IGAMG_HIP(hipMemcpyAsync(rel_host, rel_dev, inst.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 stream));
+        IGAMG_HIP(hipStreamSynchronize(stream));
+    }
+};
+
+#undef BLAUNCH
+
+// ---------------------------------------------------------------------------
 // C ABI
 
 namespace {
@@ -1296,6 +1651,7 @@ void igamg_options_default(igamg_options* opt) {
     opt->n_el_coarsest = 4;
     opt->use_graphs = 1;
     opt->tail_items = 32;
+    opt->stored_stencil = 0;
     opt->stream = nullptr;
 }
 
@@ -1623,6 +1979,119 @@ igamg_status igamg_profile_smoother(igamg_ctx* ctx, int level, int precision, in
         need(precision == IGAMG_FP64 || precision == IGAMG_FP32_IR, "bad precision");
         ctx->profile_smoother(level, precision, nsweeps, avg_ms, bytes, launches);
     });
+}
+
+igamg_status igamg_setup_batch(int count, const igamg_geometry* geoms, const int* degrees,
+                               const igamg_options* opt, igamg_batch** out) {
+    return guarded([&] {
+        need(count >= 1 && geoms && degrees && out, "bad argument");
+        *out = nullptr;
+        std::unique_ptr<igamg_batch> B(new igamg_batch());
+        igamg_options o;
+        if (opt)
+            o = *opt;
+        else
+            igamg_options_default(&o);
+        if (o.stream) {
+            B->stream = (hipStream_t)o.stream;
+        } else {
+            IGAMG_HIP(hipStreamCreateWithFlags(&B->stream, hipStreamDefault));
+            B->own_stream = true;
+        }
+        o.stream = B->stream;
+        o.precision = IGAMG_FP32_IR;
+        o.smoother = IGAMG_SMOOTH_MCGS;
+        o.stored_stencil = 1;
+        if (!opt) o.tail_items = 32;
+        o.n_el_coarsest = 0;
+        o.use_graphs = 0;
+        for (int i = 0; i < count; ++i) {
+            need(geoms[i].kind == IGAMG_UNIT_SQUARE || geoms[i].kind == IGAMG_QUARTER_ANNULUS,
+                 "batches hold 2D problems");
+            std::unique_ptr<igamg_ctx> c(new igamg_ctx());
+            c->opt = o;
+            c->setup(geoms[i], degrees[i], 0);
+            B->inst.push_back(c.release());
+        }
+        for (int g = 0; g < 5; ++g) {
+            hipStream_t st;
+            IGAMG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            B->side.push_back(st);
+        }
+        for (int e = 0; e < 6; ++e) {
+            hipEvent_t evv;
+            IGAMG_HIP(hipEventCreateWithFlags(&evv, hipEventDisableTiming));
+            B->ev.push_back(evv);
+        }
+        IGAMG_HIP(hipMalloc((void**)&B->rel_dev, count * sizeof(double)));
+        IGAMG_HIP(hipHostMalloc((void**)&B->rel_host, count * sizeof(double), hipHostMallocDefault));
+        std::vector<const double*> sp(count);
+        for (int i = 0; i < count; ++i) sp[i] = B->inst[i]->scal;
+        IGAMG_HIP(hipMalloc((void**)&B->scal_ptrs, count * sizeof(double*)));
+        IGAMG_HIP(hipMemcpy((void*)B->scal_ptrs, sp.data(), count * sizeof(double*), hipMemcpyHostToDevice));
+        *out = B.release();
+    });
+}
+
+void igamg_destroy_batch(igamg_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+igamg_status igamg_batch_instance(igamg_batch* b, int i, igamg_ctx** ctx) {
+    return guarded([&] {
+        need(b && ctx && i >= 0 && i < (int)b->inst.size(), "bad argument");
+        *ctx = b->inst[i];
+    });
+}
+
+igamg_status igamg_solve_batch(igamg_batch* b, double tol, int max_restarts, int q,
+                               double* const* x_dev, igamg_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    int n = b ? (int)b->inst.size() : 0;
+    std::vector<igamg_stats> st(n);
+    bool all = false;
+    igamg_status s = guarded([&] {
+        need(b && x_dev && tol > 0 && max_restarts > 0, "bad argument");
+        need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
+        std::vector<int> act;
+        for (int i = 0; i < n; ++i) {
+            need(x_dev[i] != nullptr, "null iterate");
+            igamg_ctx* c = b->inst[i];
+            c->ensure_iterates(q);
+            c->copy(x_dev[i], c->S[0], c->lv[c->L].N);
+            act.push_back(i);
+        }
+        for (int k = 0; k < max_restarts && !act.empty(); ++k) {
+            b->run_round(act, q);
+            std::vector<int> next;
+            for (int i : act) {
+                double rel = b->rel_host[i];
+                st[i].restarts++;
+                st[i].vcycles += q + 1;
+                st[i].rel_residual = rel;
+                if (!std::isfinite(rel)) throw Error(IGAMG_ENONFINITE, "non-finite residual in a batch problem");
+                if (rel > tol) next.push_back(i);
+            }
+            act = next;
+        }
+        for (int i = 0; i < n; ++i) {
+            igamg_ctx* c = b->inst[i];
+            c->copy(c->S[0], x_dev[i], c->lv[c->L].N);
+            st[i].setup_ms = c->setup_ms;
+        }
+        IGAMG_HIP(hipStreamSynchronize(b->stream));
+        all = act.empty();
+        if (!all) throw Error(IGAMG_ENOCONV, "some batch problems did not converge");
+    });
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats)
+        for (int i = 0; i < n; ++i) {
+            st[i].solve_ms = ms;
+            stats[i] = st[i];
+        }
+    return s;
 }
 
 void igamg_train_options_default(igamg_train_options* o) {

@@ -263,15 +263,13 @@ struct Kron3D {
 // (all of the slice's loads in flight at once), the partials meet in LDS and
 // are summed in slice order.
 template <class Op>
-__global__ void __launch_bounds__(64 * Op::NW) k_gs_colour_sliced(Op A,
-                                                                  const typename Op::T* __restrict__ b,
-                                                                  typename Op::T* __restrict__ x,
-                                                                  int c) {
+__device__ __forceinline__ void gs_colour_body(const Op& A, const typename Op::T* __restrict__ b,
+                                               typename Op::T* __restrict__ x, int c, int blk) {
     using T = typename Op::T;
     __shared__ T part[Op::NW][64];
     __shared__ T dg[64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int k = xcd_swizzle(blockIdx.x, gridDim.x) * 64 + lane;
+    int k = blk * 64 + lane;
     typename Op::Pt pt;
     bool ok = A.point(c, k, pt);
     T d = 1, sl = 0;
@@ -287,19 +285,24 @@ __global__ void __launch_bounds__(64 * Op::NW) k_gs_colour_sliced(Op A,
     }
 }
 
-// Residual-type products with the sliced layout: r = b - A x (mode 0),
-// y = A x (mode 1), damped Jacobi step (mode 2); optional per-block sums of
-// squares.  Colour-ordered traversal for stored stencils, natural otherwise.
+template <class Op>
+__global__ void __launch_bounds__(64 * Op::NW) k_gs_colour_sliced(Op A,
+                                                                  const typename Op::T* __restrict__ b,
+                                                                  typename Op::T* __restrict__ x,
+                                                                  int c) {
+    gs_colour_body(A, b, x, c, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
 template <class Op, typename Tout>
-__global__ void __launch_bounds__(64 * Op::NW) k_residual_sliced(
-    Op A, const typename Op::T* __restrict__ b, const typename Op::T* __restrict__ x,
-    Tout* __restrict__ out, int mode, double omega, long long N, double* __restrict__ partial) {
+__device__ __forceinline__ void residual_body(const Op& A, const typename Op::T* __restrict__ b,
+                                              const typename Op::T* __restrict__ x,
+                                              Tout* __restrict__ out, int mode, double omega,
+                                              long long N, double* __restrict__ partial, int blk,
+                                              int slot) {
     using T = typename Op::T;
     __shared__ T part[Op::NW][64];
     __shared__ T dg[64];
-    __shared__ double red[Op::NW];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int blk = xcd_swizzle(blockIdx.x, gridDim.x);
     typename Op::Pt pt;
     bool ok;
     int c = 0, k = 0;
@@ -335,9 +338,20 @@ __global__ void __launch_bounds__(64 * Op::NW) k_residual_sliced(
     if (partial) {
         if (w == 0) {
             double t = wave_sum(sq);
-            if (lane == 0) partial[blockIdx.x] = t;
+            if (lane == 0) partial[slot] = t;
         }
     }
+}
+
+// Residual-type products with the sliced layout: r = b - A x (mode 0),
+// y = A x (mode 1), damped Jacobi step (mode 2); optional per-block sums of
+// squares.  Colour-ordered traversal for stored stencils, natural otherwise.
+template <class Op, typename Tout>
+__global__ void __launch_bounds__(64 * Op::NW) k_residual_sliced(
+    Op A, const typename Op::T* __restrict__ b, const typename Op::T* __restrict__ x,
+    Tout* __restrict__ out, int mode, double omega, long long N, double* __restrict__ partial) {
+    residual_body<Op, Tout>(A, b, x, out, mode, omega, N, partial, xcd_swizzle(blockIdx.x, gridDim.x),
+                            blockIdx.x);
 }
 
 // Deterministic final reduction: out[0] = sqrt(sum partial) / denom.
@@ -833,7 +847,7 @@ __device__ void tail_prolong(const T* ec, int nc, T* xf, int nf, const int* ps, 
 // V-cycle (Algorithm 2, mu = 1) on levels 0..top with right-hand side b[top]
 // and iterate x[top] (in place), by one workgroup.
 template <class Op>
-__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs<Op> a) {
+__device__ void vcycle_tail_body(const TailArgs<Op>& a) {
     using T = typename Op::T;
     constexpr int NW = Op::NW;
     constexpr int DIM = std::is_same<typename Op::Pt, Pt3>::value ? 3 : 2;
@@ -860,6 +874,17 @@ __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs<Op> a) {
         for (int s = 0; s < a.nu2; ++s)
             for (int c = 0; c < Op::NC; ++c) tail_colour(A, a.b[l], a.x[l], a.r[l], c, 0, part, dg);
     }
+}
+
+template <class Op>
+__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs<Op> a) {
+    vcycle_tail_body(a);
+}
+
+// Batched: workgroup e runs problem e's small-level V-cycle.
+template <class Op>
+__global__ void __launch_bounds__(kTailThreads) k_b_tail(const TailArgs<Op>* __restrict__ A) {
+    vcycle_tail_body(A[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1134,6 +1159,31 @@ __global__ void k_to_colour_blocked(const double* __restrict__ st, int n, int nc
     double v = st[t];
     c64[dst] = v;
     if (c32) c32[dst] = (float)v;
+}
+
+// Unit-square Kronecker operator K(x)M + M(x)K written out as colour-blocked
+// (2p+1)^2 stencils (FP64 and FP32), entry by entry from the band factors.
+template <int P>
+__global__ void k_kron_to_stencil(const double* __restrict__ K, const double* __restrict__ M, int n,
+                                  int ncp, double* __restrict__ c64, float* __restrict__ c32) {
+    constexpr int W = 2 * P + 1, S = W * W;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long long)n * n * S) return;
+    long long I = t / S;
+    int o = (int)(t - I * S);
+    int j = (int)(I / n), i = (int)(I - (long long)j * n);
+    int da = o % W - P, db = o / W - P;
+    double v = 0.0;
+    if (i + da >= 0 && i + da < n && j + db >= 0 && j + db < n)
+        v = K[(size_t)i * W + da + P] * M[(size_t)j * W + db + P] +
+            M[(size_t)i * W + da + P] * K[(size_t)j * W + db + P];
+    int ci = i % (P + 1), cj = j % (P + 1);
+    int c = ci + (P + 1) * cj;
+    int ni = (n - ci + P) / (P + 1);
+    int k = i / (P + 1) + ni * (j / (P + 1));
+    size_t dst = ((size_t)c * S + o) * ncp + k;
+    c64[dst] = v;
+    c32[dst] = (float)v;
 }
 
 // Diagonal of a colour-blocked stencil in natural order (FP64 and FP32).

@@ -33,7 +33,8 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("smoother", ctypes.c_int),
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("n_el_coarsest", ctypes.c_int), ("use_graphs", ctypes.c_int),
-                ("tail_items", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("tail_items", ctypes.c_int), ("stored_stencil", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -111,6 +112,10 @@ _SIGNATURES = {
     "igamg_set_smoother_weights": (_i, [_P, _i, _P, ctypes.c_size_t]),
     "igamg_smoother_forward": (_i, [_P, _i, _P, _P]),
     "igamg_smoother_loss_grad": (_i, [_P, _i, _P, _P, ctypes.POINTER(_d), _P]),
+    "igamg_setup_batch": (_i, [_i, _P, _P, ctypes.POINTER(Options), ctypes.POINTER(_P)]),
+    "igamg_destroy_batch": (None, [_P]),
+    "igamg_batch_instance": (_i, [_P, _i, ctypes.POINTER(_P)]),
+    "igamg_solve_batch": (_i, [_P, _d, _i, _i, _P, _P]),
     "igamg_last_error": (ctypes.c_char_p, []),
     "igamg_host_gauss_legendre": (_i, [_i, _P, _P]),
     "igamg_host_basis": (_i, [_i, _i, _d, _P, _P, ctypes.POINTER(_i)]),
@@ -368,6 +373,67 @@ class Solver:
         _check(lib().igamg_extrap_coeffs(self._h, method, q, _ptr(iterates), _np_ptr(gamma),
                                          ctypes.byref(info)), "igamg_extrap_coeffs")
         return gamma, info.value
+
+
+class _Borrowed(Solver):
+    """A problem owned by a batch, addressed with the single-problem calls."""
+
+    def __init__(self, handle, geometry, n_el, degree):
+        self._h = handle
+        self._owned = False
+        self.geometry, self.n_el, self.degree = geometry, n_el, degree
+
+    def close(self):
+        self._h = None
+
+
+class Batch:
+    """A batch of independent 2D problems (include/igamg.h, igamg_setup_batch)."""
+
+    def __init__(self, problems, stream=None):
+        """problems: list of (geometry, n_el, degree)."""
+        import torch
+        if stream is None:
+            cs = torch.cuda.current_stream()
+            stream = None if cs.cuda_stream == 0 else cs.cuda_stream
+        n = len(problems)
+        geoms = (Geometry * n)(*[Geometry(g, e) for g, e, _ in problems])
+        degs = (ctypes.c_int * n)(*[d for _, _, d in problems])
+        o = default_options()
+        o.stream = stream
+        h = _P()
+        _check(lib().igamg_setup_batch(n, ctypes.cast(geoms, _P), ctypes.cast(degs, _P),
+                                       ctypes.byref(o), ctypes.byref(h)), "igamg_setup_batch")
+        self._h = h
+        self.problems = list(problems)
+        self.instances = []
+        for i, (g, e, d) in enumerate(problems):
+            ih = _P()
+            _check(lib().igamg_batch_instance(h, i, ctypes.byref(ih)), "igamg_batch_instance")
+            self.instances.append(_Borrowed(ih, g, e, d))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for s in self.instances:
+                s.close()
+            lib().igamg_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, xs, tol=1e-10, max_restarts=100, q=5, check=True):
+        n = len(xs)
+        ptrs = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+        stats = (Stats * n)()
+        st = lib().igamg_solve_batch(self._h, tol, max_restarts, q, ctypes.cast(ptrs, _P),
+                                     ctypes.cast(stats, _P))
+        if check:
+            _check(st, "igamg_solve_batch")
+        return [stats[i] for i in range(n)], st
 
 
 # ---- host-only helpers (no GPU needed)

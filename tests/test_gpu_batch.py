@@ -1,0 +1,60 @@
+"""Batched solves: every problem of a batch must equal its standalone solve
+(same kernels, same order) and reach the tolerance by its true residual; the
+unit-square stored-stencil form must equal the Kronecker form."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import assemble
+from paper_2412_20205_amd import igamg
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+PROBLEMS = [(igamg.QUARTER_ANNULUS, 32, 3), (igamg.UNIT_SQUARE, 40, 2), (igamg.QUARTER_ANNULUS, 56, 5),
+            (igamg.UNIT_SQUARE, 48, 4), (igamg.QUARTER_ANNULUS, 80, 2), (igamg.UNIT_SQUARE, 112, 5),
+            (igamg.QUARTER_ANNULUS, 64, 4), (igamg.QUARTER_ANNULUS, 28 * 4, 3)]
+
+
+def test_stored_stencil_square_equals_kronecker():
+    a = igamg.Solver(igamg.UNIT_SQUARE, 32, 3)
+    b = igamg.Solver(igamg.UNIT_SQUARE, 32, 3, stored_stencil=1)
+    for l in range(a.num_levels):
+        rows = np.arange(a.level_ndof(l))
+        assert np.abs(a.operator_rows(l, rows) - b.operator_rows(l, rows)).max() < 1e-15 * 100
+
+
+def test_batch_equals_standalone_and_converges():
+    print("[case] batch of %d" % len(PROBLEMS), flush=True)
+    B = igamg.Batch(PROBLEMS)
+    xs = []
+    for i, (g, e, d) in enumerate(PROBLEMS):
+        B.instances[i].set_rhs_field(synth.random_field_modes(4000 + i))
+        xs.append(torch.zeros(B.instances[i].ndof, dtype=torch.float64, device=DEV))
+    stats, _ = B.solve(xs, tol=1e-10, max_restarts=60, q=5)
+    for i, (g, e, d) in enumerate(PROBLEMS):
+        rel = B.instances[i].residual(xs[i])
+        s = igamg.Solver(g, e, d, precision=igamg.FP32_IR, stored_stencil=1, tail_items=32,
+                         n_el_coarsest=0)
+        s.set_rhs_field(synth.random_field_modes(4000 + i))
+        x = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+        st, _ = s.solve(x, tol=1e-10, max_restarts=60, method=igamg.RRE, q=5)
+        diff = (torch.linalg.norm(x - xs[i]) / torch.linalg.norm(x)).item()
+        print("[batch] problem %d geom=%d n_el=%d p=%d restarts=%d/%d rel=%.2e diff=%.1e"
+              % (i, g, e, d, stats[i].restarts, st.restarts, rel, diff))
+        assert rel <= 1.0000001e-10
+        assert stats[i].restarts == st.restarts
+        assert diff < 1e-13
+    # true residual by the oracle for two problems
+    for i in (0, 1):
+        g, e, d = PROBLEMS[i]
+        if g == igamg.QUARTER_ANNULUS:
+            A = assemble.mapped_stiffness_2d(e, d)
+            bb = assemble.load_vector_2d(e, d, synth.random_field_modes(4000 + i))
+        else:
+            A = assemble.kron_operator_2d(e, d)
+            bb = assemble.kron_load_2d(e, d, synth.random_field_modes(4000 + i))
+        xv = xs[i].cpu().numpy()
+        assert np.linalg.norm(bb - A @ xv) / np.linalg.norm(bb) <= 1.0000001e-10
+    B.close()
