@@ -65,7 +65,10 @@ typedef struct {
 
 /* Smoothers of Algorithm 2.  MCGS: multicolour Gauss-Seidel with (p+1)^d
  * colours c(I) = sum_d (i_d mod (p+1)) (p+1)^d swept in increasing order;
- * JACOBI: x += omega D^{-1} (b - A x).  LEXGS and LEARNED are reserved. */
+ * LEXGS: lexicographic Gauss-Seidel (x fastest, forward; 2D only, one
+ * workgroup per sweep, for small grids); JACOBI: x += omega D^{-1} (b - A x).
+ * The learned step is switched on separately (igamg_set_learned) and works
+ * with MCGS; LEARNED is reserved. */
 typedef enum {
     IGAMG_SMOOTH_MCGS = 0,
     IGAMG_SMOOTH_LEXGS = 1,
@@ -204,6 +207,14 @@ igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q,
 igamg_status igamg_profile_smoother(igamg_ctx* ctx, int level, int precision, int nsweeps,
                                     double* avg_ms, double* bytes, int* launches);
 
+/* Autotuner: times V-cycles (current precision and smoother) for every
+ * distinct split between multi-block levels and the single-workgroup kernel
+ * (the tail_items option), keeps the fastest, and caches the choice for this
+ * process keyed by (GPU architecture, geometry kind, degree, n_el, precision);
+ * a later igamg_setup with tail_items < 0 takes the cached choice (or 32).
+ * Outputs (may be NULL): the chosen tail_items and its V-cycle time in ms. */
+igamg_status igamg_autotune(igamg_ctx* ctx, int* tail_items, double* vcycle_ms);
+
 /* ---- Learned smoother (2D only) ------------------------------------------
  * Per level l >= 1 a network N_l (3x3 convolutions 1 -> 16 -> 16 -> 1, ReLU,
  * zero padding, no biases; BF16 weights, FP32 accumulation on MFMA) replaces
@@ -266,7 +277,9 @@ igamg_status igamg_smoother_loss_grad(igamg_ctx* ctx, int level, const float* z_
  * per degree group covering all unconverged problems of that degree; the
  * degree groups run as parallel branches of one captured graph per restart
  * cycle; extrapolation and the accuracy test are per problem.  All work is on
- * opt->stream (or a stream the batch creates). */
+ * opt->stream (or a stream the batch creates).  With opt->tail_items < 0 each
+ * problem's multi-block / single-workgroup split comes from the autotuner
+ * (cached per architecture, geometry, degree, grid and precision). */
 typedef struct igamg_batch igamg_batch;
 igamg_status igamg_setup_batch(int count, const igamg_geometry* geoms, const int* degrees,
                                const igamg_options* opt, igamg_batch** out);

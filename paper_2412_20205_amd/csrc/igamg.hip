@@ -14,6 +14,8 @@
 #include <memory>
 #include <string>
 #include <type_traits>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/igamg.h"
@@ -28,6 +30,10 @@ using namespace igamg;
 namespace {
 
 thread_local std::string g_last_error;
+
+// Autotuning cache: key -> tail_items (process-wide).
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
 
 enum OpKind { OP_STENCIL2D = 0, OP_KRON2D = 1, OP_KRON3D = 2 };
 
@@ -225,6 +231,15 @@ struct igamg_ctx {
     void smooth(int l, const T* bb, T* x, int nsweeps) {
         Level& v = lv[l];
         for (int s = 0; s < nsweeps; ++s) {
+            if (opt.smoother == IGAMG_SMOOTH_LEXGS) {
+                with_op<T>(l, [&](auto op) {
+                    using Op = decltype(op);
+                    if constexpr (std::is_same_v<typename Op::Pt, Pt2>)
+                        hipLaunchKernelGGL((k_lexgs_sweep<Op>), dim3(1), dim3(kLexThreads), 0, stream, op, bb, x);
+                });
+                check_launch();
+                continue;
+            }
             if (opt.smoother == IGAMG_SMOOTH_JACOBI) {
                 residual<T, T>(l, bb, x, v.r<T>(), 2, nullptr);
                 copy(v.r<T>(), x, v.N);
@@ -263,8 +278,23 @@ struct igamg_ctx {
         for (int c = 0; c < lv[l].ncol; ++c) mx = std::max(mx, colour_size_host(lv[l].n, p, dim, c));
         return ((mx + 63) / 64) * (2 * p + 1);
     }
+    std::string tune_key() const {
+        hipDeviceProp_t prop;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::string arch = "?";
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+        return arch + "/" + std::to_string(geom) + "/" + std::to_string(p) + "/" +
+               std::to_string(lv[L].n_el) + "/" + std::to_string(opt.precision);
+    }
     void choose_tail() {
         tail_top = 0;
+        if (opt.smoother != IGAMG_SMOOTH_MCGS) return;  // the single-workgroup kernel sweeps colours
+        if (opt.tail_items < 0) {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_tune_cache.find(tune_key());
+            opt.tail_items = (it != g_tune_cache.end()) ? it->second : 32;
+        }
         if (opt.tail_items <= 0) return;
         for (int l = 1; l <= L && l < kTailMaxLevels; ++l) {
             if (colour_items(l) > opt.tail_items) break;
@@ -645,6 +675,8 @@ struct igamg_ctx {
     void train(const igamg_train_options& o, igamg_train_report& rep);
     double measure_rho(int vcycles, bool learned);
 
+    void autotune(int* best_items, double* best_ms);
+
     void setup(const igamg_geometry& g, int degree, int levels);
     void setup_levels(int n_el, int levels);
     void setup_kron();
@@ -884,8 +916,11 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
     }
     if (p < 1 || p > 5 || (dim == 3 && p > 3)) throw Error(IGAMG_EINVAL, "unsupported degree");
     if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu1 + opt.nu2 == 0) throw Error(IGAMG_EINVAL, "bad nu1/nu2");
-    if (opt.smoother != IGAMG_SMOOTH_MCGS && opt.smoother != IGAMG_SMOOTH_JACOBI)
-        throw Error(IGAMG_EINVAL, "smoother not available in this build");
+    if (opt.smoother != IGAMG_SMOOTH_MCGS && opt.smoother != IGAMG_SMOOTH_JACOBI &&
+        opt.smoother != IGAMG_SMOOTH_LEXGS)
+        throw Error(IGAMG_EINVAL, "unknown smoother");
+    if (opt.smoother == IGAMG_SMOOTH_LEXGS && g.kind == IGAMG_UNIT_CUBE)
+        throw Error(IGAMG_EINVAL, "lexicographic Gauss-Seidel is 2D only");
     if (opt.precision != IGAMG_FP64 && opt.precision != IGAMG_FP32_IR)
         throw Error(IGAMG_EINVAL, "bad precision");
     if (opt.stream) {
@@ -975,6 +1010,51 @@ void igamg_ctx::set_rhs_field(const double* modes, int n_modes) {
     }
     release(dmodes);
     set_bnorm(vector_norm(b, f.N));
+}
+
+// ---------------------------------------------------------------------------
+// autotuning of the multi-block / single-workgroup split
+
+void igamg_ctx::autotune(int* best_items, double* best_ms) {
+    const int cand[] = {0, 8, 16, 32, 64, 128, 256, 512};
+    double* x = alloc<double>(lv[L].N);
+    hipEvent_t e0, e1;
+    IGAMG_HIP(hipEventCreate(&e0));
+    IGAMG_HIP(hipEventCreate(&e1));
+    int save_items = opt.tail_items;
+    int best = save_items;
+    double bms = 1e300;
+    int last_top = -1;
+    for (int items : cand) {
+        opt.tail_items = items;
+        choose_tail();
+        if (tail_top == last_top) continue;  // same split as a smaller threshold
+        last_top = tail_top;
+        fill(x, lv[L].N);
+        G(x);  // warm-up
+        IGAMG_HIP(hipEventRecord(e0, stream));
+        for (int k = 0; k < 3; ++k) G(x);
+        IGAMG_HIP(hipEventRecord(e1, stream));
+        IGAMG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        IGAMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / 3.0 < bms) {
+            bms = ms / 3.0;
+            best = items;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    release(x);
+    opt.tail_items = best;
+    choose_tail();
+    graph_method = -1;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[tune_key()] = best;
+    }
+    if (best_items) *best_items = best;
+    if (best_ms) *best_ms = bms;
 }
 
 // ---------------------------------------------------------------------------
@@ -2003,6 +2083,7 @@ igamg_status igamg_setup_batch(int count, const igamg_geometry* geoms, const int
         o.smoother = IGAMG_SMOOTH_MCGS;
         o.stored_stencil = 1;
         if (!opt) o.tail_items = 32;
+        const bool tune = o.tail_items < 0;
         o.n_el_coarsest = 0;
         o.use_graphs = 0;
         for (int i = 0; i < count; ++i) {
@@ -2011,6 +2092,14 @@ igamg_status igamg_setup_batch(int count, const igamg_geometry* geoms, const int
             std::unique_ptr<igamg_ctx> c(new igamg_ctx());
             c->opt = o;
             c->setup(geoms[i], degrees[i], 0);
+            if (tune) {
+                bool cached;
+                {
+                    std::lock_guard<std::mutex> g(g_tune_mu);
+                    cached = g_tune_cache.count(c->tune_key()) > 0;
+                }
+                if (!cached) c->autotune(nullptr, nullptr);
+            }
             B->inst.push_back(c.release());
         }
         for (int g = 0; g < 5; ++g) {
@@ -2092,6 +2181,13 @@ igamg_status igamg_solve_batch(igamg_batch* b, double tol, int max_restarts, int
             stats[i] = st[i];
         }
     return s;
+}
+
+igamg_status igamg_autotune(igamg_ctx* ctx, int* tail_items, double* vcycle_ms) {
+    return guarded([&] {
+        need(ctx, "null argument");
+        ctx->autotune(tail_items, vcycle_ms);
+    });
 }
 
 void igamg_train_options_default(igamg_train_options* o) {

@@ -354,6 +354,62 @@ __global__ void __launch_bounds__(64 * Op::NW) k_residual_sliced(
                             blockIdx.x);
 }
 
+// Lexicographic Gauss-Seidel sweep (x index fastest, forward) in exact
+// lexicographic semantics by one workgroup: point (i, j) only reads updated
+// values of points before it in lexicographic order and within reach p, all of
+// which lie on hyperplanes i + (p+1) j of smaller index, while the points after
+// it lie on larger ones; the points of one hyperplane are therefore updated
+// together, hyperplane after hyperplane.  Each row's slices are spread over
+// the block's waves (2D operators).
+constexpr int kLexThreads = 1024;
+template <class Op>
+__global__ void __launch_bounds__(kLexThreads) k_lexgs_sweep(Op A, const typename Op::T* __restrict__ b,
+                                                             typename Op::T* __restrict__ x) {
+    using T = typename Op::T;
+    constexpr int P = (Op::NW - 1) / 2;
+    constexpr int NW = Op::NW;
+    constexpr int PPB = kLexThreads / 64 / NW;  // 64-point groups per pass
+    __shared__ T part[PPB][NW][64];
+    __shared__ T dg[PPB][64];
+    const int n = A.n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = wave / NW, w = wave % NW;
+    const int tmax = (n - 1) + (P + 1) * (n - 1);
+    for (int t = 0; t <= tmax; ++t) {
+        int j0 = max(0, (t - (n - 1) + P) / (P + 1));
+        int j1 = min(n - 1, t / (P + 1));
+        int cnt = j1 - j0 + 1;
+        for (int base = 0; base < cnt; base += PPB * 64) {
+            int q = base + grp * 64 + lane;
+            bool ok = grp < PPB && q < cnt;
+            Pt2 pt;
+            int c = 0, k = 0;
+            T d = 1, sl = 0;
+            if (ok) {
+                pt.j = j0 + q;
+                pt.i = t - (P + 1) * pt.j;
+                pt.I = pt.i + (long long)n * pt.j;
+                int ci = pt.i % (P + 1), cj = pt.j % (P + 1);
+                c = ci + (P + 1) * cj;
+                k = pt.i / (P + 1) + ((n - ci + P) / (P + 1)) * (pt.j / (P + 1));
+                sl = A.slice(x, pt, c, k, w, d);
+            }
+            if (grp < PPB) {
+                part[grp][w][lane] = sl;
+                if (w == NW / 2) dg[grp][lane] = d;
+            }
+            __syncthreads();
+            if (ok && w == 0) {
+                T acc = 0;
+#pragma unroll
+                for (int v = 0; v < NW; ++v) acc += part[grp][v][lane];
+                x[pt.I] = x[pt.I] + (b[pt.I] - acc) / dg[grp][lane];
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Deterministic final reduction: out[0] = sqrt(sum partial) / denom.
 __global__ void __launch_bounds__(kBlock) k_finalize_norm(const double* __restrict__ partial,
                                                           int np, double denom,

@@ -116,6 +116,7 @@ _SIGNATURES = {
     "igamg_destroy_batch": (None, [_P]),
     "igamg_batch_instance": (_i, [_P, _i, ctypes.POINTER(_P)]),
     "igamg_solve_batch": (_i, [_P, _d, _i, _i, _P, _P]),
+    "igamg_autotune": (_i, [_P, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "igamg_last_error": (ctypes.c_char_p, []),
     "igamg_host_gauss_legendre": (_i, [_i, _P, _P]),
     "igamg_host_basis": (_i, [_i, _i, _d, _P, _P, ctypes.POINTER(_i)]),
@@ -319,6 +320,12 @@ class Solver:
                "igamg_profile_smoother")
         return ms.value, by.value, n.value
 
+    def autotune(self):
+        """(chosen tail_items, V-cycle ms)."""
+        t, ms = _i(), _d()
+        _check(lib().igamg_autotune(self._h, ctypes.byref(t), ctypes.byref(ms)), "igamg_autotune")
+        return t.value, ms.value
+
     # ---- learned smoother
     def train_smoother(self, modes_list, val_modes=None, **kw):
         o = TrainOptions()
@@ -390,8 +397,8 @@ class _Borrowed(Solver):
 class Batch:
     """A batch of independent 2D problems (include/igamg.h, igamg_setup_batch)."""
 
-    def __init__(self, problems, stream=None):
-        """problems: list of (geometry, n_el, degree)."""
+    def __init__(self, problems, stream=None, tail_items=32):
+        """problems: list of (geometry, n_el, degree); tail_items < 0 autotunes."""
         import torch
         if stream is None:
             cs = torch.cuda.current_stream()
@@ -401,6 +408,7 @@ class Batch:
         degs = (ctypes.c_int * n)(*[d for _, _, d in problems])
         o = default_options()
         o.stream = stream
+        o.tail_items = tail_items
         h = _P()
         _check(lib().igamg_setup_batch(n, ctypes.cast(geoms, _P), ctypes.cast(degs, _P),
                                        ctypes.byref(o), ctypes.byref(h)), "igamg_setup_batch")

@@ -58,3 +58,21 @@ def test_batch_equals_standalone_and_converges():
         xv = xs[i].cpu().numpy()
         assert np.linalg.norm(bb - A @ xv) / np.linalg.norm(bb) <= 1.0000001e-10
     B.close()
+
+
+def test_autotune_choice_is_cached_and_used():
+    s = igamg.Solver(igamg.QUARTER_ANNULUS, 128, 4)
+    items, ms = s.autotune()
+    print("[autotune] annulus 128 p=4 -> tail_items=%d (%.3f ms per V-cycle)" % (items, ms))
+    assert items in (0, 8, 16, 32, 64, 128, 256, 512) and ms > 0
+    t = igamg.Solver(igamg.QUARTER_ANNULUS, 128, 4, tail_items=-1)
+    assert t.options.tail_items == -1  # resolved inside the library
+    modes = synth.random_field_modes(77)
+    for solver in (s, t):
+        solver.set_rhs_field(modes)
+    xa = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+    xb = torch.zeros(t.ndof, dtype=torch.float64, device=DEV)
+    sa, _ = s.solve(xa, tol=1e-10, method=igamg.RRE, q=5)
+    sb, _ = t.solve(xb, tol=1e-10, method=igamg.RRE, q=5)
+    assert sa.vcycles == sb.vcycles
+    assert torch.equal(xa, xb)

@@ -305,3 +305,40 @@ def test_single_level_is_direct_solve():
     xg = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
     s.vcycle(xg)
     assert rel(host(xg), H.coarse_solve(b)) < 1e-12
+
+
+@pytest.mark.parametrize("geom,n_el,p", [("square", 32, 2), ("annulus", 16, 3), ("annulus", 16, 5),
+                                         ("square", 32, 4)])
+def test_lexicographic_sweeps(geom, n_el, p):
+    s, H, _ = case(geom, n_el, p, smoother=igamg.SMOOTH_LEXGS)
+    for l in range(1, len(H.levels)):
+        lev = H.levels[l]
+        bl = synth.random_vector(lev.A.shape[0], 60 + l)
+        x0 = synth.random_vector(lev.A.shape[0], 70 + l)
+        xg = dev(x0)
+        s.smooth(l, dev(bl), xg, 2)
+        xr = mg.smooth(lev, bl, x0.copy(), mg.SMOOTH_LEXGS, 2)
+        assert rel(host(xg), xr) < 1e-13, l
+
+
+@pytest.mark.parametrize("method", [igamg.EXTRAP_NONE, igamg.RRE, igamg.MPE])
+def test_lexicographic_c1_solve(method):
+    """The unit-square workload of 64^2 elements, p = 2, lexicographic V(2,2)."""
+    s, H, b = case("square", 64, 2, smoother=igamg.SMOOTH_LEXGS)
+    N = len(b)
+    A = H.fine.A
+    nb = np.linalg.norm(b)
+    G = lambda x: mg.vcycle(H, b, x, mg.SMOOTH_LEXGS)
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    xr = np.zeros(N)
+    for it in range(4):
+        s.vcycle(xg)
+        xr = G(xr)
+        assert rel(host(xg), xr) < 1e-12, it
+    om = {igamg.EXTRAP_NONE: None, igamg.RRE: ex.RRE, igamg.MPE: ex.MPE}[method]
+    xo, st_r, _ = ex.restarted_solve(G, lambda x: np.linalg.norm(b - A @ x) / nb, np.zeros(N), 5, om,
+                                     tol=1e-10, max_restarts=200)
+    x = torch.zeros(N, dtype=torch.float64, device=DEV)
+    st, _ = s.solve(x, tol=1e-10, max_restarts=200, method=method, q=5)
+    assert st.vcycles == st_r.vcycles
+    assert rel(host(x), xo) < 1e-11
