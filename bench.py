@@ -142,6 +142,61 @@ def batch_measure(igamg, torch, synth, steps, warmup):
             "setup_s": round(setup_s, 2)}
 
 
+def c1_measure(igamg, torch, synth, steps):
+    """Unit square, p = 2, 64^2 elements, f = 2 pi^2 sin(pi x) sin(pi y), FP64:
+    {multicolour, lexicographic} V(2,2) x {plain, RRE(5), MPE(5)}."""
+    out = {}
+    for sm_name, sm in (("mcgs", igamg.SMOOTH_MCGS), ("lexgs", igamg.SMOOTH_LEXGS)):
+        s = igamg.Solver(igamg.UNIT_SQUARE, 64, 2, smoother=sm)
+        s.set_rhs_field(synth.manufactured_sine_modes_2d())
+        for m_name, m in (("plain", igamg.EXTRAP_NONE), ("rre5", igamg.RRE), ("mpe5", igamg.MPE)):
+            ms, st, _ = time_form(s, igamg, torch, m, igamg.FP64, steps, 1)
+            out["%s_%s" % (sm_name, m_name)] = {"ms": round(ms, 3), "vcycles": st.vcycles,
+                                                "restarts": st.restarts,
+                                                "rel_residual": st.rel_residual}
+        s.close()
+    return out
+
+
+def c3_measure(igamg, torch, synth, steps):
+    """Unit cube, p = 3, 128^3 elements, f = 3 pi^2 prod sin(pi x_d), V(2,2)
+    multicolour GS (64 colours): plain FP64 V-cycles, FP64 MPE(4), and MPE(4)
+    around FP32 V-cycles in FP64 refinement."""
+    s = igamg.Solver(igamg.UNIT_CUBE, 128, 3)
+    s.set_rhs_field(synth.manufactured_sine_modes_3d())
+    out = {"ndof": s.ndof}
+    xs = {}
+    for name, m, prec in (("plain_fp64", igamg.EXTRAP_NONE, igamg.FP64), ("mpe4_fp64", igamg.MPE, igamg.FP64),
+                          ("mpe4_ir", igamg.MPE, igamg.FP32_IR)):
+        s.set_precision(prec)
+        x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
+        s.solve(x, tol=TOL, max_restarts=2000, method=m, q=4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            st, _ = s.solve(x, tol=TOL, max_restarts=2000, method=m, q=4)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[name] = {"ms": round(ms, 2), "vcycles": st.vcycles, "rel_residual": st.rel_residual}
+        xs[name] = x.clone()
+    s.close()
+    return out, xs
+
+
+def c3_oracle_error(xs):
+    """Distance of the GPU solutions to the oracle's exact discrete solution
+    (fast diagonalisation of the oracle's own assembly)."""
+    import numpy as np
+
+    import synth
+    from oracle import assemble, fastdiag
+    b = assemble.load_vector_3d(128, 3, synth.manufactured_sine_modes_3d())
+    u = fastdiag.solve_kronecker(128, 3, b, 3)
+    nu = np.linalg.norm(u)
+    return {k: float(np.linalg.norm(v.cpu().numpy() - u) / nu) for k, v in xs.items()}
+
+
 def cpu_baseline(p, gpu_restarts):
     """The FP64 oracle's restarted RRE(5) solve of the same workload (p, 1024^2)."""
     import numpy as np
@@ -179,6 +234,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-c1c3", action="store_true")
     ap.add_argument("--only-batch", action="store_true")
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--tail-items", type=int, default=32,
@@ -278,6 +334,13 @@ def main():
         headline = results[degrees[0]]
         args.headline_degree = degrees[0]
 
+    c1 = c3 = c3x = None
+    if not args.no_c1c3:
+        log("[bench] unit square 64^2 p=2")
+        c1 = c1_measure(igamg, torch, synth, args.steps)
+        log("[bench] unit cube 128^3 p=3")
+        c3, c3x = c3_measure(igamg, torch, synth, max(1, args.steps // 2))
+
     batch = None
     if not args.no_batch:
         log("[bench] batch of 96 problems")
@@ -291,6 +354,9 @@ def main():
         xc = xsol[(args.headline_degree, "chosen")].cpu().numpy()
         cpu["gpu_fp64_rre_vs_oracle"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
         cpu["gpu_chosen_vs_oracle"] = float(np.linalg.norm(xc - xo) / np.linalg.norm(xo))
+        if c3x is not None:
+            log("[bench] cube: oracle exact discrete solution")
+            c3["error_vs_oracle_exact"] = c3_oracle_error(c3x)
 
     hp = args.headline_degree
     line = {
@@ -318,7 +384,9 @@ def main():
                    "smoother_fp64_gbs": headline["smoother_fp64"]["achieved"],
                    "smoother_fp32_gbs": headline["smoother_fp32"]["achieved"],
                    "per_degree": {str(k): v for k, v in results.items()},
-                   "batch": batch},
+                   "batch": batch,
+                   "unit_square_64_p2": c1,
+                   "unit_cube_128_p3": c3},
         "roofline": headline["smoother_fp32"],
         "cpu_baseline": cpu,
     }

@@ -84,17 +84,15 @@ def test_annulus_jacobian_bounds():
     assert abs(det.min() - 1.5) < 1e-12 and abs(det.max() - 4.0) < 1e-12
 
 
-def test_fast_diagonalisation_equals_sparse_solve():
-    """A^{-1} = (V (x) V)(Lambda (+) Lambda)^{-1}(V (x) V)^T from K1 V = M1 V Lambda."""
-    import scipy.linalg as sla
-    n_el, p = 12, 3
-    K, M = bspline.stiffness_mass_1d(n_el, p)
-    lam, V = sla.eigh(K, M)
-    b = synth.random_vector((n_el + p - 2) ** 2, 3)
-    Bm = b.reshape(n_el + p - 2, -1)
-    U = V @ ((V.T @ Bm @ V) / (lam[:, None] + lam[None, :])) @ V.T
-    x = spla.spsolve(assemble.kron_operator_2d(n_el, p).tocsc(), b)
-    np.testing.assert_allclose(U.reshape(-1), x, rtol=1e-10, atol=1e-12)
+@pytest.mark.parametrize("dim,n_el,p", [(2, 12, 3), (2, 8, 5), (3, 4, 2), (3, 8, 3)])
+def test_fast_diagonalisation_equals_sparse_solve(dim, n_el, p):
+    """A^{-1} = (V (x) V ..)(Lambda (+) Lambda ..)^{-1}(V (x) V ..)^T from K1 V = M1 V Lambda."""
+    from oracle import fastdiag
+    N = (n_el + p - 2) ** dim
+    b = synth.random_vector(N, 3)
+    A = assemble.kron_operator_2d(n_el, p) if dim == 2 else assemble.kron_operator_3d(n_el, p)
+    x = spla.spsolve(A.tocsc(), b)
+    np.testing.assert_allclose(fastdiag.solve_kronecker(n_el, p, b, dim), x, rtol=1e-9, atol=1e-12)
 
 
 @pytest.mark.parametrize("p", [2, 3])
