@@ -62,7 +62,7 @@ struct BTr {
 };
 
 // restriction (dst = R src on the coarse grid, zero <- 0)
-template <typename T>
+template <int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_b_restrict(const BTr<T>* __restrict__ E,
                                                        const int* __restrict__ offs, int ne) {
     int e = bmap_find(offs, ne, blockIdx.x);
@@ -72,20 +72,11 @@ __global__ void __launch_bounds__(kBlock) k_b_restrict(const BTr<T>* __restrict_
     if (C >= (long long)nc * nc) return;
     en.zero[C] = 0;
     int J = (int)(C / nc), I = (int)(C - (long long)J * nc);
-    int si = en.st[I], sj = en.st[J];
-    T acc = 0;
-    for (int b = 0; b < en.W; ++b) {
-        T wj = en.w[(size_t)J * en.W + b];
-        const T* row = en.src + (size_t)min(sj + b, nf - 1) * nf;
-        T s = 0;
-        for (int a = 0; a < en.W; ++a) s = fma(en.w[(size_t)I * en.W + a], row[min(si + a, nf - 1)], s);
-        acc = fma(wj, s, acc);
-    }
-    en.dst[C] = acc;
+    en.dst[C] = transfer2d<P + 2, T>(en.src, nf, en.st, en.w, en.W, nc, I, J);
 }
 
 // prolongation and correction (dst += P src), src coarse, dst fine
-template <typename T>
+template <int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_b_prolong(const BTr<T>* __restrict__ E,
                                                       const int* __restrict__ offs, int ne) {
     int e = bmap_find(offs, ne, blockIdx.x);
@@ -94,16 +85,7 @@ __global__ void __launch_bounds__(kBlock) k_b_prolong(const BTr<T>* __restrict__
     int nc = en.nc, nf = en.nf;
     if (F >= (long long)nf * nf) return;
     int j = (int)(F / nf), i = (int)(F - (long long)j * nf);
-    int si = en.st[i], sj = en.st[j];
-    T acc = 0;
-    for (int b = 0; b < en.W; ++b) {
-        T wj = en.w[(size_t)j * en.W + b];
-        const T* row = en.src + (size_t)min(sj + b, nc - 1) * nc;
-        T s = 0;
-        for (int a = 0; a < en.W; ++a) s = fma(en.w[(size_t)i * en.W + a], row[min(si + a, nc - 1)], s);
-        acc = fma(wj, s, acc);
-    }
-    en.dst[F] += acc;
+    en.dst[F] += transfer2d<P + 2, T>(en.src, nc, en.st, en.w, en.W, nf, i, j);
 }
 
 template <typename T>

@@ -45,6 +45,7 @@ struct Level {
     int ncol = 0, ncp = 0;
     double* coef64 = nullptr;
     float* coef32 = nullptr;
+    float* rec32 = nullptr;  // per-point FP32 records for the prefetching tail (p <= 3)
     double *K64 = nullptr, *M64 = nullptr;
     float *K32 = nullptr, *M32 = nullptr;
     Band1D Kh, Mh;
@@ -136,6 +137,13 @@ struct igamg_ctx {
             throw Error(IGAMG_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
         allocs.push_back(p);
         return (T*)p;
+    }
+    // FP32 iterate vector with kXPad zeros before and after (the FP32 stencil
+    // kernels read stencil rows unclamped); never released before the context.
+    float* alloc_padded32(long long n) {
+        float* base = alloc<float>((size_t)n + 2 * kXPad);
+        fill(base, n + 2 * kXPad);
+        return base + kXPad;
     }
     void release(void* p) {
         if (!p) return;
@@ -264,8 +272,11 @@ struct igamg_ctx {
         Level& f = lv[l];
         Level& c = lv[l - 1];
         if (dim == 2)
-            hipLaunchKernelGGL(k_restrict2d<T>, dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf, f.n,
-                               bc, c.n, f.r_start, f.rw<T>(), f.RW, xc);
+            with_p([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                hipLaunchKernelGGL((k_restrict2d<P, T>), dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf,
+                                   f.n, bc, c.n, f.r_start, f.rw<T>(), f.RW, xc);
+            });
         else
             hipLaunchKernelGGL(k_restrict3d<T>, dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf, f.n,
                                bc, c.n, f.r_start, f.rw<T>(), f.RW, xc);
@@ -296,10 +307,44 @@ struct igamg_ctx {
             opt.tail_items = (it != g_tune_cache.end()) ? it->second : 32;
         }
         if (opt.tail_items <= 0) return;
-        for (int l = 1; l <= L && l < kTailMaxLevels; ++l) {
+        const int limit = (opt.precision == IGAMG_FP64) ? tail_limit<double>() : tail_limit<float>();
+        for (int l = 1; l <= limit; ++l) {
             if (colour_items(l) > opt.tail_items) break;
             tail_top = l;
         }
+    }
+    // Finest level whose iterates, with those of all coarser levels, fit the
+    // single-workgroup kernel's LDS store in precision T.
+    template <typename T>
+    int tail_limit() {
+        long long used = 0;
+        int top = 0;
+        for (int l = 0; l <= L && l < kTailMaxLevels; ++l) {
+            used += tail_level_size<T>(l);
+            if (used > tail_capacity<T>() || !tail_level_ok<T>(l)) break;
+            top = l;
+        }
+        return top;
+    }
+    // LDS values that level l's iterate takes in the single-workgroup kernel:
+    // the padded layout for stored 2D stencils, the natural one otherwise.
+    // The prefetching tail variant (FP32 stored stencils, p <= 3) needs the
+    // records of every level it smooths, which exist where a colour fits the block.
+    template <typename T>
+    bool tail_level_ok(int l) {
+        bool ok = true;
+        with_op<T>(l, [&](auto opl) {
+            if constexpr (tail_prefetch<decltype(opl)>()) ok = (l == 0) || lv[l].rec32 != nullptr;
+        });
+        return ok;
+    }
+    template <typename T>
+    long long tail_level_size(int l) {
+        long long sz = lv[l].N;
+        with_op<T>(l, [&](auto opl) {
+            if constexpr (decltype(opl)::kColourOrder) sz = tl_size(p, tl_vw(sizeof(T)), lv[l].n);
+        });
+        return sz;
     }
 
     // Arguments of the single-workgroup V-cycle on levels 0..tail_top.
@@ -312,14 +357,23 @@ struct igamg_ctx {
         a.nu2 = opt.nu2;
         a.n0 = n0;
         a.Ainv = Ainv0;
+        long long off = 0;
         for (int l = 0; l <= tail_top; ++l) {
             with_op<T>(l, [&](auto opl) {
                 if constexpr (std::is_same_v<decltype(opl), Op>) a.op[l] = opl;
             });
             a.N[l] = lv[l].N;
+            a.xoff[l] = (int)off;  // a multiple of the vector width in both layouts used
+            off += tail_level_size<T>(l);
+            if constexpr (Op::kColourOrder) {
+                if (l >= 1 && (lv[l].RW > p + 2 || lv[l].PW > p + 2))
+                    throw Error(IGAMG_EINVAL, "transfer window wider than p + 2");
+            }
             a.x[l] = (l == tail_top) ? xt : lv[l].x<T>();
             a.b[l] = (l == tail_top) ? (T*)bt : lv[l].b<T>();
             a.r[l] = lv[l].r<T>();
+            if constexpr (std::is_same_v<T, float>) a.rec[l] = lv[l].rec32;
+            if (!tail_level_ok<T>(l)) throw Error(IGAMG_EINVAL, "tail level without coefficient records");
             if (l >= 1) {
                 a.rs[l] = lv[l].r_start;
                 a.rw[l] = lv[l].rw<T>();
@@ -329,6 +383,8 @@ struct igamg_ctx {
                 a.PW[l] = lv[l].PW;
             }
         }
+        if (tail_top >= kTailMaxLevels || off > tail_capacity<T>())
+            throw Error(IGAMG_EINVAL, "levels 0..tail_top do not fit the single-workgroup kernel");
         return a;
     }
 
@@ -337,30 +393,8 @@ struct igamg_ctx {
     void tail(const T* bt, T* xt) {
         with_op<T>(0, [&](auto op0) {
             using Op = decltype(op0);
-            TailArgs<Op> a{};
-            a.top = tail_top;
-            a.nu1 = opt.nu1;
-            a.nu2 = opt.nu2;
-            a.n0 = n0;
-            a.Ainv = Ainv0;
-            for (int l = 0; l <= tail_top; ++l) {
-                with_op<T>(l, [&](auto opl) {
-                    if constexpr (std::is_same_v<decltype(opl), Op>) a.op[l] = opl;
-                });
-                a.N[l] = lv[l].N;
-                a.x[l] = (l == tail_top) ? xt : lv[l].x<T>();
-                a.b[l] = (l == tail_top) ? (T*)bt : lv[l].b<T>();
-                a.r[l] = lv[l].r<T>();
-                if (l >= 1) {
-                    a.rs[l] = lv[l].r_start;
-                    a.rw[l] = lv[l].rw<T>();
-                    a.ps[l] = lv[l].p_start;
-                    a.pw[l] = lv[l].pw<T>();
-                    a.RW[l] = lv[l].RW;
-                    a.PW[l] = lv[l].PW;
-                }
-            }
-            hipLaunchKernelGGL((k_vcycle_tail<Op>), dim3(1), dim3(kTailThreads), 0, stream, a);
+            TailArgs<Op> a = tail_args<Op>(bt, xt);
+            hipLaunchKernelGGL((k_vcycle_tail<Op>), dim3(1), dim3(tail_threads<Op>()), 0, stream, a);
         });
         check_launch();
     }
@@ -369,8 +403,11 @@ struct igamg_ctx {
         Level& f = lv[l];
         Level& c = lv[l - 1];
         if (dim == 2)
-            hipLaunchKernelGGL(k_prolong2d<T>, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, ec, c.n,
-                               xf, f.n, f.p_start, f.pw<T>(), f.PW);
+            with_p([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                hipLaunchKernelGGL((k_prolong2d<P, T>), dim3(grid_for(f.N)), dim3(kBlock), 0, stream, ec,
+                                   c.n, xf, f.n, f.p_start, f.pw<T>(), f.PW);
+            });
         else
             hipLaunchKernelGGL(k_prolong3d<T>, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, ec, c.n,
                                xf, f.n, f.p_start, f.pw<T>(), f.PW);
@@ -417,7 +454,7 @@ struct igamg_ctx {
             coarse<T>(bt, xt);
             return;
         }
-        const int tt = std::min(tail_top, top);
+        const int tt = std::min({tail_top, top, tail_limit<T>()});
         for (int l = top; l > tt; --l) {
             const T* bl = (l == top) ? bt : lv[l].b<T>();
             T* xl = (l == top) ? xt : lv[l].x<T>();
@@ -683,6 +720,7 @@ struct igamg_ctx {
     void setup_annulus();
     void setup_coarse();
     void setup_kron_stencils();
+    void setup_records();
     void set_rhs_field(const double* modes, int n_modes);
 };
 
@@ -738,6 +776,9 @@ void igamg_ctx::setup_levels(int n_el, int levels) {
         Level& v = lv[l];
         v.RW = T.RW;
         v.PW = T.PW;
+        // the transfer kernels unroll their windows to p + 2 (the width of a
+        // refined B-spline's knot-insertion mask)
+        if (v.RW > p + 2 || v.PW > p + 2) throw Error(IGAMG_EINVAL, "transfer window wider than p + 2");
         v.r_start = upload(T.r_start);
         v.p_start = upload(T.p_start);
         v.r_w64 = upload(T.r_w);
@@ -877,6 +918,26 @@ void igamg_ctx::setup_coarse() {
     Ainv0 = upload(inverse_from_cholesky(A, n0));
 }
 
+// Per-point FP32 coefficient records of the levels whose colours fit the
+// prefetching single-workgroup kernel's block.
+void igamg_ctx::setup_records() {
+    for (int l = 1; l <= L; ++l) {
+        Level& v = lv[l];
+        int mx = 0;
+        for (int c = 0; c < v.ncol; ++c) mx = std::max(mx, colour_size_host(v.n, p, dim, c));
+        if (mx > kTailPfThreads) continue;
+        const long long cnt = (long long)v.ncol * v.ncp * rec_len(p);
+        v.rec32 = alloc<float>(cnt);
+        with_p([&](auto PC) {
+            constexpr int P = decltype(PC)::value;
+            if constexpr (P <= 3)
+                hipLaunchKernelGGL(k_to_records<P>, dim3(grid_for(cnt)), dim3(kBlock), 0, stream,
+                                   (const float*)v.coef32, v.ncp, v.ncol, v.rec32);
+        });
+        check_launch();
+    }
+}
+
 // Unit square with stored stencils: every level's (2p+1)^2 rows written out
 // from its Kronecker factors (the same operator, one operator type for all 2D
 // problems of a batch).
@@ -938,17 +999,17 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
         setup_coarse();
         if (kind == OP_STENCIL2D) setup_kron_stencils();
     }
+    if (kind == OP_STENCIL2D && p <= 3) setup_records();
     for (int l = 0; l <= L; ++l) {
         Level& v = lv[l];
         v.x64 = alloc<double>(v.N);
         v.b64 = alloc<double>(v.N);
         v.r64 = alloc<double>(v.N);
-        v.x32 = alloc<float>(v.N);
+        v.x32 = alloc_padded32(v.N);
         v.b32 = alloc<float>(v.N);
         v.r32 = alloc<float>(v.N);
         fill(v.x64, v.N);
         fill(v.b64, v.N);
-        fill(v.x32, v.N);
         fill(v.b32, v.N);
     }
     choose_tail();
@@ -1552,7 +1613,7 @@ struct igamg_batch {
             auto tR = up(R);
             auto tT = up(T);
             BLAUNCH((k_b_res<Op32, float>), dim3(rt), dim3(64 * Op32::NW), 0, st, tR, ro, (int)R.size());
-            BLAUNCH(k_b_restrict<float>, dim3(tt), dim3(kBlock), 0, st, tT, to, (int)T.size());
+            BLAUNCH((k_b_restrict<Op32::kP, float>), dim3(tt), dim3(kBlock), 0, st, tT, to, (int)T.size());
         }
         {
             // every problem's small levels (and its coarsest solve): one workgroup each
@@ -1563,7 +1624,7 @@ struct igamg_batch {
                 TA.push_back(c->tail_args<Op32>(c->lv[t].b32, c->lv[t].x32));
             }
             auto tTA = up(TA);
-            BLAUNCH((k_b_tail<Op32>), dim3(ne), dim3(kTailThreads), 0, st, tTA);
+            BLAUNCH((k_b_tail<Op32>), dim3(ne), dim3(tail_threads<Op32>()), 0, st, tTA);
         }
         for (int d = D - 1; d >= 0; --d) {
             std::vector<BTr<float>> T;
@@ -1581,7 +1642,7 @@ struct igamg_batch {
             int tt;
             const int* to = offsets(tc, tt);
             auto tb_T_6 = up(T);
-            BLAUNCH(k_b_prolong<float>, dim3(tt), dim3(kBlock), 0, st, tb_T_6, to, (int)T.size());
+            BLAUNCH((k_b_prolong<Op32::kP, float>), dim3(tt), dim3(kBlock), 0, st, tb_T_6, to, (int)T.size());
             launch_sweeps(d, inst[mem[0]]->opt.nu2);
         }
         // W += x32
@@ -1815,6 +1876,7 @@ igamg_status igamg_set_precision(igamg_ctx* ctx, int precision) {
         need(precision == IGAMG_FP64 || precision == IGAMG_FP32_IR, "bad precision");
         if (precision != ctx->opt.precision) {
             ctx->opt.precision = precision;
+            ctx->choose_tail();      // the LDS store holds more FP32 levels
             ctx->graph_method = -1;  // recapture the restart cycle
         }
     });

@@ -41,6 +41,18 @@ __device__ __forceinline__ T stream_load(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
+// Pointers that kernels read from memory (argument tables of batched launches)
+// are generic; these casts state that they address global memory, so that the
+// loads are global (vmcnt) rather than flat (which an LDS wait also waits for).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -60,6 +72,32 @@ __device__ inline double block_sum(double v, double* red) {
     return s;
 }
 
+// Zero values kept before and after every FP32 iterate vector (at least p).
+constexpr int kXPad = 64;
+
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+
+// W consecutive floats from a 4-byte aligned address with 16/8/4-byte loads.
+template <int W>
+__device__ __forceinline__ void load_window(const float* p, float (&v)[W]) {
+#pragma unroll
+    for (int m = 0; m + 4 <= W; m += 4) {
+        const f4u q = *reinterpret_cast<const f4u*>(p + m);
+        v[m] = q[0];
+        v[m + 1] = q[1];
+        v[m + 2] = q[2];
+        v[m + 3] = q[3];
+    }
+    constexpr int m = W - W % 4;
+    if constexpr (W % 4 >= 2) {
+        const f2u q = *reinterpret_cast<const f2u*>(p + m);
+        v[m] = q[0];
+        v[m + 1] = q[1];
+    }
+    if constexpr (W % 2 == 1) v[W - 1] = p[W - 1];
+}
+
 // ---------------------------------------------------------------------------
 // operators
 
@@ -76,7 +114,7 @@ template <int P, typename T_>
 struct Stencil2D {
     using T = T_;
     using Pt = Pt2;
-    static constexpr int W = 2 * P + 1, S = W * W, NC = (P + 1) * (P + 1);
+    static constexpr int kP = P, W = 2 * P + 1, S = W * W, NC = (P + 1) * (P + 1);
     static constexpr bool kColourOrder = true;
     const T* __restrict__ coef;
     int n;
@@ -100,6 +138,13 @@ struct Stencil2D {
     static constexpr int NW = W;  // one slice per stencil row
     // Partial row product over stencil row bb = w - P (coefficients streamed
     // once, coalesced across the 64 points of the wave); diag set by w == P.
+    // kStream: non-temporal coefficient loads (a pass that reads them once);
+    // the single-workgroup cycle re-reads them and keeps them cached.
+    // FP32 iterates are the library's own vectors, allocated with kXPad zero
+    // values before and after: a stencil row's W values are then read from
+    // column i - p with vector loads, unclamped (entries outside the row meet
+    // zero coefficients).  FP64 iterates may be the caller's: clamped reads.
+    template <bool kStream = true>
     __device__ __forceinline__ T slice(const T* __restrict__ x, const Pt& pt, int c, int k, int w,
                                        T& diag) const {
         const int bb = w - P;
@@ -107,9 +152,12 @@ struct Stencil2D {
         const T* xr = x + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
         T cv[W], xv[W];
 #pragma unroll
-        for (int a = 0; a < W; ++a) cv[a] = stream_load(cf + (size_t)a * ncp);
+        for (int a = 0; a < W; ++a) cv[a] = kStream ? stream_load(cf + (size_t)a * ncp) : cf[(size_t)a * ncp];
+        if constexpr (std::is_same<T, float>::value)
+            load_window<W>(xr + pt.i - P, xv);
+        else
 #pragma unroll
-        for (int a = 0; a < W; ++a) xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
+            for (int a = 0; a < W; ++a) xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
         T acc = 0;
 #pragma unroll
         for (int a = 0; a < W; ++a) acc = fma(cv[a], xv[a], acc);
@@ -152,6 +200,7 @@ struct Kron2D {
     }
     static constexpr int NW = W;
     // Row bb = w - P of the sum-factorised product: M_jb (K_i . x_row) + K_jb (M_i . x_row).
+    template <bool kStream = true>
     __device__ __forceinline__ T slice(const T* __restrict__ x, const Pt& pt, int, int, int w,
                                        T& diag) const {
         const int bb = w - P;
@@ -215,6 +264,7 @@ struct Kron3D {
     }
     static constexpr int NW = W;
     // Plane cc = w - P: M_kc (sum_b M_jb Kx + K_jb Mx) + K_kc (sum_b M_jb Mx).
+    template <bool kStream = true>
     __device__ __forceinline__ T slice(const T* __restrict__ x, const Pt& pt, int, int, int w,
                                        T& diag) const {
         const int cc = w - P;
@@ -272,6 +322,13 @@ __device__ __forceinline__ void gs_colour_body(const Op& A, const typename Op::T
     int k = blk * 64 + lane;
     typename Op::Pt pt;
     bool ok = A.point(c, k, pt);
+    // the finishing wave loads x_I and b_I together with its slice (no other
+    // thread writes them in this pass), keeping one memory latency per pass
+    T xo = 0, bo = 0;
+    if (w == 0 && ok) {
+        xo = x[pt.I];
+        bo = b[pt.I];
+    }
     T d = 1, sl = 0;
     if (ok) sl = A.slice(x, pt, c, k, w, d);
     part[w][lane] = sl;
@@ -281,7 +338,7 @@ __device__ __forceinline__ void gs_colour_body(const Op& A, const typename Op::T
         T acc = 0;
 #pragma unroll
         for (int v = 0; v < Op::NW; ++v) acc += part[v][lane];
-        x[pt.I] = x[pt.I] + (b[pt.I] - acc) / dg[lane];
+        x[pt.I] = xo + (bo - acc) / dg[lane];
     }
 }
 
@@ -315,6 +372,11 @@ __device__ __forceinline__ void residual_body(const Op& A, const typename Op::T*
         long long I = (long long)blk * 64 + lane;
         ok = (I < N) && A.point_nat(I, pt);
     }
+    T xo = 0, bo = 0;  // loaded with the slices, as in the colour pass
+    if (w == 0 && ok) {
+        if (mode != 1) bo = b[pt.I];
+        if (mode == 2) xo = x[pt.I];
+    }
     T d = 1, sl = 0;
     if (ok) sl = A.slice(x, pt, c, k, w, d);
     part[w][lane] = sl;
@@ -327,11 +389,11 @@ __device__ __forceinline__ void residual_body(const Op& A, const typename Op::T*
         for (int v = 0; v < Op::NW; ++v) acc += part[v][lane];
         T v;
         if (mode == 0)
-            v = b[pt.I] - acc;
+            v = bo - acc;
         else if (mode == 1)
             v = acc;
         else
-            v = x[pt.I] + (T)omega * (b[pt.I] - acc) / dg[lane];
+            v = xo + (T)omega * (bo - acc) / dg[lane];
         out[pt.I] = (Tout)v;
         sq = (double)v * (double)v;
     }
@@ -468,7 +530,37 @@ __global__ void __launch_bounds__(kBlock) k_add_f32_to_f64(const float* __restri
 
 // bc = R rf on the coarse grid; xc (if given) is zeroed: the coarse-grid
 // correction of Algorithm 2 starts from a zero error.
-template <typename T>
+// One value of a separable 2D transfer: sum_b w_j[b] sum_a w_i[a] g(sj+b, si+a)
+// over the windows of a 1D table (start st[], weights w[idx*W + a], nw rows),
+// on an n x n row-major grid, indices clamped to the grid.  The windows are
+// unrolled to their bound M (entries a >= W weigh zero), so all loads of a
+// point are in flight together.
+template <int M, typename T>
+__device__ __forceinline__ T transfer2d(const T* __restrict__ g, int n, const int* __restrict__ st,
+                                        const T* __restrict__ w, int W, int nw, int i, int j) {
+    const int si = st[i], sj = st[j];
+    const int last = nw * W - 1;
+    T wi[M], wj[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        const T u = w[min(i * W + a, last)], v = w[min(j * W + a, last)];
+        wi[a] = (a < W) ? u : (T)0;
+        wj[a] = (a < W) ? v : (T)0;
+    }
+    T acc = 0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+        const T* row = g + (size_t)min(sj + b, n - 1) * n;
+        T s = 0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) s = fma(wi[a], row[min(si + a, n - 1)], s);
+        acc = fma(wj[b], s, acc);
+    }
+    return acc;
+}
+
+// bc = R rf (R = P^T; window bound p + 2) and, optionally, xc = 0.
+template <int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict2d(const T* __restrict__ rf, int nf,
                                                        T* __restrict__ bc, int nc,
                                                        const int* __restrict__ rs,
@@ -478,19 +570,11 @@ __global__ void __launch_bounds__(kBlock) k_restrict2d(const T* __restrict__ rf,
     if (C >= (long long)nc * nc) return;
     if (xc) xc[C] = 0;
     int J = (int)(C / nc), I = (int)(C - (long long)J * nc);
-    int si = rs[I], sj = rs[J];
-    T acc = 0;
-    for (int b = 0; b < RW; ++b) {
-        T wj = rw[(size_t)J * RW + b];
-        const T* row = rf + (size_t)min(sj + b, nf - 1) * nf;
-        T s = 0;
-        for (int a = 0; a < RW; ++a) s = fma(rw[(size_t)I * RW + a], row[min(si + a, nf - 1)], s);
-        acc = fma(wj, s, acc);
-    }
-    bc[C] = acc;
+    bc[C] = transfer2d<P + 2, T>(rf, nf, rs, rw, RW, nc, I, J);
 }
 
-template <typename T>
+// xf += P ec (window bound p + 2).
+template <int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong2d(const T* __restrict__ ec, int nc,
                                                       T* __restrict__ xf, int nf,
                                                       const int* __restrict__ ps,
@@ -498,16 +582,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong2d(const T* __restrict__ ec, 
     long long F = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (F >= (long long)nf * nf) return;
     int j = (int)(F / nf), i = (int)(F - (long long)j * nf);
-    int si = ps[i], sj = ps[j];
-    T acc = 0;
-    for (int b = 0; b < PW; ++b) {
-        T wj = pw[(size_t)j * PW + b];
-        const T* row = ec + (size_t)min(sj + b, nc - 1) * nc;
-        T s = 0;
-        for (int a = 0; a < PW; ++a) s = fma(pw[(size_t)i * PW + a], row[min(si + a, nc - 1)], s);
-        acc = fma(wj, s, acc);
-    }
-    xf[F] += acc;
+    xf[F] += transfer2d<P + 2, T>(ec, nc, ps, pw, PW, nf, i, j);
 }
 
 template <typename T>
@@ -785,13 +860,54 @@ __global__ void __launch_bounds__(kBlock) k_extrap_combine(IterPtrs S, int q, lo
 
 
 // ---------------------------------------------------------------------------
-// single-workgroup V-cycle on the small levels 0..top (one launch replaces the
-// hundreds of tiny launches those levels would need; colour passes are
-// separated by workgroup barriers and the data stay in L2)
+// single-workgroup V-cycle on the small levels 0..top.  One launch replaces the
+// hundreds of tiny launches those levels would need.  The iterates of all
+// levels 0..top stay in LDS for the whole cycle, so a colour pass reads the
+// neighbours of its points from LDS and only the read-only coefficients, b and
+// r go to memory; passes are separated by workgroup barriers.
 
 constexpr int kTailMaxLevels = 8;
 constexpr int kTailThreads = 1024;
-constexpr int kTailMaxChunks = 8;  // 64-point chunks held in LDS at once
+constexpr int kTailPfThreads = 512;  // prefetching variant: 256 VGPRs per thread
+
+// FP32 stored stencils up to p = 3 take the prefetching variant: the
+// coefficients of a point are one 16-byte aligned record and the next colour
+// step's records are in flight while the current step computes.
+template <class Op>
+constexpr bool tail_prefetch() {
+    if constexpr (Op::kColourOrder) return std::is_same<typename Op::T, float>::value && Op::kP <= 3;
+    else return false;
+}
+template <class Op>
+constexpr int tail_threads() {
+    return tail_prefetch<Op>() ? kTailPfThreads : kTailThreads;
+}
+// Floats per coefficient record of degree p: (2p+1)^2 rounded up to 4.
+__host__ __device__ constexpr int rec_len(int p) { return ((2 * p + 1) * (2 * p + 1) + 3) / 4 * 4; }
+constexpr int kTailLdsX = 153600;    // LDS bytes for the iterates of levels 0..top
+
+// Padded LDS layout of a level's iterate for stored 2D stencils: rows
+// j = -p .. n-1+p and, per row, a left pad of padl >= p columns (a multiple of
+// the 128-bit vector width vw, so rows stay 16-byte aligned) and a right pad
+// wide enough that the nv aligned vector reads covering a stencil row never
+// leave the row.  Pads hold zeros (the coefficients of out-of-domain
+// neighbours are zero as well), so no index is clamped.
+__host__ __device__ constexpr int tl_vw(int bytes) { return 16 / bytes; }
+__host__ __device__ constexpr int tl_padl(int p, int vw) { return ((p + vw - 1) / vw) * vw; }
+__host__ __device__ constexpr int tl_nv(int p, int vw) { return (vw - 1 + 2 * p + 1 + vw - 1) / vw; }
+__host__ __device__ constexpr int tl_stride(int p, int vw, int n) {
+    return ((tl_padl(p, vw) + n + tl_nv(p, vw) * vw + vw - 1) / vw) * vw;
+}
+__host__ __device__ constexpr long long tl_size(int p, int vw, int n) {
+    return (long long)(n + 2 * p) * tl_stride(p, vw, n);
+}
+
+
+// Unknowns of levels 0..top that fit the LDS iterate store in precision T.
+template <typename T>
+constexpr long long tail_capacity() {
+    return kTailLdsX / (long long)sizeof(T);
+}
 
 template <class Op>
 struct TailArgs {
@@ -802,9 +918,11 @@ struct TailArgs {
     const double* Ainv;             // coarsest inverse (FP64)
     Op op[kTailMaxLevels];
     long long N[kTailMaxLevels];
-    T* x[kTailMaxLevels];
+    int xoff[kTailMaxLevels];       // offset of level l's iterate in the LDS store
+    T* x[kTailMaxLevels];           // only x[top] is read and written (in and out)
     T* b[kTailMaxLevels];
     T* r[kTailMaxLevels];
+    const T* rec[kTailMaxLevels];   // per-point coefficient records (prefetching variant)
     const int* rs[kTailMaxLevels];  // transfer tables between l-1 and l
     const T* rw[kTailMaxLevels];
     const int* ps[kTailMaxLevels];
@@ -812,45 +930,60 @@ struct TailArgs {
     int RW[kTailMaxLevels], PW[kTailMaxLevels];
 };
 
-// One colour pass (mode 0) or residual of colour c (mode 1, into r) by the
-// whole block, sliced as in the multi-block kernels.
+// (A x)_I for one point as the sum, in slice order, of the NW stencil slices
+// (the same slices and the same summation order as the multi-block kernels).
+// A thread owns the whole point; the coefficient loads of G slices are in
+// flight at once, G bounded so that they take at most 64 VGPRs.
 template <class Op>
-__device__ void tail_colour(const Op& A, const typename Op::T* b, typename Op::T* x,
-                            typename Op::T* r, int c, int mode, typename Op::T* part,
-                            typename Op::T* dg) {
+__device__ __forceinline__ typename Op::T tail_row(const Op& A, const typename Op::T* x,
+                                                   const typename Op::Pt& pt, int c, int k,
+                                                   typename Op::T& diag) {
     using T = typename Op::T;
     constexpr int NW = Op::NW;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kTailThreads / 64;
-    const int cs = A.colour_size(c);
-    for (int ch0 = 0; ch0 * 64 < cs; ch0 += kTailMaxChunks) {
-        int nch = min(kTailMaxChunks, (cs + 63) / 64 - ch0);
-        for (int it = wave; it < nch * NW; it += nwave) {
-            int ch = it / NW, w = it - ch * NW;
-            int k = (ch0 + ch) * 64 + lane;
-            typename Op::Pt pt;
-            T d = 1, sl = 0;
-            if (A.point(c, k, pt)) sl = A.slice(x, pt, c, k, w, d);
-            part[(ch * NW + w) * 64 + lane] = sl;
-            if (w == NW / 2) dg[ch * 64 + lane] = d;
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < nch * 64; t += kTailThreads) {
-            int ch = t >> 6, ln = t & 63;
-            int k = (ch0 + ch) * 64 + ln;
-            typename Op::Pt pt;
-            if (!A.point(c, k, pt)) continue;
-            T acc = 0;
+    constexpr int VR = (int)sizeof(T) / 4;
+    constexpr int G0 = 64 / (Op::W * VR);
+    // sum-factorised slices re-read the small 1D bands: one at a time
+    constexpr int G = !Op::kColourOrder ? 1 : (G0 < 1 ? 1 : (G0 > NW ? NW : G0));
+    T acc = 0;
+#pragma unroll 1
+    for (int w0 = 0; w0 < NW; w0 += G) {
 #pragma unroll
-            for (int v = 0; v < NW; ++v) acc += part[(ch * NW + v) * 64 + ln];
-            if (mode == 0)
-                x[pt.I] = x[pt.I] + (b[pt.I] - acc) / dg[t];
-            else
-                r[pt.I] = b[pt.I] - acc;
+        for (int g = 0; g < G; ++g) {
+            const int w = w0 + g;
+            if (w < NW) acc += A.template slice<false>(x, pt, c, k, w, diag);
         }
-        __syncthreads();
     }
+    return acc;
 }
 
+// Passes over the points of colours c0..c1-1 of one level by the whole block,
+// one thread per point.  mode 0: Gauss-Seidel colours in turn,
+// x_I += (b_I - (A x)_I) / A_II, a barrier after each colour.  mode 1:
+// r = b - A x on every point of the colours (x unchanged, one barrier at the
+// end).  x lives in LDS; b, r and the coefficients in memory.
+template <class Op>
+__device__ void tail_pass(const Op& A, const typename Op::T* __restrict__ b, typename Op::T* x,
+                          typename Op::T* __restrict__ r, int c0, int c1, int mode) {
+    using T = typename Op::T;
+    for (int c = c0; c < c1; ++c) {
+        const int cs = A.colour_size(c);
+        for (int k = threadIdx.x; k < cs; k += kTailThreads) {
+            typename Op::Pt pt;
+            A.point(c, k, pt);
+            const T bv = b[pt.I];
+            T d = 1;
+            const T acc = tail_row(A, x, pt, c, k, d);
+            if (mode == 0)
+                x[pt.I] = x[pt.I] + (bv - acc) / d;
+            else
+                r[pt.I] = bv - acc;
+        }
+        if (mode == 0) __syncthreads();
+    }
+    if (mode == 1) __syncthreads();
+}
+
+// b_c = R r_f (memory to memory) and x_c = 0 (LDS).
 template <typename T>
 __device__ void tail_restrict(const T* rf, int nf, T* bc, T* xc, int nc, const int* rs,
                               const T* rw, int RW, int dim) {
@@ -876,6 +1009,7 @@ __device__ void tail_restrict(const T* rf, int nf, T* bc, T* xc, int nc, const i
     }
 }
 
+// x_f += P e_c (LDS to LDS).
 template <typename T>
 __device__ void tail_prolong(const T* ec, int nc, T* xf, int nf, const int* ps, const T* pw,
                              int PW, int dim) {
@@ -900,47 +1034,425 @@ __device__ void tail_prolong(const T* ec, int nc, T* xf, int nf, const int* ps, 
     }
 }
 
-// V-cycle (Algorithm 2, mu = 1) on levels 0..top with right-hand side b[top]
-// and iterate x[top] (in place), by one workgroup.
-template <class Op>
-__device__ void vcycle_tail_body(const TailArgs<Op>& a) {
-    using T = typename Op::T;
-    constexpr int NW = Op::NW;
-    constexpr int DIM = std::is_same<typename Op::Pt, Pt3>::value ? 3 : 2;
-    __shared__ T part[kTailMaxChunks * NW * 64];
-    __shared__ T dg[kTailMaxChunks * 64];
-    for (int l = a.top; l >= 1; --l) {
-        const Op& A = a.op[l];
-        for (int s = 0; s < a.nu1; ++s)
-            for (int c = 0; c < Op::NC; ++c) tail_colour(A, a.b[l], a.x[l], a.r[l], c, 0, part, dg);
-        for (int c = 0; c < Op::NC; ++c) tail_colour(A, a.b[l], a.x[l], a.r[l], c, 1, part, dg);
-        tail_restrict(a.r[l], A.n, a.b[l - 1], a.x[l - 1], a.op[l - 1].n, a.rs[l], a.rw[l], a.RW[l], DIM);
-        __syncthreads();
+// ---- stored 2D stencils: padded LDS layout, vector reads of x --------------
+
+// One stencil row's window of x for a point whose aligned window starts at xw:
+// NV vector reads, then the W values from phase S0 (fixed per colour).
+template <int P, typename T, int S0>
+__device__ __forceinline__ void ft_window(const T* xw, T (&xv)[2 * P + 1]) {
+    constexpr int VW = tl_vw(sizeof(T)), NV = tl_nv(P, VW);
+    typedef T vec __attribute__((ext_vector_type(VW)));
+    T win[NV * VW];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        vec v = *reinterpret_cast<const vec*>(xw + m * VW);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) win[m * VW + e] = v[e];
     }
-    for (int r = threadIdx.x; r < a.n0; r += kTailThreads) {
-        double s = 0.0;
-        for (int c = 0; c < a.n0; ++c) s = fma(a.Ainv[(size_t)r * a.n0 + c], (double)a.b[0][c], s);
-        a.x[0][r] = (T)s;
+#pragma unroll
+    for (int a = 0; a < 2 * P + 1; ++a) xv[a] = win[S0 + a];
+}
+
+// Gauss-Seidel colour c (mode 0) or residual of colour c (mode 1) on a level
+// in the padded layout, one thread per point.  S0 >= 0: the window phase of
+// every point of the colour (vector reads); S0 < 0: scalar reads.  The row
+// products and their sum follow Stencil2D::slice and the multi-block kernels.
+template <int P, typename T, int S0>
+__device__ void ft_colour(const Stencil2D<P, T>& A, const T* __restrict__ b, T* xl,
+                          T* __restrict__ r, int c, int mode) {
+    constexpr int W = 2 * P + 1, S = W * W, VW = tl_vw(sizeof(T)), PADL = tl_padl(P, VW);
+    constexpr int VR = (int)sizeof(T) / 4;
+    // rows whose loads are in flight together: coefficients and x window of
+    // a row take (W + nv*vw) values; keep G rows within 96 VGPRs
+    constexpr int G0 = 96 / ((W + tl_nv(P, VW) * VW) * VR);
+    constexpr int G = G0 < 1 ? 1 : (G0 > W ? W : G0);
+    const int n = A.n, RS = tl_stride(P, VW, n);
+    const int ci = c % (P + 1), cj = c / (P + 1);
+    const int ni = (n - ci + P) / (P + 1), nj = (n - cj + P) / (P + 1);
+    const int cs = ni * nj;
+    for (int k = threadIdx.x; k < cs; k += blockDim.x) {
+        const int jj = k / ni, ii = k - jj * ni;
+        const int i = ci + (P + 1) * ii, j = cj + (P + 1) * jj;
+        const long long I = i + (long long)n * j;
+        const T bv = as_global(b)[I];
+        const auto cf = as_global(A.coef + (size_t)c * S * A.ncp + k);
+        const int sc = PADL - P + i;                      // first window column
+        const T* xr = xl + (size_t)j * RS + (S0 >= 0 ? sc - S0 : sc);  // padded row j = stencil row 0
+        T acc = 0, d = 1;
+        // both loops unrolled (w is a constant, no branches); the scheduling
+        // barrier keeps the loads of one group of G rows together
+#pragma unroll
+        for (int w0 = 0; w0 < W; w0 += G) {
+            if (w0 > 0) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int w = w0 + g;
+                if (w < W) {
+                    T cv[W], xv[W];
+#pragma unroll
+                    for (int e = 0; e < W; ++e) cv[e] = cf[(size_t)(w * W + e) * A.ncp];
+                    if constexpr (S0 >= 0) {
+                        ft_window<P, T, S0>(xr + (size_t)w * RS, xv);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < W; ++e) xv[e] = xr[(size_t)w * RS + e];
+                    }
+                    T ra = 0;
+#pragma unroll
+                    for (int e = 0; e < W; ++e) ra = fma(cv[e], xv[e], ra);
+                    if (w == P) d = cv[P];
+                    acc += ra;
+                }
+            }
+        }
+        if (mode == 0) {
+            T* xp = xl + (size_t)(j + P) * RS + PADL + i;
+            *xp = *xp + (bv - acc) / d;
+        } else {
+            as_global(r)[I] = bv - acc;
+        }
+    }
+}
+
+// Phase dispatch: the window phase is a function of the colour alone when the
+// colour stride p+1 is a multiple of the vector width.
+template <int P, typename T, int S0 = 0>
+__device__ __forceinline__ void ft_colour_phase(const Stencil2D<P, T>& A, const T* b, T* xl, T* r,
+                                                int c, int mode, int s0) {
+    constexpr int VW = tl_vw(sizeof(T));
+    if constexpr (S0 < VW - 1) {
+        if (s0 != S0) {
+            ft_colour_phase<P, T, S0 + 1>(A, b, xl, r, c, mode, s0);
+            return;
+        }
+    }
+    ft_colour<P, T, S0>(A, b, xl, r, c, mode);
+}
+
+template <int P, typename T>
+__device__ void ft_pass(const Stencil2D<P, T>& A, const T* __restrict__ b, T* xl,
+                        T* __restrict__ r, int c0, int c1, int mode) {
+    constexpr int VW = tl_vw(sizeof(T)), PADL = tl_padl(P, VW);
+    for (int c = c0; c < c1; ++c) {
+        if constexpr ((P + 1) % VW == 0)
+            ft_colour_phase<P, T>(A, b, xl, r, c, mode, (PADL - P + c % (P + 1)) % VW);
+        else
+            ft_colour<P, T, -1>(A, b, xl, r, c, mode);
+        if (mode == 0) __syncthreads();
+    }
+    if (mode == 1) __syncthreads();
+}
+
+// b_c = R r_f from memory; the windows are unrolled to their bound p + 2.
+template <int P, typename T>
+__device__ void ft_restrict(const T* __restrict__ rf_, int nf, T* __restrict__ bc_, int nc,
+                            const int* __restrict__ rs_, const T* __restrict__ rw_, int RW) {
+    constexpr int RM = P + 2;
+    const auto rf = as_global(rf_);
+    const auto bc = as_global(bc_);
+    const auto rs = as_global(rs_);
+    const auto rw = as_global(rw_);
+    const int last = nc * RW - 1;
+    for (int C = threadIdx.x; C < nc * nc; C += blockDim.x) {
+        const int I = C % nc, J = C / nc;
+        const int i0 = rs[I], j0 = rs[J];
+        T wi[RM], wj[RM];
+#pragma unroll
+        for (int a = 0; a < RM; ++a) {
+            wi[a] = (a < RW) ? rw[min(I * RW + a, last)] : (T)0;
+            wj[a] = (a < RW) ? rw[min(J * RW + a, last)] : (T)0;
+        }
+        T s2 = 0;
+#pragma unroll
+        for (int bq = 0; bq < RM; ++bq) {
+            const auto row = rf + (size_t)min(j0 + bq, nf - 1) * nf;
+            T s1 = 0;
+#pragma unroll
+            for (int a = 0; a < RM; ++a) s1 = fma(wi[a], row[min(i0 + a, nf - 1)], s1);
+            s2 = fma(wj[bq], s1, s2);
+        }
+        bc[C] = s2;
+    }
+}
+
+// x_f += P e_c, both in the padded LDS layout.
+template <int P, typename T>
+__device__ void ft_prolong(const T* ec, int nc, T* xf, int nf, const int* __restrict__ ps_,
+                           const T* __restrict__ pw_, int PW) {
+    const auto ps = as_global(ps_);
+    const auto pw = as_global(pw_);
+    constexpr int PM = P + 2, VW = tl_vw(sizeof(T)), PADL = tl_padl(P, VW);
+    const int RSc = tl_stride(P, VW, nc), RSf = tl_stride(P, VW, nf);
+    const int last = nf * PW - 1;
+    for (int F = threadIdx.x; F < nf * nf; F += blockDim.x) {
+        const int i = F % nf, j = F / nf;
+        const int i0 = ps[i], j0 = ps[j];
+        T wi[PM], wj[PM];
+#pragma unroll
+        for (int a = 0; a < PM; ++a) {
+            wi[a] = (a < PW) ? pw[min(i * PW + a, last)] : (T)0;
+            wj[a] = (a < PW) ? pw[min(j * PW + a, last)] : (T)0;
+        }
+        T s2 = 0;
+#pragma unroll
+        for (int bq = 0; bq < PM; ++bq) {
+            const T* row = ec + (size_t)(min(j0 + bq, nc - 1) + P) * RSc + PADL;
+            T s1 = 0;
+#pragma unroll
+            for (int a = 0; a < PM; ++a) s1 = fma(wi[a], row[min(i0 + a, nc - 1)], s1);
+            s2 = fma(wj[bq], s1, s2);
+        }
+        xf[(size_t)(j + P) * RSf + PADL + i] += s2;
+    }
+}
+
+// Prefetching variant (FP32, p <= 3): records rec[(c*ncp + k)*RL + o],
+// o = w*W + a, RL = rec_len(p); one point per thread and colour.
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <int P, int S0>
+__device__ __forceinline__ void pf_point(const f4v (&cq)[rec_len(P) / 4], const float* xr, int RS,
+                                         float& acc, float& d) {
+    constexpr int W = 2 * P + 1;
+    acc = 0.f;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        float xv[W];
+        ft_window<P, float, S0>(xr + (size_t)w * RS, xv);
+        float ra = 0.f;
+#pragma unroll
+        for (int e = 0; e < W; ++e) ra = fma(cq[(w * W + e) / 4][(w * W + e) % 4], xv[e], ra);
+        acc += ra;
+    }
+    d = cq[(P * W + P) / 4][(P * W + P) % 4];
+}
+
+template <int P, int S0 = 0>
+__device__ __forceinline__ void pf_point_phase(const f4v (&cq)[rec_len(P) / 4], const float* xr, int RS,
+                                               int s0, float& acc, float& d) {
+    if constexpr (S0 < 3) {
+        if (s0 != S0) {
+            pf_point_phase<P, S0 + 1>(cq, xr, RS, s0, acc, d);
+            return;
+        }
+    }
+    pf_point<P, S0>(cq, xr + (S0 - s0), RS, acc, d);
+}
+
+// Records, right-hand side value and position of this thread's point of the
+// colour of step s (has = false when the colour is smaller than the block).
+template <int P>
+__device__ __forceinline__ void pf_fetch(const Stencil2D<P, float>& A, const float* __restrict__ rec,
+                                         const float* __restrict__ b, int s, f4v (&q)[rec_len(P) / 4],
+                                         float& bv, int& i, int& j, bool& has) {
+    constexpr int NC = (P + 1) * (P + 1), RL = rec_len(P);
+    const int n = A.n, k = threadIdx.x;
+    const int c = s % NC, ci = c % (P + 1), cj = c / (P + 1);
+    const int ni = (n - ci + P) / (P + 1), nj = (n - cj + P) / (P + 1);
+    has = k < ni * nj;
+    if (has) {
+        const int jj = k / ni, ii = k - jj * ni;
+        i = ci + (P + 1) * ii;
+        j = cj + (P + 1) * jj;
+        const auto src = as_global(reinterpret_cast<const f4v*>(rec + ((size_t)c * A.ncp + k) * RL));
+#pragma unroll
+        for (int m = 0; m < RL / 4; ++m) q[m] = src[m];
+        bv = as_global(b)[i + (size_t)n * j];
+    }
+}
+
+// Step s of a sequence with its prefetched data: Gauss-Seidel colour
+// (s < ngs, barrier after) or residual colour (barrier after the last step).
+template <int P>
+__device__ __forceinline__ void pf_step(const Stencil2D<P, float>& A, float* xl, float* __restrict__ r,
+                                        int s, int ngs, int total, const f4v (&q)[rec_len(P) / 4],
+                                        float bq, int pi, int pj, bool ok) {
+    constexpr int NC = (P + 1) * (P + 1), PADL = tl_padl(P, 4);
+    const int n = A.n, RS = tl_stride(P, 4, n);
+    if (ok) {
+        const int c = s % NC;
+        const int s0 = (PADL - P + c % (P + 1)) % 4;  // window phase of the colour
+        const int sc = PADL - P + pi;                  // sc - s0 is a multiple of 4
+        float acc, d;
+        pf_point_phase<P>(q, xl + (size_t)pj * RS + sc - s0, RS, s0, acc, d);
+        if (s < ngs) {
+            float* xp = xl + (size_t)(pj + P) * RS + PADL + pi;
+            *xp = *xp + (bq - acc) / d;
+        } else {
+            as_global(r)[pi + (size_t)n * pj] = bq - acc;
+        }
+    }
+    if (s < ngs || s == total - 1) __syncthreads();
+}
+
+// nsw Gauss-Seidel sweeps (a barrier after every colour), then, if resid,
+// r = b - A x over all colours (one barrier at the end).  The records of step
+// s + 1 are loaded before step s computes, into the other of two register
+// sets, and stay in flight across the LDS-only barriers.
+template <int P>
+__device__ void pf_sequence(const Stencil2D<P, float>& A, const float* __restrict__ rec,
+                            const float* __restrict__ b, float* xl, float* __restrict__ r, int nsw,
+                            bool resid) {
+    constexpr int NC = (P + 1) * (P + 1), NQ = rec_len(P) / 4;
+    const int ngs = nsw * NC, total = ngs + (resid ? NC : 0);
+    if (total == 0) return;
+    f4v qa[NQ], qb[NQ];
+    float ba = 0.f, bb = 0.f;
+    int ia = 0, ja = 0, ib = 0, jb = 0;
+    bool oka = false, okb = false;
+    pf_fetch<P>(A, rec, b, 0, qa, ba, ia, ja, oka);
+    for (int s = 0; s < total; s += 2) {
+        if (s + 1 < total) pf_fetch<P>(A, rec, b, s + 1, qb, bb, ib, jb, okb);
+        pf_step<P>(A, xl, r, s, ngs, total, qa, ba, ia, ja, oka);
+        if (s + 1 >= total) break;
+        if (s + 2 < total) pf_fetch<P>(A, rec, b, s + 2, qa, ba, ia, ja, oka);
+        pf_step<P>(A, xl, r, s + 1, ngs, total, qb, bb, ib, jb, okb);
+    }
+}
+
+template <int P, typename T>
+__device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
+    using Op = Stencil2D<P, T>;
+    constexpr int VW = tl_vw(sizeof(T)), PADL = tl_padl(P, VW);
+    __shared__ __align__(16) T xs[tail_capacity<T>()];
+    const int top = a.top;
+    const int used = a.xoff[top] + (int)tl_size(P, VW, a.op[top].n);
+    for (int e = threadIdx.x; e < used; e += blockDim.x) xs[e] = 0;
+    __syncthreads();
+    {
+        const int n = a.op[top].n, RS = tl_stride(P, VW, n);
+        const auto xg = as_global((const T*)a.x[top]);
+        T* xt = xs + a.xoff[top];
+        for (int I = threadIdx.x; I < n * n; I += blockDim.x)
+            xt[(size_t)(I / n + P) * RS + PADL + I % n] = xg[I];
     }
     __syncthreads();
-    for (int l = 1; l <= a.top; ++l) {
+    for (int l = top; l >= 1; --l) {
         const Op& A = a.op[l];
-        tail_prolong(a.x[l - 1], a.op[l - 1].n, a.x[l], A.n, a.ps[l], a.pw[l], a.PW[l], DIM);
+        T* xl = xs + a.xoff[l];
+        if constexpr (tail_prefetch<Op>()) {
+            pf_sequence<P>(A, a.rec[l], a.b[l], xl, a.r[l], a.nu1, true);
+        } else {
+            for (int s = 0; s < a.nu1; ++s) ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 0);
+            ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1);
+        }
+        ft_restrict<P, T>(a.r[l], A.n, a.b[l - 1], a.op[l - 1].n, a.rs[l], a.rw[l], a.RW[l]);
+        __syncthreads();
+    }
+    {
+        const int nc = a.op[0].n, RS = tl_stride(P, VW, nc);
+        T* x0 = xs + a.xoff[0];
+        const auto b0 = as_global((const T*)a.b[0]);
+        const auto Ainv = as_global(a.Ainv);
+        for (int r = threadIdx.x; r < a.n0; r += blockDim.x) {
+            double s = 0.0;
+#pragma unroll 8
+            for (int c = 0; c < a.n0; ++c) s = fma(Ainv[(size_t)r * a.n0 + c], (double)b0[c], s);
+            x0[(size_t)(r / nc + P) * RS + PADL + r % nc] = (T)s;
+        }
+    }
+    __syncthreads();
+    for (int l = 1; l <= top; ++l) {
+        const Op& A = a.op[l];
+        T* xl = xs + a.xoff[l];
+        ft_prolong<P, T>(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l]);
+        __syncthreads();
+        if constexpr (tail_prefetch<Op>())
+            pf_sequence<P>(A, a.rec[l], a.b[l], xl, a.r[l], a.nu2, false);
+        else
+            for (int s = 0; s < a.nu2; ++s) ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 0);
+    }
+    {
+        const int n = a.op[top].n, RS = tl_stride(P, VW, n);
+        const auto xg = as_global(a.x[top]);
+        const T* xt = xs + a.xoff[top];
+        for (int I = threadIdx.x; I < n * n; I += blockDim.x)
+            xg[I] = xt[(size_t)(I / n + P) * RS + PADL + I % n];
+    }
+}
+
+// ---- sum-factorised operators: natural layout ------------------------------
+
+// V-cycle (Algorithm 2, mu = 1) on levels 0..top with right-hand side b[top]
+// and iterate x[top] (in place), by one workgroup.  The host guarantees that
+// the LDS store holds levels 0..top (xoff[top] + size of level top).
+template <class Op>
+__device__ void gt_vcycle(const TailArgs<Op>& a) {
+    using T = typename Op::T;
+    constexpr int DIM = std::is_same<typename Op::Pt, Pt3>::value ? 3 : 2;
+    __shared__ T xs[tail_capacity<T>()];
+    const int top = a.top;
+    {
+        const T* xg = a.x[top];
+        T* xt = xs + a.xoff[top];
+        for (long long i = threadIdx.x; i < a.N[top]; i += kTailThreads) xt[i] = xg[i];
+    }
+    __syncthreads();
+    for (int l = top; l >= 1; --l) {
+        const Op& A = a.op[l];
+        T* xl = xs + a.xoff[l];
+        for (int s = 0; s < a.nu1; ++s)
+            for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0);
+        tail_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1);
+        tail_restrict(a.r[l], A.n, a.b[l - 1], xs + a.xoff[l - 1], a.op[l - 1].n, a.rs[l], a.rw[l],
+                      a.RW[l], DIM);
+        __syncthreads();
+    }
+    {
+        T* x0 = xs + a.xoff[0];
+        const T* b0 = a.b[0];
+        for (int r = threadIdx.x; r < a.n0; r += kTailThreads) {
+            double s = 0.0;
+            for (int c = 0; c < a.n0; ++c) s = fma(a.Ainv[(size_t)r * a.n0 + c], (double)b0[c], s);
+            x0[r] = (T)s;
+        }
+    }
+    __syncthreads();
+    for (int l = 1; l <= top; ++l) {
+        const Op& A = a.op[l];
+        T* xl = xs + a.xoff[l];
+        tail_prolong(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l], DIM);
         __syncthreads();
         for (int s = 0; s < a.nu2; ++s)
-            for (int c = 0; c < Op::NC; ++c) tail_colour(A, a.b[l], a.x[l], a.r[l], c, 0, part, dg);
+            for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0);
+    }
+    {
+        T* xg = a.x[top];
+        const T* xt = xs + a.xoff[top];
+        for (long long i = threadIdx.x; i < a.N[top]; i += kTailThreads) xg[i] = xt[i];
     }
 }
 
 template <class Op>
-__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(TailArgs<Op> a) {
+__device__ __forceinline__ void vcycle_tail_body(const TailArgs<Op>& a) {
+    if constexpr (Op::kColourOrder)
+        ft_vcycle<Op::kP, typename Op::T>(a);
+    else
+        gt_vcycle(a);
+}
+
+template <class Op>
+__global__ void __launch_bounds__(tail_threads<Op>()) k_vcycle_tail(TailArgs<Op> a) {
     vcycle_tail_body(a);
 }
 
 // Batched: workgroup e runs problem e's small-level V-cycle.
 template <class Op>
-__global__ void __launch_bounds__(kTailThreads) k_b_tail(const TailArgs<Op>* __restrict__ A) {
+__global__ void __launch_bounds__(tail_threads<Op>()) k_b_tail(const TailArgs<Op>* __restrict__ A) {
     vcycle_tail_body(A[blockIdx.x]);
+}
+
+// Per-point coefficient records of a level for the prefetching tail:
+// rec[(c*ncp + k)*RL + o] = coef[(c*S + o)*ncp + k] for o < S, zero padding.
+template <int P>
+__global__ void k_to_records(const float* __restrict__ coef, int ncp, int ncol, float* __restrict__ rec) {
+    constexpr int S = (2 * P + 1) * (2 * P + 1), RL = rec_len(P);
+    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= (long long)ncol * ncp * RL) return;
+    const int o = (int)(t % RL);
+    const long long ck = t / RL;
+    const int k = (int)(ck % ncp), c = (int)(ck / ncp);
+    rec[t] = (o < S) ? coef[((size_t)c * S + o) * ncp + k] : 0.f;
 }
 
 // ---------------------------------------------------------------------------

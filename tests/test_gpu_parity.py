@@ -139,9 +139,12 @@ def test_multicolour_sweeps(geom, n_el, p):
         assert rel(host(xg), xr) < 1e-13
 
 
+# tail = 512: the single-workgroup kernel takes every level whose iterates
+# (with those of the coarser levels) fit its LDS store
 VCYCLE_CASES = ([(g, n, p, 32) for g, n, p in CASES_ALL] + [(g, n, p, 0) for g, n, p in CASES_ALL] +
                 [("annulus", 128, 3, 32), ("square", 128, 2, 32), ("annulus", 64, 5, 32),
-                 ("cube", 16, 2, 32)])
+                 ("cube", 16, 2, 32), ("annulus", 128, 3, 512), ("square", 128, 2, 512),
+                 ("annulus", 64, 5, 512), ("cube", 16, 3, 512), ("annulus", 32, 4, 512)])
 
 
 @pytest.mark.parametrize("geom,n_el,p,tail", VCYCLE_CASES)
@@ -271,6 +274,29 @@ def test_fp32_refinement_reaches_tolerance(geom, n_el, p, method):
     print("[fp32-ir] %s n_el=%d p=%d method=%d vcycles=%d err_vs_exact=%.2e"
           % (geom, n_el, p, method, st.vcycles, err))
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("geom,n_el,p", [("annulus", 128, 3), ("cube", 16, 2)])
+def test_fp32_large_tail_matches_multiblock(geom, n_el, p):
+    """FP32 V-cycles with the small levels in the single-workgroup kernel (its
+    LDS store holds twice as many FP32 unknowns) agree with all-multi-block
+    FP32 V-cycles to FP32 rounding, and both reach the FP64 tolerance."""
+    res = {}
+    for tail in (0, 512):
+        s, H, b = case(geom, n_el, p, precision=igamg.FP32_IR, tail_items=tail)
+        N = len(b)
+        xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+        for _ in range(3):
+            s.vcycle(xg)
+        x3 = host(xg)
+        xg.zero_()
+        st, _ = s.solve(xg, tol=1e-10, max_restarts=400, method=igamg.RRE, q=5)
+        A = H.fine.A
+        assert np.linalg.norm(b - A @ host(xg)) / np.linalg.norm(b) <= 1.0000001e-10
+        res[tail] = (x3, host(xg), st.vcycles)
+    assert rel(res[512][0], res[0][0]) < 1e-5
+    assert rel(res[512][1], res[0][1]) < 1e-8
+    assert abs(res[512][2] - res[0][2]) <= 6
 
 
 def test_error_paths():
