@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # Counter-derived HBM traffic per launch of the finest-level colour pass (FETCH_SIZE x 2.0 +
 # WRITE_SIZE, calibrated on a 1 GiB copy), from profiles/gs_colour_annulus1024_p3.md.
 # Valid only for the kernel as profiled; entries are removed when the kernel changes.
-MEASURED_TRAFFIC = {(3, "double"): 38.52e6, (3, "float"): 19.31e6}
+MEASURED_TRAFFIC = {(3, "double"): 38.53e6, (3, "float"): 19.29e6}
 TOL = 1e-10
 Q = 5
 N_EL = 1024
@@ -237,8 +237,9 @@ def main():
     ap.add_argument("--no-c1c3", action="store_true")
     ap.add_argument("--only-batch", action="store_true")
     ap.add_argument("--epochs", type=int, default=10)
-    ap.add_argument("--tail-items", type=int, default=32,
-                    help="single-workgroup V-cycle threshold (0 = one launch per step everywhere)")
+    ap.add_argument("--tail-items", type=int, default=-1,
+                    help="single-workgroup V-cycle threshold (0 = one launch per step everywhere, "
+                         "-1 = autotuned per precision)")
     ap.add_argument("--only-smoother", action="store_true",
                     help="setup + finest-level smoother sweeps only (for kernel profiling)")
     args = ap.parse_args()
@@ -287,6 +288,13 @@ def main():
         log("[bench] setup quarter annulus %d^2 p=%d" % (N_EL, p))
         s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p, tail_items=args.tail_items)
         res = {}
+        if args.tail_items < 0:
+            # split between multi-block levels and the single-workgroup kernel,
+            # tuned per precision (the FP32 form trains above its own split)
+            t64 = s.autotune()
+            s.set_precision(igamg.FP32_IR)
+            t32 = s.autotune()
+            res["tail_split"] = {"fp64": t64[0], "fp32": t32[0]}
         trained = False
         if p == args.headline_degree and not args.no_learned:
             log("[bench] training the learned smoother p=%d" % p)

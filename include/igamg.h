@@ -141,7 +141,9 @@ igamg_status igamg_set_rhs_field(igamg_ctx* ctx, const double* modes, int n_mode
 igamg_status igamg_get_rhs(igamg_ctx* ctx, double* b_dev);
 
 /* Switches the form of G between FP64 and FP32_IR (both operator copies are
- * built at setup).  Errors: EINVAL. */
+ * built at setup).  A context set up with tail_items < 0 then takes the split
+ * igamg_autotune cached for the new precision, if there is one (the FP32 store
+ * of the single-workgroup kernel holds more levels).  Errors: EINVAL. */
 igamg_status igamg_set_precision(igamg_ctx* ctx, int precision);
 
 /* x <- G(x): one V(nu1, nu2) cycle (Algorithm 2, mu = 1) on the finest level,
@@ -197,9 +199,11 @@ igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q,
 
 /* Measurement hook: runs nsweeps multicolour Gauss-Seidel sweeps on level
  * `level` (1..L) in the given precision (igamg_precision: FP64 uses the FP64
- * operator, FP32_IR the FP32 copy) on the context's own work vectors, with a
- * pair of HIP events around every colour launch on the context stream.
- * Outputs (host): avg_ms -- mean duration of one colour launch; bytes --
+ * operator, FP32_IR the FP32 copy) on the context's own work vectors.  The
+ * colour launches are captured as one HIP graph on the context stream (the
+ * form a solve runs them in), replayed once to warm up and once between two
+ * HIP events.  Outputs (host): avg_ms -- elapsed time of the timed replay
+ * divided by the number of colour launches; bytes --
  * algorithmic HBM bytes of one average launch (per updated unknown: the
  * stored coefficients of its row plus b_I and x_I read and x_I written;
  * Kronecker operators count the vectors only); launches -- number timed.

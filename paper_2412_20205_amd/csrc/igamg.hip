@@ -107,6 +107,7 @@ struct igamg_ctx {
     hipGraph_t graph = nullptr;
     int graph_method = -1, graph_q = -1;
     int tail_top = 0;  // levels 0..tail_top run in the single-workgroup kernel
+    bool tail_auto = false;  // tail_items < 0 at setup: take the tuned split of each precision
     // learned smoother
     struct Net {
         bool have = false;
@@ -302,6 +303,7 @@ struct igamg_ctx {
         tail_top = 0;
         if (opt.smoother != IGAMG_SMOOTH_MCGS) return;  // the single-workgroup kernel sweeps colours
         if (opt.tail_items < 0) {
+            tail_auto = true;
             std::lock_guard<std::mutex> g(g_tune_mu);
             auto it = g_tune_cache.find(tune_key());
             opt.tail_items = (it != g_tune_cache.end()) ? it->second : 32;
@@ -654,6 +656,9 @@ struct igamg_ctx {
         return read_scal();
     }
 
+    // nsweeps multicolour sweeps of level l captured as one HIP graph (the form
+    // in which a solve runs them), replayed once to warm up and once between
+    // two events: avg = elapsed / launches.
     template <typename T>
     void profile_smoother_t(int l, int nsweeps, double* avg_ms, double* bytes, int* launches) {
         Level& v = lv[l];
@@ -665,35 +670,49 @@ struct igamg_ctx {
         const int W = 2 * p + 1;
         long long S = (dim == 2) ? W * W : (long long)W * W * W;
         double per_point = (kind == OP_STENCIL2D ? (double)S : 0.0) * sizeof(T) + 3.0 * sizeof(T);
-        int total = nsweeps * v.ncol;
-        std::vector<hipEvent_t> ev(2 * total);
-        for (auto& e : ev) IGAMG_HIP(hipEventCreate(&e));
+        int total = 0;
         double tot_bytes = 0.0;
-        int k = 0;
-        with_op<T>(l, [&](auto op) {
-            using Op = decltype(op);
-            for (int sw = 0; sw < nsweeps; ++sw)
-                for (int c = 0; c < v.ncol; ++c, ++k) {
-                    int cs = colour_size_host(v.n, p, dim, c);
-                    IGAMG_HIP(hipEventRecord(ev[2 * k], stream));
-                    if (cs > 0)
-                        hipLaunchKernelGGL((k_gs_colour_sliced<Op>), dim3((cs + 63) / 64),
-                                           dim3(64 * Op::NW), 0, stream, op, (const T*)bb, x, c);
-                    IGAMG_HIP(hipEventRecord(ev[2 * k + 1], stream));
-                    tot_bytes += cs * per_point;
-                }
-        });
-        check_launch();
-        sync();
-        double ms = 0.0;
-        for (int i = 0; i < total; ++i) {
-            float e = 0.f;
-            IGAMG_HIP(hipEventElapsedTime(&e, ev[2 * i], ev[2 * i + 1]));
-            ms += e;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        IGAMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        try {
+            with_op<T>(l, [&](auto op) {
+                using Op = decltype(op);
+                for (int sw = 0; sw < nsweeps; ++sw)
+                    for (int c = 0; c < v.ncol; ++c) {
+                        int cs = colour_size_host(v.n, p, dim, c);
+                        if (cs == 0) continue;
+                        hipLaunchKernelGGL((k_gs_colour_sliced<Op>), dim3((cs + 63) / 64), dim3(64 * Op::NW),
+                                           0, stream, op, (const T*)bb, x, c);
+                        tot_bytes += cs * per_point;
+                        ++total;
+                    }
+            });
+            check_launch();
+        } catch (...) {
+            (void)hipStreamEndCapture(stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
         }
-        for (auto& e : ev) (void)hipEventDestroy(e);
-        *avg_ms = ms / total;
-        *bytes = tot_bytes / total;
+        IGAMG_HIP(hipStreamEndCapture(stream, &g));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (err == hipSuccess) err = hipEventCreate(&e0);
+        if (err == hipSuccess) err = hipEventCreate(&e1);
+        if (err == hipSuccess) err = hipGraphLaunch(ge, stream);  // warm-up
+        if (err == hipSuccess) err = hipEventRecord(e0, stream);
+        if (err == hipSuccess) err = hipGraphLaunch(ge, stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        (void)hipGraphDestroy(g);
+        if (err != hipSuccess) throw Error(IGAMG_EHIP, std::string("profile: ") + hipGetErrorString(err));
+        *avg_ms = total ? ms / total : 0.0;
+        *bytes = total ? tot_bytes / total : 0.0;
         *launches = total;
     }
     void profile_smoother(int l, int precision, int nsweeps, double* avg_ms, double* bytes,
@@ -1876,6 +1895,11 @@ igamg_status igamg_set_precision(igamg_ctx* ctx, int precision) {
         need(precision == IGAMG_FP64 || precision == IGAMG_FP32_IR, "bad precision");
         if (precision != ctx->opt.precision) {
             ctx->opt.precision = precision;
+            if (ctx->tail_auto) {  // the tuned split of this precision, if any
+                std::lock_guard<std::mutex> g(g_tune_mu);
+                auto it = g_tune_cache.find(ctx->tune_key());
+                if (it != g_tune_cache.end()) ctx->opt.tail_items = it->second;
+            }
             ctx->choose_tail();      // the LDS store holds more FP32 levels
             ctx->graph_method = -1;  // recapture the restart cycle
         }

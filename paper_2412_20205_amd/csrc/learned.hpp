@@ -66,10 +66,10 @@ __device__ __forceinline__ bool l_inside(const LImage& im, int pj, int pi) {
 
 struct LShared {
     float z[22 * 22];
-    uint16_t h1[20 * 20 * kLC];
-    float h2[18 * 18 * kLC];
-    float w1[kLW1];
-    float w3[kLW3];
+    alignas(16) uint16_t h1[20 * 20 * kLC];
+    alignas(16) float h2[18 * 18 * kLC];
+    alignas(16) float w1t[kLW1];  // layer-1 weights tap-major: w1t[tap * 16 + c]
+    alignas(16) float w3t[kLW3];  // layer-3 weights tap-major: w3t[tap * 16 + ci]
 };
 
 // Forward pass of one 16x16 output tile with origin (tj0, ti0); zscale
@@ -78,27 +78,46 @@ struct LShared {
 __device__ inline float l_forward_tile(const LImage& im, const LearnedW& W, int tj0, int ti0,
                                        float zscale, LShared& S) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int t = tid; t < kLW1; t += kLThreads) S.w1[t] = bf16_to_f32(W.w[t]);
-    for (int t = tid; t < kLW3; t += kLThreads) S.w3[t] = bf16_to_f32(W.w[kLW1 + kLW2 + t]);
+    for (int t = tid; t < kLW1; t += kLThreads) S.w1t[(t % 9) * kLC + t / 9] = bf16_to_f32(W.w[t]);
+    for (int t = tid; t < kLW3; t += kLThreads)
+        S.w3t[(t % 9) * kLC + t / 9] = bf16_to_f32(W.w[kLW1 + kLW2 + t]);
     for (int t = tid; t < 22 * 22; t += kLThreads) {
         int pj = tj0 - 3 + t / 22, pi = ti0 - 3 + t % 22;
         S.z[t] = l_inside(im, pj, pi) ? im.z[(size_t)pj * im.width + pi] * zscale : 0.f;
     }
     __syncthreads();
-    // layer 1 (VALU): h1 on 20 x 20, 16 channels, ReLU, zero outside the domain
+    // layer 1 (VALU): h1 on 20 x 20, 16 channels, ReLU, zero outside the domain.
+    // Each channel sums its taps in tap order; weights come 4 channels per
+    // 16-byte LDS read, the 16 BF16 outputs leave in two 16-byte writes.
     for (int p = tid; p < 400; p += kLThreads) {
         int py = p / 20, px = p % 20;
         bool in = l_inside(im, tj0 - 2 + py, ti0 - 2 + px);
         float zz[9];
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) zz[tap] = S.z[(py + tap / 3) * 22 + px + tap % 3];
+        float a[kLC];
 #pragma unroll
-        for (int c = 0; c < kLC; ++c) {
-            float a = 0.f;
+        for (int c = 0; c < kLC; ++c) a[c] = 0.f;
 #pragma unroll
-            for (int tap = 0; tap < 9; ++tap) a = fmaf(S.w1[c * 9 + tap], zz[tap], a);
-            S.h1[p * kLC + c] = f32_to_bf16(in ? fmaxf(a, 0.f) : 0.f);
+        for (int tap = 0; tap < 9; ++tap) {
+            const floatx4* wv = reinterpret_cast<const floatx4*>(&S.w1t[tap * kLC]);
+#pragma unroll
+            for (int q = 0; q < kLC / 4; ++q) {
+                const floatx4 w = wv[q];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[4 * q + e] = fmaf(w[e], zz[tap], a[4 * q + e]);
+            }
         }
+        uint32_t pk[kLC / 2];
+#pragma unroll
+        for (int c2 = 0; c2 < kLC / 2; ++c2) {
+            uint32_t lo = f32_to_bf16(in ? fmaxf(a[2 * c2], 0.f) : 0.f);
+            uint32_t hi = f32_to_bf16(in ? fmaxf(a[2 * c2 + 1], 0.f) : 0.f);
+            pk[c2] = lo | (hi << 16);
+        }
+        uint4* dst = reinterpret_cast<uint4*>(&S.h1[p * kLC]);
+        dst[0] = uint4{pk[0], pk[1], pk[2], pk[3]};
+        dst[1] = uint4{pk[4], pk[5], pk[6], pk[7]};
     }
     __syncthreads();
     // layer 2 (MFMA 16x16x16 BF16): rows = 16 pixels of the 18 x 18 region,
@@ -117,10 +136,9 @@ __device__ inline float l_forward_tile(const LImage& im, const LearnedW& W, int 
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             bf16x4 a = {0, 0, 0, 0};
-            if (va) {
-                const uint16_t* src = &S.h1[((qy + tap / 3) * 20 + qx + tap % 3) * kLC + 4 * (lane >> 4)];
-                a = bf16x4{(short)src[0], (short)src[1], (short)src[2], (short)src[3]};
-            }
+            if (va)
+                a = *reinterpret_cast<const bf16x4*>(
+                    &S.h1[((qy + tap / 3) * 20 + qx + tap % 3) * kLC + 4 * (lane >> 4)]);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[tap], acc, 0, 0, 0);
         }
         int co = lane & 15;
@@ -139,9 +157,14 @@ __device__ inline float l_forward_tile(const LImage& im, const LearnedW& W, int 
     float y = 0.f;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-        const float* h = &S.h2[((oy + tap / 3) * 18 + ox + tap % 3) * kLC];
+        const floatx4* h = reinterpret_cast<const floatx4*>(&S.h2[((oy + tap / 3) * 18 + ox + tap % 3) * kLC]);
+        const floatx4* w = reinterpret_cast<const floatx4*>(&S.w3t[tap * kLC]);
 #pragma unroll
-        for (int c = 0; c < kLC; ++c) y = fmaf(S.w3[c * 9 + tap], h[c], y);
+        for (int q = 0; q < kLC / 4; ++q) {
+            const floatx4 hv = h[q], wv = w[q];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) y = fmaf(wv[e], hv[e], y);
+        }
     }
     return y;
 }
@@ -258,7 +281,7 @@ __global__ void __launch_bounds__(kLThreads) k_learned_train(const LItem* __rest
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
                 int gyy = qy - tap / 3, gxx = qx - tap % 3;
-                if (gyy >= 0 && gyy < 16 && gxx >= 0 && gxx < 16) s = fmaf(S.w3[ci * 9 + tap], gy[gyy * 16 + gxx], s);
+                if (gyy >= 0 && gyy < 16 && gxx >= 0 && gxx < 16) s = fmaf(S.w3t[tap * kLC + ci], gy[gyy * 16 + gxx], s);
             }
         }
         gh2[e] = f32_to_bf16(s);
