@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kBlock) k_b_restrict(const BTr<T>* __restrict_
     if (C >= (long long)nc * nc) return;
     en.zero[C] = 0;
     int J = (int)(C / nc), I = (int)(C - (long long)J * nc);
-    en.dst[C] = transfer2d<P + 2, T>(en.src, nf, en.st, en.w, en.W, nc, I, J);
+    en.dst[C] = transfer2d<restrict_bound(P), T>(en.src, nf, en.st, en.w, en.W, nc, I, J);
 }
 
 // prolongation and correction (dst += P src), src coarse, dst fine
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(kBlock) k_b_prolong(const BTr<T>* __restrict__
     int nc = en.nc, nf = en.nf;
     if (F >= (long long)nf * nf) return;
     int j = (int)(F / nf), i = (int)(F - (long long)j * nf);
-    en.dst[F] += transfer2d<P + 2, T>(en.src, nc, en.st, en.w, en.W, nf, i, j);
+    en.dst[F] += transfer2d<prolong_bound(P), T>(en.src, nc, en.st, en.w, en.W, nf, i, j);
 }
 
 template <typename T>

@@ -279,8 +279,11 @@ struct igamg_ctx {
                                    f.n, bc, c.n, f.r_start, f.rw<T>(), f.RW, xc);
             });
         else
-            hipLaunchKernelGGL(k_restrict3d<T>, dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf, f.n,
-                               bc, c.n, f.r_start, f.rw<T>(), f.RW, xc);
+            with_p3([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                hipLaunchKernelGGL((k_restrict3d<P, T>), dim3(grid_for(c.N)), dim3(kBlock), 0, stream, rf,
+                                   f.n, bc, c.n, f.r_start, f.rw<T>(), f.RW, xc);
+            });
         check_launch();
     }
 
@@ -323,13 +326,11 @@ struct igamg_ctx {
         int top = 0;
         for (int l = 0; l <= L && l < kTailMaxLevels; ++l) {
             used += tail_level_size<T>(l);
-            if (used > tail_capacity<T>() || !tail_level_ok<T>(l)) break;
+            if (used + kTailPadVals + kTailPartVals > tail_capacity<T>() || !tail_level_ok<T>(l)) break;
             top = l;
         }
         return top;
     }
-    // LDS values that level l's iterate takes in the single-workgroup kernel:
-    // the padded layout for stored 2D stencils, the natural one otherwise.
     // The prefetching tail variant (FP32 stored stencils, p <= 3) needs the
     // records of every level it smooths, which exist where a colour fits the block.
     template <typename T>
@@ -340,9 +341,12 @@ struct igamg_ctx {
         });
         return ok;
     }
+    // LDS values that level l takes in the single-workgroup kernel: the padded
+    // iterate for stored 2D stencils; the natural iterate plus (l >= 1) the two
+    // 1D bands for sum-factorised operators.
     template <typename T>
     long long tail_level_size(int l) {
-        long long sz = lv[l].N;
+        long long sz = lv[l].N + (l >= 1 ? 2LL * lv[l].n * (2 * p + 1) : 0);
         with_op<T>(l, [&](auto opl) {
             if constexpr (decltype(opl)::kColourOrder) sz = tl_size(p, tl_vw(sizeof(T)), lv[l].n);
         });
@@ -365,12 +369,14 @@ struct igamg_ctx {
                 if constexpr (std::is_same_v<decltype(opl), Op>) a.op[l] = opl;
             });
             a.N[l] = lv[l].N;
-            a.xoff[l] = (int)off;  // a multiple of the vector width in both layouts used
-            off += tail_level_size<T>(l);
             if constexpr (Op::kColourOrder) {
-                if (l >= 1 && (lv[l].RW > p + 2 || lv[l].PW > p + 2))
-                    throw Error(IGAMG_EINVAL, "transfer window wider than p + 2");
+                a.xoff[l] = (int)off;  // a multiple of the vector width
+            } else {
+                a.boff[l] = (int)off;  // bands K, M (levels >= 1), then the iterate
+                a.xoff[l] = (int)(off + (l >= 1 ? 2LL * lv[l].n * (2 * p + 1) : 0));
             }
+            off += tail_level_size<T>(l);
+
             a.x[l] = (l == tail_top) ? xt : lv[l].x<T>();
             a.b[l] = (l == tail_top) ? (T*)bt : lv[l].b<T>();
             a.r[l] = lv[l].r<T>();
@@ -385,7 +391,7 @@ struct igamg_ctx {
                 a.PW[l] = lv[l].PW;
             }
         }
-        if (tail_top >= kTailMaxLevels || off > tail_capacity<T>())
+        if (tail_top >= kTailMaxLevels || off + kTailPadVals + kTailPartVals > tail_capacity<T>())
             throw Error(IGAMG_EINVAL, "levels 0..tail_top do not fit the single-workgroup kernel");
         return a;
     }
@@ -411,8 +417,11 @@ struct igamg_ctx {
                                    c.n, xf, f.n, f.p_start, f.pw<T>(), f.PW);
             });
         else
-            hipLaunchKernelGGL(k_prolong3d<T>, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, ec, c.n,
-                               xf, f.n, f.p_start, f.pw<T>(), f.PW);
+            with_p3([&](auto PC) {
+                constexpr int P = decltype(PC)::value;
+                hipLaunchKernelGGL((k_prolong3d<P, T>), dim3(grid_for(f.N)), dim3(kBlock), 0, stream, ec,
+                                   c.n, xf, f.n, f.p_start, f.pw<T>(), f.PW);
+            });
         check_launch();
     }
     template <typename T>
@@ -795,9 +804,9 @@ void igamg_ctx::setup_levels(int n_el, int levels) {
         Level& v = lv[l];
         v.RW = T.RW;
         v.PW = T.PW;
-        // the transfer kernels unroll their windows to p + 2 (the width of a
-        // refined B-spline's knot-insertion mask)
-        if (v.RW > p + 2 || v.PW > p + 2) throw Error(IGAMG_EINVAL, "transfer window wider than p + 2");
+        // the transfer kernels unroll their windows to these bounds
+        if (v.RW > restrict_bound(p) || v.PW > prolong_bound(p))
+            throw Error(IGAMG_EINVAL, "transfer window wider than the knot-insertion bound");
         v.r_start = upload(T.r_start);
         v.p_start = upload(T.p_start);
         v.r_w64 = upload(T.r_w);

@@ -170,7 +170,7 @@ template <int P, typename T_>
 struct Kron2D {
     using T = T_;
     using Pt = Pt2;
-    static constexpr int W = 2 * P + 1, NC = (P + 1) * (P + 1);
+    static constexpr int kP = P, W = 2 * P + 1, NC = (P + 1) * (P + 1);
     static constexpr bool kColourOrder = false;
     const T* __restrict__ K;  // n x W bands
     const T* __restrict__ M;
@@ -199,19 +199,38 @@ struct Kron2D {
         return true;
     }
     static constexpr int NW = W;
+    // The i-row of both 1D bands (the same for every slice of a point).
+    struct Bands {
+        T ki[W], mi[W];
+    };
+    __device__ __forceinline__ void bands(const Pt& pt, Bands& B) const {
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            B.ki[a] = K[(size_t)pt.i * W + a];
+            B.mi[a] = M[(size_t)pt.i * W + a];
+        }
+    }
     // Row bb = w - P of the sum-factorised product: M_jb (K_i . x_row) + K_jb (M_i . x_row).
     template <bool kStream = true>
     __device__ __forceinline__ T slice(const T* __restrict__ x, const Pt& pt, int, int, int w,
                                        T& diag) const {
+        Bands B;
+        bands(pt, B);
+        return slice_b(B, x, pt, w, diag);
+    }
+    __device__ __forceinline__ T slice_b(const Bands& B, const T* __restrict__ x, const Pt& pt, int w,
+                                         T& diag) const {
         const int bb = w - P;
         const T* xr = x + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
-        T ki[W], mi[W], xv[W];
+        const T *ki = B.ki, *mi = B.mi;
+        T xv[W];
+        // FP32 iterates are padded (see Stencil2D::slice); band entries of
+        // out-of-range columns are zero
+        if constexpr (std::is_same<T, float>::value)
+            load_window<W>(xr + pt.i - P, xv);
+        else
 #pragma unroll
-        for (int a = 0; a < W; ++a) {
-            ki[a] = K[(size_t)pt.i * W + a];
-            mi[a] = M[(size_t)pt.i * W + a];
-            xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
-        }
+            for (int a = 0; a < W; ++a) xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
         T mj = M[(size_t)pt.j * W + w], kj = K[(size_t)pt.j * W + w];
         T sk = 0, sm = 0;
 #pragma unroll
@@ -228,7 +247,7 @@ template <int P, typename T_>
 struct Kron3D {
     using T = T_;
     using Pt = Pt3;
-    static constexpr int W = 2 * P + 1, NC = (P + 1) * (P + 1) * (P + 1);
+    static constexpr int kP = P, W = 2 * P + 1, NC = (P + 1) * (P + 1) * (P + 1);
     static constexpr bool kColourOrder = false;
     const T* __restrict__ K;
     const T* __restrict__ M;
@@ -263,19 +282,31 @@ struct Kron3D {
         return true;
     }
     static constexpr int NW = W;
+    // The i- and j-rows of both 1D bands (the same for every slice of a point).
+    struct Bands {
+        T ki[W], mi[W], kj[W], mj[W];
+    };
+    __device__ __forceinline__ void bands(const Pt& pt, Bands& B) const {
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            B.ki[a] = K[(size_t)pt.i * W + a];
+            B.mi[a] = M[(size_t)pt.i * W + a];
+            B.kj[a] = K[(size_t)pt.j * W + a];
+            B.mj[a] = M[(size_t)pt.j * W + a];
+        }
+    }
     // Plane cc = w - P: M_kc (sum_b M_jb Kx + K_jb Mx) + K_kc (sum_b M_jb Mx).
     template <bool kStream = true>
     __device__ __forceinline__ T slice(const T* __restrict__ x, const Pt& pt, int, int, int w,
                                        T& diag) const {
+        Bands B;
+        bands(pt, B);
+        return slice_b(B, x, pt, w, diag);
+    }
+    __device__ __forceinline__ T slice_b(const Bands& B, const T* __restrict__ x, const Pt& pt, int w,
+                                         T& diag) const {
         const int cc = w - P;
-        T ki[W], mi[W], kj[W], mj[W];
-#pragma unroll
-        for (int a = 0; a < W; ++a) {
-            ki[a] = K[(size_t)pt.i * W + a];
-            mi[a] = M[(size_t)pt.i * W + a];
-            kj[a] = K[(size_t)pt.j * W + a];
-            mj[a] = M[(size_t)pt.j * W + a];
-        }
+        const T *ki = B.ki, *mi = B.mi, *kj = B.kj, *mj = B.mj;
         const size_t nn = (size_t)n * n;
         const T* xs = x + (size_t)clampi(pt.k + cc, 0, n - 1) * nn;
         T y1 = 0, y2 = 0;
@@ -283,8 +314,11 @@ struct Kron3D {
         for (int bb = -P; bb <= P; ++bb) {
             const T* xr = xs + (size_t)clampi(pt.j + bb, 0, n - 1) * n;
             T xv[W];
+            if constexpr (std::is_same<T, float>::value)
+                load_window<W>(xr + pt.i - P, xv);
+            else
 #pragma unroll
-            for (int a = 0; a < W; ++a) xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
+                for (int a = 0; a < W; ++a) xv[a] = xr[clampi(pt.i + a - P, 0, n - 1)];
             T sk = 0, sm = 0;
 #pragma unroll
             for (int a = 0; a < W; ++a) {
@@ -530,6 +564,13 @@ __global__ void __launch_bounds__(kBlock) k_add_f32_to_f64(const float* __restri
 
 // bc = R rf on the coarse grid; xc (if given) is zeroed: the coarse-grid
 // correction of Algorithm 2 starts from a zero error.
+// Window bounds of the knot-insertion transfers: a coarse B-spline of degree
+// p refines into at most p + 2 fine ones (restriction window); a fine one
+// receives at most floor((p + 1) / 2) + 1 coarse ones (prolongation window).
+// The host checks both when it builds the tables.
+__host__ __device__ constexpr int restrict_bound(int p) { return p + 2; }
+__host__ __device__ constexpr int prolong_bound(int p) { return (p + 1) / 2 + 1; }
+
 // One value of a separable 2D transfer: sum_b w_j[b] sum_a w_i[a] g(sj+b, si+a)
 // over the windows of a 1D table (start st[], weights w[idx*W + a], nw rows),
 // on an n x n row-major grid, indices clamped to the grid.  The windows are
@@ -559,7 +600,7 @@ __device__ __forceinline__ T transfer2d(const T* __restrict__ g, int n, const in
     return acc;
 }
 
-// bc = R rf (R = P^T; window bound p + 2) and, optionally, xc = 0.
+// bc = R rf (R = P^T) and, optionally, xc = 0.
 template <int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict2d(const T* __restrict__ rf, int nf,
                                                        T* __restrict__ bc, int nc,
@@ -570,10 +611,10 @@ __global__ void __launch_bounds__(kBlock) k_restrict2d(const T* __restrict__ rf,
     if (C >= (long long)nc * nc) return;
     if (xc) xc[C] = 0;
     int J = (int)(C / nc), I = (int)(C - (long long)J * nc);
-    bc[C] = transfer2d<P + 2, T>(rf, nf, rs, rw, RW, nc, I, J);
+    bc[C] = transfer2d<restrict_bound(P), T>(rf, nf, rs, rw, RW, nc, I, J);
 }
 
-// xf += P ec (window bound p + 2).
+// xf += P ec.
 template <int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong2d(const T* __restrict__ ec, int nc,
                                                       T* __restrict__ xf, int nf,
@@ -582,10 +623,43 @@ __global__ void __launch_bounds__(kBlock) k_prolong2d(const T* __restrict__ ec, 
     long long F = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (F >= (long long)nf * nf) return;
     int j = (int)(F / nf), i = (int)(F - (long long)j * nf);
-    xf[F] += transfer2d<P + 2, T>(ec, nc, ps, pw, PW, nf, i, j);
+    xf[F] += transfer2d<prolong_bound(P), T>(ec, nc, ps, pw, PW, nf, i, j);
 }
 
-template <typename T>
+// One value of a separable 3D transfer (as transfer2d, one more factor): the
+// window of each plane is unrolled to M, the planes are taken in turn.
+template <int M, typename T>
+__device__ __forceinline__ T transfer3d(const T* __restrict__ g, int n, const int* __restrict__ st,
+                                        const T* __restrict__ w, int W, int nw, int i, int j, int k) {
+    const int si = st[i], sj = st[j], sk = st[k];
+    const int last = nw * W - 1;
+    T wi[M], wj[M], wk[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        const T u = w[min(i * W + a, last)], v = w[min(j * W + a, last)], q = w[min(k * W + a, last)];
+        wi[a] = (a < W) ? u : (T)0;
+        wj[a] = (a < W) ? v : (T)0;
+        wk[a] = (a < W) ? q : (T)0;
+    }
+    T acc = 0;
+#pragma unroll 1
+    for (int c = 0; c < M; ++c) {
+        const T* sl = g + (size_t)min(sk + c, n - 1) * n * n;
+        T s2 = 0;
+#pragma unroll
+        for (int b = 0; b < M; ++b) {
+            const T* row = sl + (size_t)min(sj + b, n - 1) * n;
+            T s1 = 0;
+#pragma unroll
+            for (int a = 0; a < M; ++a) s1 = fma(wi[a], row[min(si + a, n - 1)], s1);
+            s2 = fma(wj[b], s1, s2);
+        }
+        acc = fma(wk[c], s2, acc);
+    }
+    return acc;
+}
+
+template <int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict3d(const T* __restrict__ rf, int nf,
                                                        T* __restrict__ bc, int nc,
                                                        const int* __restrict__ rs,
@@ -598,26 +672,10 @@ __global__ void __launch_bounds__(kBlock) k_restrict3d(const T* __restrict__ rf,
     int K = (int)(C / ncc);
     long long rem = C - (long long)K * ncc;
     int J = (int)(rem / nc), I = (int)(rem - (long long)J * nc);
-    int si = rs[I], sj = rs[J], sk = rs[K];
-    T acc = 0;
-    for (int c = 0; c < RW; ++c) {
-        T wk = rw[(size_t)K * RW + c];
-        const T* sl = rf + (size_t)min(sk + c, nf - 1) * nf * nf;
-        T s2 = 0;
-        for (int b = 0; b < RW; ++b) {
-            T wj = rw[(size_t)J * RW + b];
-            const T* row = sl + (size_t)min(sj + b, nf - 1) * nf;
-            T s = 0;
-            for (int a = 0; a < RW; ++a)
-                s = fma(rw[(size_t)I * RW + a], row[min(si + a, nf - 1)], s);
-            s2 = fma(wj, s, s2);
-        }
-        acc = fma(wk, s2, acc);
-    }
-    bc[C] = acc;
+    bc[C] = transfer3d<restrict_bound(P), T>(rf, nf, rs, rw, RW, nc, I, J, K);
 }
 
-template <typename T>
+template <int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong3d(const T* __restrict__ ec, int nc,
                                                       T* __restrict__ xf, int nf,
                                                       const int* __restrict__ ps,
@@ -628,23 +686,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong3d(const T* __restrict__ ec, 
     int k = (int)(F / nff);
     long long rem = F - (long long)k * nff;
     int j = (int)(rem / nf), i = (int)(rem - (long long)j * nf);
-    int si = ps[i], sj = ps[j], sk = ps[k];
-    T acc = 0;
-    for (int c = 0; c < PW; ++c) {
-        T wk = pw[(size_t)k * PW + c];
-        const T* sl = ec + (size_t)min(sk + c, nc - 1) * nc * nc;
-        T s2 = 0;
-        for (int b = 0; b < PW; ++b) {
-            T wj = pw[(size_t)j * PW + b];
-            const T* row = sl + (size_t)min(sj + b, nc - 1) * nc;
-            T s = 0;
-            for (int a = 0; a < PW; ++a)
-                s = fma(pw[(size_t)i * PW + a], row[min(si + a, nc - 1)], s);
-            s2 = fma(wj, s, s2);
-        }
-        acc = fma(wk, s2, acc);
-    }
-    xf[F] += acc;
+    xf[F] += transfer3d<prolong_bound(P), T>(ec, nc, ps, pw, PW, nf, i, j, k);
 }
 
 // Coarsest grid: x = A_0^{-1} b with the inverse formed from the FP64 Cholesky
@@ -885,6 +927,9 @@ constexpr int tail_threads() {
 // Floats per coefficient record of degree p: (2p+1)^2 rounded up to 4.
 __host__ __device__ constexpr int rec_len(int p) { return ((2 * p + 1) * (2 * p + 1) + 3) / 4 * 4; }
 constexpr int kTailLdsX = 153600;    // LDS bytes for the iterates of levels 0..top
+constexpr int kTailPadVals = 16;     // zero values after the last level (unclamped row reads)
+// slice partials and diagonals of the sliced 3D pass, at the end of the LDS store
+constexpr int kTailPartVals = kTailThreads + kTailThreads / 3 + 1;
 
 // Padded LDS layout of a level's iterate for stored 2D stencils: rows
 // j = -p .. n-1+p and, per row, a left pad of padl >= p columns (a multiple of
@@ -919,6 +964,7 @@ struct TailArgs {
     Op op[kTailMaxLevels];
     long long N[kTailMaxLevels];
     int xoff[kTailMaxLevels];       // offset of level l's iterate in the LDS store
+    int boff[kTailMaxLevels];       // sum-factorised operators: offset of level l's 1D bands (K, M)
     T* x[kTailMaxLevels];           // only x[top] is read and written (in and out)
     T* b[kTailMaxLevels];
     T* r[kTailMaxLevels];
@@ -930,28 +976,22 @@ struct TailArgs {
     int RW[kTailMaxLevels], PW[kTailMaxLevels];
 };
 
-// (A x)_I for one point as the sum, in slice order, of the NW stencil slices
-// (the same slices and the same summation order as the multi-block kernels).
-// A thread owns the whole point; the coefficient loads of G slices are in
-// flight at once, G bounded so that they take at most 64 VGPRs.
+// (A x)_I for one point of a sum-factorised operator: the bands of the point
+// are loaded once, the slices are summed in slice order (as the multi-block
+// kernels sum them); diag receives A_II.
 template <class Op>
 __device__ __forceinline__ typename Op::T tail_row(const Op& A, const typename Op::T* x,
-                                                   const typename Op::Pt& pt, int c, int k,
-                                                   typename Op::T& diag) {
+                                                   const typename Op::Pt& pt, typename Op::T& diag) {
     using T = typename Op::T;
-    constexpr int NW = Op::NW;
-    constexpr int VR = (int)sizeof(T) / 4;
-    constexpr int G0 = 64 / (Op::W * VR);
-    // sum-factorised slices re-read the small 1D bands: one at a time
-    constexpr int G = !Op::kColourOrder ? 1 : (G0 < 1 ? 1 : (G0 > NW ? NW : G0));
+    typename Op::Bands B;
+    A.bands(pt, B);
     T acc = 0;
+    if constexpr (std::is_same<typename Op::Pt, Pt3>::value) {
 #pragma unroll 1
-    for (int w0 = 0; w0 < NW; w0 += G) {
+        for (int w = 0; w < Op::NW; ++w) acc += A.slice_b(B, x, pt, w, diag);
+    } else {
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int w = w0 + g;
-            if (w < NW) acc += A.template slice<false>(x, pt, c, k, w, diag);
-        }
+        for (int w = 0; w < Op::NW; ++w) acc += A.slice_b(B, x, pt, w, diag);
     }
     return acc;
 }
@@ -963,8 +1003,43 @@ __device__ __forceinline__ typename Op::T tail_row(const Op& A, const typename O
 // end).  x lives in LDS; b, r and the coefficients in memory.
 template <class Op>
 __device__ void tail_pass(const Op& A, const typename Op::T* __restrict__ b, typename Op::T* x,
-                          typename Op::T* __restrict__ r, int c0, int c1, int mode) {
+                          typename Op::T* __restrict__ r, int c0, int c1, int mode, typename Op::T* part) {
     using T = typename Op::T;
+    if constexpr (std::is_same<typename Op::Pt, Pt3>::value) {
+        // 3D: one lane per (point, slice), w fastest; the owner lane (w = 0)
+        // sums the point's slices in slice order after a barrier
+        constexpr int NW = Op::NW;
+        constexpr int PPG = kTailThreads / NW;  // points per group
+        for (int c = c0; c < c1; ++c) {
+            const int cs = A.colour_size(c);
+            for (int k0 = 0; k0 < cs; k0 += PPG) {
+                const int t = threadIdx.x, kk = t / NW, w = t - kk * NW, k = k0 + kk;
+                const bool act = kk < PPG && k < cs;
+                typename Op::Pt pt;
+                T bv = 0, d = 1;
+                if (act) {
+                    A.point(c, k, pt);
+                    if (w == 0) bv = b[pt.I];
+                    typename Op::Bands B;
+                    A.bands(pt, B);
+                    part[t] = A.slice_b(B, x, pt, w, d);
+                    if (w == NW / 2) part[kTailThreads + kk] = d;  // A_II from slice p
+                }
+                __syncthreads();
+                if (act && w == 0) {
+                    T acc = 0;
+#pragma unroll
+                    for (int v = 0; v < NW; ++v) acc += part[kk * NW + v];
+                    if (mode == 0)
+                        x[pt.I] = x[pt.I] + (bv - acc) / part[kTailThreads + kk];
+                    else
+                        r[pt.I] = bv - acc;
+                }
+                __syncthreads();
+            }
+        }
+        return;
+    }
     for (int c = c0; c < c1; ++c) {
         const int cs = A.colour_size(c);
         for (int k = threadIdx.x; k < cs; k += kTailThreads) {
@@ -972,7 +1047,7 @@ __device__ void tail_pass(const Op& A, const typename Op::T* __restrict__ b, typ
             A.point(c, k, pt);
             const T bv = b[pt.I];
             T d = 1;
-            const T acc = tail_row(A, x, pt, c, k, d);
+            const T acc = tail_row(A, x, pt, d);
             if (mode == 0)
                 x[pt.I] = x[pt.I] + (bv - acc) / d;
             else
@@ -983,54 +1058,31 @@ __device__ void tail_pass(const Op& A, const typename Op::T* __restrict__ b, typ
     if (mode == 1) __syncthreads();
 }
 
-// b_c = R r_f (memory to memory) and x_c = 0 (LDS).
-template <typename T>
-__device__ void tail_restrict(const T* rf, int nf, T* bc, T* xc, int nc, const int* rs,
-                              const T* rw, int RW, int dim) {
-    long long Nc = (long long)nc * nc * (dim == 3 ? nc : 1);
-    for (long long C = threadIdx.x; C < Nc; C += kTailThreads) {
-        int I = (int)(C % nc), J = (int)((C / nc) % nc), K = (dim == 3) ? (int)(C / ((long long)nc * nc)) : 0;
-        T acc = 0;
-        int KR = (dim == 3) ? RW : 1;
-        for (int cc = 0; cc < KR; ++cc) {
-            T wk = (dim == 3) ? rw[(size_t)K * RW + cc] : (T)1;
-            size_t zoff = (dim == 3) ? (size_t)min(rs[K] + cc, nf - 1) * nf * nf : 0;
-            T s2 = 0;
-            for (int bq = 0; bq < RW; ++bq) {
-                const T* row = rf + zoff + (size_t)min(rs[J] + bq, nf - 1) * nf;
-                T s1 = 0;
-                for (int a = 0; a < RW; ++a) s1 = fma(rw[(size_t)I * RW + a], row[min(rs[I] + a, nf - 1)], s1);
-                s2 = fma(rw[(size_t)J * RW + bq], s1, s2);
-            }
-            acc = fma(wk, s2, acc);
-        }
-        bc[C] = acc;
+// b_c = R r_f (r_f in memory) and x_c = 0 (LDS); windows unrolled to their bounds.
+template <int P, int DIM, typename T>
+__device__ void tail_restrict(const T* rf, int nf, T* bc, T* xc, int nc, const int* rs, const T* rw,
+                              int RW) {
+    const int nn = nc * nc, Nc = (DIM == 3) ? nn * nc : nn;
+    for (int C = threadIdx.x; C < Nc; C += kTailThreads) {
+        const int K = C / nn, rem = C - K * nn, J = rem / nc, I = rem - J * nc;
+        if constexpr (DIM == 3)
+            bc[C] = transfer3d<restrict_bound(P), T>(rf, nf, rs, rw, RW, nc, I, J, K);
+        else
+            bc[C] = transfer2d<restrict_bound(P), T>(rf, nf, rs, rw, RW, nc, I, J);
         xc[C] = 0;
     }
 }
 
-// x_f += P e_c (LDS to LDS).
-template <typename T>
-__device__ void tail_prolong(const T* ec, int nc, T* xf, int nf, const int* ps, const T* pw,
-                             int PW, int dim) {
-    long long Nf = (long long)nf * nf * (dim == 3 ? nf : 1);
-    for (long long F = threadIdx.x; F < Nf; F += kTailThreads) {
-        int i = (int)(F % nf), j = (int)((F / nf) % nf), k = (dim == 3) ? (int)(F / ((long long)nf * nf)) : 0;
-        T acc = 0;
-        int KP = (dim == 3) ? PW : 1;
-        for (int cc = 0; cc < KP; ++cc) {
-            T wk = (dim == 3) ? pw[(size_t)k * PW + cc] : (T)1;
-            size_t zoff = (dim == 3) ? (size_t)min(ps[k] + cc, nc - 1) * nc * nc : 0;
-            T s2 = 0;
-            for (int bq = 0; bq < PW; ++bq) {
-                const T* row = ec + zoff + (size_t)min(ps[j] + bq, nc - 1) * nc;
-                T s1 = 0;
-                for (int a = 0; a < PW; ++a) s1 = fma(pw[(size_t)i * PW + a], row[min(ps[i] + a, nc - 1)], s1);
-                s2 = fma(pw[(size_t)j * PW + bq], s1, s2);
-            }
-            acc = fma(wk, s2, acc);
-        }
-        xf[F] += acc;
+// x_f += P e_c (both in LDS).
+template <int P, int DIM, typename T>
+__device__ void tail_prolong(const T* ec, int nc, T* xf, int nf, const int* ps, const T* pw, int PW) {
+    const int nn = nf * nf, Nf = (DIM == 3) ? nn * nf : nn;
+    for (int F = threadIdx.x; F < Nf; F += kTailThreads) {
+        const int k = F / nn, rem = F - k * nn, j = rem / nf, i = rem - j * nf;
+        if constexpr (DIM == 3)
+            xf[F] += transfer3d<prolong_bound(P), T>(ec, nc, ps, pw, PW, nf, i, j, k);
+        else
+            xf[F] += transfer2d<prolong_bound(P), T>(ec, nc, ps, pw, PW, nf, i, j);
     }
 }
 
@@ -1143,11 +1195,11 @@ __device__ void ft_pass(const Stencil2D<P, T>& A, const T* __restrict__ b, T* xl
     if (mode == 1) __syncthreads();
 }
 
-// b_c = R r_f from memory; the windows are unrolled to their bound p + 2.
+// b_c = R r_f from memory; the windows are unrolled to their bound.
 template <int P, typename T>
 __device__ void ft_restrict(const T* __restrict__ rf_, int nf, T* __restrict__ bc_, int nc,
                             const int* __restrict__ rs_, const T* __restrict__ rw_, int RW) {
-    constexpr int RM = P + 2;
+    constexpr int RM = restrict_bound(P);
     const auto rf = as_global(rf_);
     const auto bc = as_global(bc_);
     const auto rs = as_global(rs_);
@@ -1181,7 +1233,7 @@ __device__ void ft_prolong(const T* ec, int nc, T* xf, int nf, const int* __rest
                            const T* __restrict__ pw_, int PW) {
     const auto ps = as_global(ps_);
     const auto pw = as_global(pw_);
-    constexpr int PM = P + 2, VW = tl_vw(sizeof(T)), PADL = tl_padl(P, VW);
+    constexpr int PM = prolong_bound(P), VW = tl_vw(sizeof(T)), PADL = tl_padl(P, VW);
     const int RSc = tl_stride(P, VW, nc), RSf = tl_stride(P, VW, nf);
     const int last = nf * PW - 1;
     for (int F = threadIdx.x; F < nf * nf; F += blockDim.x) {
@@ -1374,28 +1426,48 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
 // ---- sum-factorised operators: natural layout ------------------------------
 
 // V-cycle (Algorithm 2, mu = 1) on levels 0..top with right-hand side b[top]
-// and iterate x[top] (in place), by one workgroup.  The host guarantees that
-// the LDS store holds levels 0..top (xoff[top] + size of level top).
+// and iterate x[top] (in place), by one workgroup.  LDS holds, level by
+// level, the 1D bands K and M (levels >= 1, at boff) and the iterate (at
+// xoff), then kTailPadVals zeros, and at its end kTailPartVals values for
+// the sliced 3D pass; the host checks that this fits.
 template <class Op>
 __device__ void gt_vcycle(const TailArgs<Op>& a) {
     using T = typename Op::T;
     constexpr int DIM = std::is_same<typename Op::Pt, Pt3>::value ? 3 : 2;
+    constexpr int P = Op::kP, W = Op::W;
     __shared__ T xs[tail_capacity<T>()];
+    T* part = xs + tail_capacity<T>() - kTailPartVals;
     const int top = a.top;
+    for (int l = 1; l <= top; ++l) {
+        const int nw = a.op[l].n * W;
+        T* kb = xs + a.boff[l];
+        for (int e = threadIdx.x; e < nw; e += kTailThreads) {
+            kb[e] = a.op[l].K[e];
+            kb[nw + e] = a.op[l].M[e];
+        }
+    }
     {
         const T* xg = a.x[top];
         T* xt = xs + a.xoff[top];
-        for (long long i = threadIdx.x; i < a.N[top]; i += kTailThreads) xt[i] = xg[i];
+        const int Nt = (int)a.N[top];
+        for (int i = threadIdx.x; i < Nt + kTailPadVals; i += kTailThreads) xt[i] = (i < Nt) ? xg[i] : (T)0;
     }
     __syncthreads();
+    // operator of level l reading its bands from LDS
+    auto lop = [&](int l) {
+        Op A = a.op[l];
+        A.K = xs + a.boff[l];
+        A.M = A.K + A.n * W;
+        return A;
+    };
     for (int l = top; l >= 1; --l) {
-        const Op& A = a.op[l];
+        const Op A = lop(l);
         T* xl = xs + a.xoff[l];
         for (int s = 0; s < a.nu1; ++s)
-            for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0);
-        tail_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1);
-        tail_restrict(a.r[l], A.n, a.b[l - 1], xs + a.xoff[l - 1], a.op[l - 1].n, a.rs[l], a.rw[l],
-                      a.RW[l], DIM);
+            for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0, part);
+        tail_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1, part);
+        tail_restrict<P, DIM, T>(a.r[l], A.n, a.b[l - 1], xs + a.xoff[l - 1], a.op[l - 1].n, a.rs[l],
+                                 a.rw[l], a.RW[l]);
         __syncthreads();
     }
     {
@@ -1403,18 +1475,19 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
         const T* b0 = a.b[0];
         for (int r = threadIdx.x; r < a.n0; r += kTailThreads) {
             double s = 0.0;
+#pragma unroll 8
             for (int c = 0; c < a.n0; ++c) s = fma(a.Ainv[(size_t)r * a.n0 + c], (double)b0[c], s);
             x0[r] = (T)s;
         }
     }
     __syncthreads();
     for (int l = 1; l <= top; ++l) {
-        const Op& A = a.op[l];
+        const Op A = lop(l);
         T* xl = xs + a.xoff[l];
-        tail_prolong(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l], DIM);
+        tail_prolong<P, DIM, T>(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l]);
         __syncthreads();
         for (int s = 0; s < a.nu2; ++s)
-            for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0);
+            for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0, part);
     }
     {
         T* xg = a.x[top];
