@@ -236,6 +236,14 @@ struct igamg_ctx {
         check_launch();
     }
 
+    // Bytes of level l's stored coefficients in a precision (0 for Kronecker operators).
+    long long coef_bytes(int l, size_t elem) const {
+        if (kind != OP_STENCIL2D) return 0;
+        const long long W = 2 * p + 1;
+        return (long long)lv[l].ncol * W * W * lv[l].ncp * (long long)elem;
+    }
+    static constexpr long long kCachedCoefBytes = 64LL << 20;
+
     template <typename T>
     void smooth(int l, const T* bb, T* x, int nsweeps) {
         Level& v = lv[l];
@@ -254,13 +262,20 @@ struct igamg_ctx {
                 copy(v.r<T>(), x, v.N);
                 continue;
             }
+            // coefficients of levels up to kCachedCoefBytes are re-read from
+            // cache by the next sweep; larger levels stream them
+            const bool stream_coef = coef_bytes(l, sizeof(T)) > kCachedCoefBytes;
             with_op<T>(l, [&](auto op) {
                 using Op = decltype(op);
                 for (int c = 0; c < v.ncol; ++c) {
                     int cs = colour_size_host(v.n, p, dim, c);
                     if (cs == 0) continue;
-                    hipLaunchKernelGGL((k_gs_colour_sliced<Op>), dim3((cs + 63) / 64), dim3(64 * Op::NW),
-                                       0, stream, op, bb, x, c);
+                    if (stream_coef)
+                        hipLaunchKernelGGL((k_gs_colour_sliced<Op, true>), dim3((cs + 63) / 64),
+                                           dim3(64 * Op::NW), 0, stream, op, bb, x, c);
+                    else
+                        hipLaunchKernelGGL((k_gs_colour_sliced<Op, false>), dim3((cs + 63) / 64),
+                                           dim3(64 * Op::NW), 0, stream, op, bb, x, c);
                 }
             });
             check_launch();

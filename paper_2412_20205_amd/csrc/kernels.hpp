@@ -346,7 +346,9 @@ struct Kron3D {
 // wave w computes the partial product of stencil slice w for its 64 points
 // (all of the slice's loads in flight at once), the partials meet in LDS and
 // are summed in slice order.
-template <class Op>
+// kStream: non-temporal coefficient loads (levels whose coefficients do not
+// stay in cache between the passes of a sweep); cached loads otherwise.
+template <class Op, bool kStream = true>
 __device__ __forceinline__ void gs_colour_body(const Op& A, const typename Op::T* __restrict__ b,
                                                typename Op::T* __restrict__ x, int c, int blk) {
     using T = typename Op::T;
@@ -364,7 +366,7 @@ __device__ __forceinline__ void gs_colour_body(const Op& A, const typename Op::T
         bo = b[pt.I];
     }
     T d = 1, sl = 0;
-    if (ok) sl = A.slice(x, pt, c, k, w, d);
+    if (ok) sl = A.template slice<kStream>(x, pt, c, k, w, d);
     part[w][lane] = sl;
     if (w == Op::NW / 2) dg[lane] = d;
     __syncthreads();
@@ -376,12 +378,12 @@ __device__ __forceinline__ void gs_colour_body(const Op& A, const typename Op::T
     }
 }
 
-template <class Op>
+template <class Op, bool kStream = true>
 __global__ void __launch_bounds__(64 * Op::NW) k_gs_colour_sliced(Op A,
                                                                   const typename Op::T* __restrict__ b,
                                                                   typename Op::T* __restrict__ x,
                                                                   int c) {
-    gs_colour_body(A, b, x, c, xcd_swizzle(blockIdx.x, gridDim.x));
+    gs_colour_body<Op, kStream>(A, b, x, c, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 template <class Op, typename Tout>
