@@ -170,9 +170,10 @@ __device__ inline float l_forward_tile(const LImage& im, const LearnedW& W, int 
 }
 
 // Inference on a whole level: x_I += sigma * N(z / sigma)_I, with
+// (three waves per SIMD: at most 168 VGPRs, three workgroups per CU)
 // sigma = scal[0] (skipped when sigma <= 0), or y written to yout.
 template <typename T>
-__global__ void __launch_bounds__(kLThreads) k_learned_apply(LImage im, LearnedW W,
+__global__ void __launch_bounds__(kLThreads, 3) k_learned_apply(LImage im, LearnedW W,
                                                              const double* __restrict__ sigma_dev,
                                                              T* __restrict__ x,
                                                              float* __restrict__ yout) {
