@@ -45,7 +45,7 @@ struct Level {
     int ncol = 0, ncp = 0;
     double* coef64 = nullptr;
     float* coef32 = nullptr;
-    float* rec32 = nullptr;  // per-point FP32 records for the prefetching tail (p <= 3)
+    float* rec32 = nullptr;  // per-point FP32 coefficient records for the prefetching tail
     double *K64 = nullptr, *M64 = nullptr;
     float *K32 = nullptr, *M32 = nullptr;
     Band1D Kh, Mh;
@@ -346,8 +346,8 @@ struct igamg_ctx {
         }
         return top;
     }
-    // The prefetching tail variant (FP32 stored stencils, p <= 3) needs the
-    // records of every level it smooths, which exist where a colour fits the block.
+    // The prefetching tail variant (FP32 stored stencils) needs the records of
+    // every level it smooths, which exist where a colour fits the block.
     template <typename T>
     bool tail_level_ok(int l) {
         bool ok = true;
@@ -962,20 +962,19 @@ void igamg_ctx::setup_coarse() {
 }
 
 // Per-point FP32 coefficient records of the levels whose colours fit the
-// prefetching single-workgroup kernel's block.
+// prefetching single-workgroup kernel's block (one point per thread).
 void igamg_ctx::setup_records() {
     for (int l = 1; l <= L; ++l) {
         Level& v = lv[l];
         int mx = 0;
         for (int c = 0; c < v.ncol; ++c) mx = std::max(mx, colour_size_host(v.n, p, dim, c));
-        if (mx > kTailPfThreads) continue;
+        if (mx > pf_threads(p)) continue;
         const long long cnt = (long long)v.ncol * v.ncp * rec_len(p);
         v.rec32 = alloc<float>(cnt);
         with_p([&](auto PC) {
             constexpr int P = decltype(PC)::value;
-            if constexpr (P <= 3)
-                hipLaunchKernelGGL(k_to_records<P>, dim3(grid_for(cnt)), dim3(kBlock), 0, stream,
-                                   (const float*)v.coef32, v.ncp, v.ncol, v.rec32);
+            hipLaunchKernelGGL(k_to_records<P>, dim3(grid_for(cnt)), dim3(kBlock), 0, stream,
+                               (const float*)v.coef32, v.ncp, v.ncol, v.rec32);
         });
         check_launch();
     }
@@ -1042,7 +1041,7 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
         setup_coarse();
         if (kind == OP_STENCIL2D) setup_kron_stencils();
     }
-    if (kind == OP_STENCIL2D && p <= 3) setup_records();
+    if (kind == OP_STENCIL2D) setup_records();
     for (int l = 0; l <= L; ++l) {
         Level& v = lv[l];
         v.x64 = alloc<double>(v.N);

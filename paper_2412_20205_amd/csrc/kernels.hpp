@@ -912,19 +912,23 @@ __global__ void __launch_bounds__(kBlock) k_extrap_combine(IterPtrs S, int q, lo
 
 constexpr int kTailMaxLevels = 8;
 constexpr int kTailThreads = 1024;
-constexpr int kTailPfThreads = 512;  // prefetching variant: 256 VGPRs per thread
-
-// FP32 stored stencils up to p = 3 take the prefetching variant: the
-// coefficients of a point are one 16-byte aligned record and the next colour
-// step's records are in flight while the current step computes.
+// FP32 stored stencils take the prefetching variant: the coefficients of a
+// point are one 16-byte aligned record and the next colour step's records are
+// in flight while the current step computes.  Two records per thread must fit
+// the register budget: 512 threads (256 VGPRs) up to p = 4, 256 threads
+// (512 VGPRs) for p = 5; one point per thread, so a level's colours must fit.
+__host__ __device__ constexpr int pf_threads(int p) { return p <= 4 ? 512 : 256; }
 template <class Op>
 constexpr bool tail_prefetch() {
-    if constexpr (Op::kColourOrder) return std::is_same<typename Op::T, float>::value && Op::kP <= 3;
+    if constexpr (Op::kColourOrder) return std::is_same<typename Op::T, float>::value;
     else return false;
 }
 template <class Op>
 constexpr int tail_threads() {
-    return tail_prefetch<Op>() ? kTailPfThreads : kTailThreads;
+    if constexpr (Op::kColourOrder)
+        return tail_prefetch<Op>() ? pf_threads(Op::kP) : kTailThreads;
+    else
+        return kTailThreads;
 }
 // Floats per coefficient record of degree p: (2p+1)^2 rounded up to 4.
 __host__ __device__ constexpr int rec_len(int p) { return ((2 * p + 1) * (2 * p + 1) + 3) / 4 * 4; }
@@ -1260,7 +1264,7 @@ __device__ void ft_prolong(const T* ec, int nc, T* xf, int nf, const int* __rest
     }
 }
 
-// Prefetching variant (FP32, p <= 3): records rec[(c*ncp + k)*RL + o],
+// Prefetching variant (FP32): records rec[(c*ncp + k)*RL + o],
 // o = w*W + a, RL = rec_len(p); one point per thread and colour.
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -1272,7 +1276,12 @@ __device__ __forceinline__ void pf_point(const f4v (&cq)[rec_len(P) / 4], const 
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         float xv[W];
-        ft_window<P, float, S0>(xr + (size_t)w * RS, xv);
+        if constexpr (S0 >= 0) {
+            ft_window<P, float, S0>(xr + (size_t)w * RS, xv);
+        } else {
+#pragma unroll
+            for (int e = 0; e < W; ++e) xv[e] = xr[(size_t)w * RS + e];
+        }
         float ra = 0.f;
 #pragma unroll
         for (int e = 0; e < W; ++e) ra = fma(cq[(w * W + e) / 4][(w * W + e) % 4], xv[e], ra);
@@ -1325,10 +1334,14 @@ __device__ __forceinline__ void pf_step(const Stencil2D<P, float>& A, float* xl,
     const int n = A.n, RS = tl_stride(P, 4, n);
     if (ok) {
         const int c = s % NC;
-        const int s0 = (PADL - P + c % (P + 1)) % 4;  // window phase of the colour
-        const int sc = PADL - P + pi;                  // sc - s0 is a multiple of 4
+        const int sc = PADL - P + pi;  // first window column
         float acc, d;
-        pf_point_phase<P>(q, xl + (size_t)pj * RS + sc - s0, RS, s0, acc, d);
+        if constexpr ((P + 1) % 4 == 0) {
+            const int s0 = (PADL - P + c % (P + 1)) % 4;  // window phase of the colour
+            pf_point_phase<P>(q, xl + (size_t)pj * RS + sc - s0, RS, s0, acc, d);
+        } else {
+            pf_point<P, -1>(q, xl + (size_t)pj * RS + sc, RS, acc, d);  // scalar window reads
+        }
         if (s < ngs) {
             float* xp = xl + (size_t)(pj + P) * RS + PADL + pi;
             *xp = *xp + (bq - acc) / d;
