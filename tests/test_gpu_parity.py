@@ -276,7 +276,8 @@ def test_fp32_refinement_reaches_tolerance(geom, n_el, p, method):
     assert err < 1e-6
 
 
-@pytest.mark.parametrize("geom,n_el,p", [("annulus", 128, 3), ("cube", 16, 2)])
+@pytest.mark.parametrize("geom,n_el,p", [("annulus", 128, 3), ("cube", 16, 2), ("annulus", 64, 5),
+                                         ("annulus", 64, 4), ("annulus", 64, 1), ("square", 64, 2)])
 def test_fp32_large_tail_matches_multiblock(geom, n_el, p):
     """FP32 V-cycles with the small levels in the single-workgroup kernel (its
     LDS store holds twice as many FP32 unknowns) agree with all-multi-block
