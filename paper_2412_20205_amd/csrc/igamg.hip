@@ -224,7 +224,8 @@ struct igamg_ctx {
         return (v.N + 63) / 64;
     }
 
-    // out = b - A x (mode 0), A x (mode 1), Jacobi step (mode 2)
+    // out = b - A x (mode 0), A x (mode 1), Jacobi step (mode 2), z = D^{-1}(b - A x)
+    // as float with per-block sums of z^2 in part (mode 3)
     template <typename T, typename Tout>
     void residual(int l, const T* bb, const T* x, Tout* out, int mode, double* part) {
         long long nb = residual_blocks(l);
@@ -452,15 +453,13 @@ struct igamg_ctx {
         return learned_on && l > tail_top && l < (int)nets.size() && nets[l].have;
     }
     // Learned first pre-smoothing step on level l: x += sigma N_l(D^{-1} r / sigma).
+    // The residual kernel writes z = D^{-1} r and per-block sums of z^2 directly.
     template <typename T>
     void learned_step(int l, const T* bl, T* xl) {
         Level& v = lv[l];
-        residual<T, T>(l, bl, xl, v.r<T>(), 0, nullptr);
-        unsigned nb = grid_for(v.N);
-        hipLaunchKernelGGL(k_learned_prep<T>, dim3(nb), dim3(kBlock), 0, stream, (const T*)v.r<T>(),
-                           (const T*)diag<T>(l), v.N, lz, partial);
-        hipLaunchKernelGGL(k_learned_sigma, dim3(1), dim3(kBlock), 0, stream, partial, (int)nb, v.N,
-                           scal + 2);
+        residual<T, float>(l, bl, xl, lz, 3, partial);
+        hipLaunchKernelGGL(k_learned_sigma, dim3(1), dim3(kLSigmaThreads), 0, stream, partial,
+                           (int)residual_blocks(l), v.N, scal + 2);
         LImage im{lz, v.n, v.n, v.n, 0, 0};
         LearnedW W{nets[l].wc, nets[l].w2f, nets[l].w2b};
         int tiles = (v.n + kLTile - 1) / kLTile;
@@ -1332,7 +1331,7 @@ void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
                 unsigned nb = grid_for(N);
                 hipLaunchKernelGGL(k_learned_sumsq_scaled, dim3(nb), dim3(kBlock), 0, stream, tmp1,
                                    diag64[l], N, partial);
-                hipLaunchKernelGGL(k_learned_sigma, dim3(1), dim3(kBlock), 0, stream, partial, (int)nb, N,
+                hipLaunchKernelGGL(k_learned_sigma, dim3(1), dim3(kLSigmaThreads), 0, stream, partial, (int)nb, N,
                                    scal + 3);
                 float* zz = alloc<float>(N);
                 float* tt = alloc<float>(N);

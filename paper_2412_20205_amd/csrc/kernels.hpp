@@ -424,14 +424,20 @@ __device__ __forceinline__ void residual_body(const Op& A, const typename Op::T*
 #pragma unroll
         for (int v = 0; v < Op::NW; ++v) acc += part[v][lane];
         T v;
-        if (mode == 0)
+        if (mode == 0 || mode == 3)
             v = bo - acc;
         else if (mode == 1)
             v = acc;
         else
             v = xo + (T)omega * (bo - acc) / dg[lane];
-        out[pt.I] = (Tout)v;
-        sq = (double)v * (double)v;
+        if (mode == 3) {  // learned-step input z = D^{-1} (b - A x) and z^2
+            const float z = (float)((double)v / (double)dg[lane]);
+            out[pt.I] = (Tout)z;
+            sq = (double)z * z;
+        } else {
+            out[pt.I] = (Tout)v;
+            sq = (double)v * (double)v;
+        }
     }
     if (partial) {
         if (w == 0) {

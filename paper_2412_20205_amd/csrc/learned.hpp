@@ -193,30 +193,14 @@ __global__ void __launch_bounds__(kLThreads, 3) k_learned_apply(LImage im, Learn
     }
 }
 
-// z = r / diag (FP32) and per-block sums of z^2.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_learned_prep(const T* __restrict__ r,
-                                                         const T* __restrict__ diag, long long N,
-                                                         float* __restrict__ z,
-                                                         double* __restrict__ partial) {
-    __shared__ double red[kBlock / 64];
-    long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
+// sigma = sqrt(sum partial / N), one block of kLSigmaThreads.
+constexpr int kLSigmaThreads = 1024;
+__global__ void __launch_bounds__(kLSigmaThreads) k_learned_sigma(const double* __restrict__ partial, int np,
+                                                                  long long N, double* __restrict__ sigma) {
+    __shared__ double red[kLSigmaThreads / 64];
     double s = 0.0;
-    if (I < N) {
-        float v = (float)((double)r[I] / (double)diag[I]);
-        z[I] = v;
-        s = (double)v * v;
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-// sigma = sqrt(sum partial / N)
-__global__ void k_learned_sigma(const double* __restrict__ partial, int np, long long N,
-                                double* __restrict__ sigma) {
-    __shared__ double red[kBlock / 64];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
+#pragma unroll 4
+    for (int i = threadIdx.x; i < np; i += kLSigmaThreads) s += partial[i];
     s = block_sum(s, red);
     if (threadIdx.x == 0) sigma[0] = sqrt(s / (double)N);
 }
