@@ -96,6 +96,10 @@ typedef struct {
                             V-cycle (default 32; 0 disables)                  */
     int stored_stencil;  /* unit square: store (2p+1)^2 stencils (expanded from
                             the Kronecker factors) instead of the factors (0) */
+    int mu;              /* cycle index of Algorithm 2: level l calls level
+                            l-1's cycle mu times on the same coarse right-hand
+                            side (1: V-cycle, 2: W-cycle; 1..4; default 1).
+                            Batches and smoother training need mu = 1.       */
     void* stream;        /* hipStream_t or NULL                               */
 } igamg_options;
 

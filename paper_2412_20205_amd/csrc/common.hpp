@@ -23,6 +23,7 @@ struct Error : std::runtime_error {
     } while (0)
 
 constexpr int kBlock = 256;       // threads per block of the streaming kernels
+constexpr int kMaxMu = 4;         // largest cycle index of Algorithm 2 accepted
 constexpr int kNumXcd = 8;        // accelerator complex dies of an MI355X
 constexpr int kQrRows = 512;      // rows of one tall-skinny QR panel (LDS <= 37 KB)
 constexpr int kMaxQ = 8;          // largest restart number q

@@ -377,6 +377,7 @@ struct igamg_ctx {
         a.top = tail_top;
         a.nu1 = opt.nu1;
         a.nu2 = opt.nu2;
+        a.mu = opt.mu;
         a.n0 = n0;
         a.Ainv = Ainv0;
         long long off = 0;
@@ -468,11 +469,48 @@ struct igamg_ctx {
         check_launch();
     }
 
-    // One V(nu1, nu2) cycle (Algorithm 2, mu = 1) in precision T starting on
-    // level `top` with right-hand side bt and iterate xt (in place).  Levels
-    // above tail_top launch one kernel per step; levels 0..min(top, tail_top)
-    // run in one single-workgroup kernel.  `rec`, when given, is called at the
-    // start of every level l >= 1 with (l, b_l, x_l).
+    // Levels 0..tt of a cycle on level l-1 (l-1 <= tt): the single-workgroup
+    // kernel when tt >= 1, else the coarse solve.
+    template <typename T>
+    void bottom(int tt, const T* bl, T* xl) {
+        if (tt >= 1) {
+            int save = tail_top;
+            tail_top = tt;
+            tail<T>(bl, xl);
+            tail_top = save;
+        } else {
+            coarse<T>(bl, xl);
+        }
+    }
+    // One mu-cycle (Algorithm 2, mu = opt.mu > 1) on a level l > tt: the
+    // coarse cycle runs mu times on the same restricted residual, each call
+    // after the first starting from the previous result.
+    template <typename T>
+    void mucycle(int l, int tt, const T* bl, T* xl) {
+        if (use_learned(l)) {
+            learned_step<T>(l, bl, xl);
+            smooth<T>(l, bl, xl, opt.nu1 - 1);
+        } else {
+            smooth<T>(l, bl, xl, opt.nu1);
+        }
+        residual<T, T>(l, bl, xl, lv[l].r<T>(), 0, nullptr);
+        restrict_<T>(l, lv[l].r<T>(), lv[l - 1].b<T>(), lv[l - 1].x<T>());
+        for (int k = 0; k < opt.mu; ++k) {
+            if (l - 1 > tt)
+                mucycle<T>(l - 1, tt, lv[l - 1].b<T>(), lv[l - 1].x<T>());
+            else
+                bottom<T>(tt, lv[tt].b<T>(), lv[tt].x<T>());
+        }
+        prolong_<T>(l, lv[l - 1].x<T>(), xl);
+        smooth<T>(l, bl, xl, opt.nu2);
+    }
+
+    // One V(nu1, nu2) cycle (Algorithm 2; the mu-cycle when opt.mu > 1) in
+    // precision T starting on level `top` with right-hand side bt and iterate
+    // xt (in place).  Levels above tail_top launch one kernel per step; levels
+    // 0..min(top, tail_top) run in one single-workgroup kernel.  `rec`, when
+    // given (V-cycles only), is called at the start of every level l >= 1
+    // with (l, b_l, x_l).
     template <typename T, class Rec = std::nullptr_t>
     void vcycle_from(int top, const T* bt, T* xt, Rec rec = nullptr) {
         if (top == 0) {
@@ -480,6 +518,15 @@ struct igamg_ctx {
             return;
         }
         const int tt = std::min({tail_top, top, tail_limit<T>()});
+        if (opt.mu > 1) {
+            if constexpr (!std::is_same_v<Rec, std::nullptr_t>)
+                throw Error(IGAMG_EINVAL, "recording levels needs mu = 1");
+            if (top <= tt)
+                bottom<T>(tt, bt, xt);
+            else
+                mucycle<T>(top, tt, bt, xt);
+            return;
+        }
         for (int l = top; l > tt; --l) {
             const T* bl = (l == top) ? bt : lv[l].b<T>();
             T* xl = (l == top) ? xt : lv[l].x<T>();
@@ -493,14 +540,7 @@ struct igamg_ctx {
             residual<T, T>(l, bl, xl, lv[l].r<T>(), 0, nullptr);
             restrict_<T>(l, lv[l].r<T>(), lv[l - 1].b<T>(), lv[l - 1].x<T>());
         }
-        if (tt >= 1) {
-            int save = tail_top;
-            tail_top = tt;
-            tail<T>((tt == top) ? bt : lv[tt].b<T>(), (tt == top) ? xt : lv[tt].x<T>());
-            tail_top = save;
-        } else {
-            coarse<T>(lv[0].b<T>(), lv[0].x<T>());
-        }
+        bottom<T>(tt, (tt == top) ? bt : lv[tt].b<T>(), (tt == top) ? xt : lv[tt].x<T>());
         for (int l = tt + 1; l <= top; ++l) {
             const T* bl = (l == top) ? bt : lv[l].b<T>();
             T* xl = (l == top) ? xt : lv[l].x<T>();
@@ -1018,6 +1058,7 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
     }
     if (p < 1 || p > 5 || (dim == 3 && p > 3)) throw Error(IGAMG_EINVAL, "unsupported degree");
     if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu1 + opt.nu2 == 0) throw Error(IGAMG_EINVAL, "bad nu1/nu2");
+    if (opt.mu < 1 || opt.mu > kMaxMu) throw Error(IGAMG_EINVAL, "cycle index mu must be in 1..4");
     if (opt.smoother != IGAMG_SMOOTH_MCGS && opt.smoother != IGAMG_SMOOTH_JACOBI &&
         opt.smoother != IGAMG_SMOOTH_LEXGS)
         throw Error(IGAMG_EINVAL, "unknown smoother");
@@ -1834,6 +1875,7 @@ void igamg_options_default(igamg_options* opt) {
     opt->use_graphs = 1;
     opt->tail_items = 32;
     opt->stored_stencil = 0;
+    opt->mu = 1;
     opt->stream = nullptr;
 }
 
@@ -2180,6 +2222,7 @@ igamg_status igamg_setup_batch(int count, const igamg_geometry* geoms, const int
             o = *opt;
         else
             igamg_options_default(&o);
+        need(o.mu == 1, "batched solves run V-cycles (mu = 1)");
         if (o.stream) {
             B->stream = (hipStream_t)o.stream;
         } else {
@@ -2314,6 +2357,7 @@ igamg_status igamg_train_smoother(igamg_ctx* ctx, const igamg_train_options* o,
                                   igamg_train_report* report) {
     return guarded([&] {
         need(ctx && o, "null argument");
+        need(ctx->opt.mu == 1, "the smoother is trained on V-cycles (mu = 1)");
         igamg_train_report rep{};
         ctx->train(*o, rep);
         if (report) *report = rep;

@@ -971,6 +971,7 @@ struct TailArgs {
     using T = typename Op::T;
     int top;                        // finest level handled here
     int nu1, nu2;
+    int mu;                         // cycle index of Algorithm 2 (1: V-cycle, 2: W-cycle)
     int n0;                         // coarsest unknowns
     const double* Ainv;             // coarsest inverse (FP64)
     Op op[kTailMaxLevels];
@@ -987,6 +988,40 @@ struct TailArgs {
     const T* pw[kTailMaxLevels];
     int RW[kTailMaxLevels], PW[kTailMaxLevels];
 };
+
+// Order of the steps of one mu-cycle (Algorithm 2) on levels 0..top, without
+// recursion: down(l) pre-smooths level l, restricts its residual to b_{l-1}
+// and zeroes x_{l-1}; coarse() solves level 0; up(l) adds the prolongated
+// correction to x_l and post-smooths.  Level l calls the cycle of level l-1
+// mu times on the same b_{l-1}, the later calls starting from the previous
+// result.  Every thread of the workgroup runs the same sequence.
+template <class Down, class Coarse, class Up>
+__device__ __forceinline__ void mu_schedule(int top, int mu, Down down, Coarse coarse, Up up) {
+    if (top == 0) {
+        coarse();
+        return;
+    }
+    unsigned done = 0;  // 4 bits per level: finished coarse calls of its active cycle
+    int l = top;
+    for (;;) {
+        for (; l > 0; --l) {
+            down(l);
+            done &= ~(15u << (4 * l));
+        }
+        coarse();
+        for (;;) {
+            ++l;
+            const unsigned d = ((done >> (4 * l)) & 15u) + 1;
+            done = (done & ~(15u << (4 * l))) | (d << (4 * l));
+            if ((int)d < mu) {
+                --l;  // the next call of level l-1's cycle
+                break;
+            }
+            up(l);
+            if (l == top) return;
+        }
+    }
+}
 
 // (A x)_I for one point of a sum-factorised operator: the bands of the point
 // are loaded once, the slices are summed in slice order (as the multi-block
@@ -1209,9 +1244,10 @@ __device__ void ft_pass(const Stencil2D<P, T>& A, const T* __restrict__ b, T* xl
 
 // b_c = R r_f from memory; the windows are unrolled to their bound.
 template <int P, typename T>
-__device__ void ft_restrict(const T* __restrict__ rf_, int nf, T* __restrict__ bc_, int nc,
+__device__ void ft_restrict(const T* __restrict__ rf_, int nf, T* __restrict__ bc_, T* xc, int nc,
                             const int* __restrict__ rs_, const T* __restrict__ rw_, int RW) {
-    constexpr int RM = restrict_bound(P);
+    constexpr int RM = restrict_bound(P), VW = tl_vw(sizeof(T)), PADL = tl_padl(P, VW);
+    const int RSc = tl_stride(P, VW, nc);
     const auto rf = as_global(rf_);
     const auto bc = as_global(bc_);
     const auto rs = as_global(rs_);
@@ -1236,6 +1272,7 @@ __device__ void ft_restrict(const T* __restrict__ rf_, int nf, T* __restrict__ b
             s2 = fma(wj[bq], s1, s2);
         }
         bc[C] = s2;
+        xc[(size_t)(J + P) * RSc + PADL + I] = 0;
     }
 }
 
@@ -1400,7 +1437,7 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
             xt[(size_t)(I / n + P) * RS + PADL + I % n] = xg[I];
     }
     __syncthreads();
-    for (int l = top; l >= 1; --l) {
+    auto down = [&](int l) {
         const Op& A = a.op[l];
         T* xl = xs + a.xoff[l];
         if constexpr (tail_prefetch<Op>()) {
@@ -1409,10 +1446,11 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
             for (int s = 0; s < a.nu1; ++s) ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 0);
             ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1);
         }
-        ft_restrict<P, T>(a.r[l], A.n, a.b[l - 1], a.op[l - 1].n, a.rs[l], a.rw[l], a.RW[l]);
+        ft_restrict<P, T>(a.r[l], A.n, a.b[l - 1], xs + a.xoff[l - 1], a.op[l - 1].n, a.rs[l], a.rw[l],
+                          a.RW[l]);
         __syncthreads();
-    }
-    {
+    };
+    auto coarse = [&]() {
         const int nc = a.op[0].n, RS = tl_stride(P, VW, nc);
         T* x0 = xs + a.xoff[0];
         const auto b0 = as_global((const T*)a.b[0]);
@@ -1423,9 +1461,9 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
             for (int c = 0; c < a.n0; ++c) s = fma(Ainv[(size_t)r * a.n0 + c], (double)b0[c], s);
             x0[(size_t)(r / nc + P) * RS + PADL + r % nc] = (T)s;
         }
-    }
-    __syncthreads();
-    for (int l = 1; l <= top; ++l) {
+        __syncthreads();
+    };
+    auto up = [&](int l) {
         const Op& A = a.op[l];
         T* xl = xs + a.xoff[l];
         ft_prolong<P, T>(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l]);
@@ -1434,7 +1472,8 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
             pf_sequence<P>(A, a.rec[l], a.b[l], xl, a.r[l], a.nu2, false);
         else
             for (int s = 0; s < a.nu2; ++s) ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 0);
-    }
+    };
+    mu_schedule(top, a.mu, down, coarse, up);
     {
         const int n = a.op[top].n, RS = tl_stride(P, VW, n);
         const auto xg = as_global(a.x[top]);
@@ -1446,8 +1485,8 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
 
 // ---- sum-factorised operators: natural layout ------------------------------
 
-// V-cycle (Algorithm 2, mu = 1) on levels 0..top with right-hand side b[top]
-// and iterate x[top] (in place), by one workgroup.  LDS holds, level by
+// mu-cycle (Algorithm 2) on levels 0..top with right-hand side b[top] and
+// iterate x[top] (in place), by one workgroup.  LDS holds, level by
 // level, the 1D bands K and M (levels >= 1, at boff) and the iterate (at
 // xoff), then kTailPadVals zeros, and at its end kTailPartVals values for
 // the sliced 3D pass; the host checks that this fits.
@@ -1481,7 +1520,7 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
         A.M = A.K + A.n * W;
         return A;
     };
-    for (int l = top; l >= 1; --l) {
+    auto down = [&](int l) {
         const Op A = lop(l);
         T* xl = xs + a.xoff[l];
         for (int s = 0; s < a.nu1; ++s)
@@ -1490,8 +1529,8 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
         tail_restrict<P, DIM, T>(a.r[l], A.n, a.b[l - 1], xs + a.xoff[l - 1], a.op[l - 1].n, a.rs[l],
                                  a.rw[l], a.RW[l]);
         __syncthreads();
-    }
-    {
+    };
+    auto coarse = [&]() {
         T* x0 = xs + a.xoff[0];
         const T* b0 = a.b[0];
         for (int r = threadIdx.x; r < a.n0; r += kTailThreads) {
@@ -1500,16 +1539,17 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
             for (int c = 0; c < a.n0; ++c) s = fma(a.Ainv[(size_t)r * a.n0 + c], (double)b0[c], s);
             x0[r] = (T)s;
         }
-    }
-    __syncthreads();
-    for (int l = 1; l <= top; ++l) {
+        __syncthreads();
+    };
+    auto up = [&](int l) {
         const Op A = lop(l);
         T* xl = xs + a.xoff[l];
         tail_prolong<P, DIM, T>(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l]);
         __syncthreads();
         for (int s = 0; s < a.nu2; ++s)
             for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0, part);
-    }
+    };
+    mu_schedule(top, a.mu, down, coarse, up);
     {
         T* xg = a.x[top];
         const T* xt = xs + a.xoff[top];

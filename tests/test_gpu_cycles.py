@@ -1,0 +1,122 @@
+"""Parity of mu-cycles (Algorithm 2 with mu = 2, the W-cycle) and of the
+paper's own smoother setting (weighted Jacobi, V(1,1), omega = 2/3, RRE(8),
+tolerance 1e-12; Section 5) with the FP64 CPU oracle.
+
+Bars as for the V-cycle: FP64 iterates to 1e-12 relative per iterate; solves
+reach their tolerance with the oracle's V-cycle and restart counts; FP32
+W-cycles with the small levels in the single-workgroup kernel agree with
+all-multi-block FP32 W-cycles to FP32 rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import extrapolation as ex, multigrid as mg
+from paper_2412_20205_amd import igamg
+
+from test_gpu_parity import DEV, case, host, rel
+
+pytestmark = pytest.mark.gpu
+
+# tail 0: every level multi-block; 32: the small levels in one workgroup;
+# 512: every level that fits the workgroup's LDS store
+W_CASES = [("annulus", 32, 3, 32), ("annulus", 32, 3, 0), ("annulus", 16, 5, 32),
+           ("square", 32, 2, 32), ("square", 16, 3, 0), ("square", 8, 1, 32),
+           ("cube", 8, 2, 32), ("cube", 8, 3, 0), ("annulus", 128, 3, 512),
+           ("square", 64, 2, 512), ("cube", 16, 2, 512)]
+
+
+@pytest.mark.parametrize("geom,n_el,p,tail", W_CASES)
+def test_wcycle_iterates(geom, n_el, p, tail):
+    s, H, b = case(geom, n_el, p, tail_items=tail, mu=2)
+    L = len(H.levels) - 1
+    N = len(b)
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    xr = np.zeros(N)
+    for it in range(4):
+        s.vcycle(xg)
+        xr = mg.mu_cycle(H, L, b, xr, mg.SMOOTH_MCGS, 2, 2, 2)
+        assert rel(host(xg), xr) < 1e-12, it
+
+
+@pytest.mark.parametrize("geom,n_el,p", [("annulus", 32, 3), ("square", 32, 2)])
+def test_mu3_iterates(geom, n_el, p):
+    """mu = 3 exercises a visit count above two in both the single-workgroup
+    schedule and the host recursion."""
+    s, H, b = case(geom, n_el, p, tail_items=32, mu=3)
+    L = len(H.levels) - 1
+    N = len(b)
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    xr = np.zeros(N)
+    for it in range(3):
+        s.vcycle(xg)
+        xr = mg.mu_cycle(H, L, b, xr, mg.SMOOTH_MCGS, 2, 2, 3)
+        assert rel(host(xg), xr) < 1e-12, it
+
+
+@pytest.mark.parametrize("geom,n_el,p", [("annulus", 128, 3), ("annulus", 64, 5), ("cube", 16, 2),
+                                         ("square", 64, 2)])
+def test_fp32_wcycle_tail_matches_multiblock(geom, n_el, p):
+    res = {}
+    for tail in (0, 512):
+        s, H, b = case(geom, n_el, p, precision=igamg.FP32_IR, tail_items=tail, mu=2)
+        N = len(b)
+        xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+        for _ in range(3):
+            s.vcycle(xg)
+        x3 = host(xg)
+        xg.zero_()
+        st, _ = s.solve(xg, tol=1e-10, max_restarts=400, method=igamg.RRE, q=5)
+        A = H.fine.A
+        assert np.linalg.norm(b - A @ host(xg)) / np.linalg.norm(b) <= 1.0000001e-10
+        res[tail] = (x3, host(xg), st.vcycles)
+    assert rel(res[512][0], res[0][0]) < 1e-5
+    assert rel(res[512][1], res[0][1]) < 1e-8
+    assert abs(res[512][2] - res[0][2]) <= 6
+
+
+@pytest.mark.parametrize("mu", [1, 2])
+@pytest.mark.parametrize("geom,n_el,p", [("square", 32, 2), ("square", 16, 4), ("annulus", 16, 3)])
+def test_jacobi_v11_iterates(geom, n_el, p, mu):
+    """Weighted Jacobi (omega = 2/3) with one pre- and one post-smoothing step."""
+    s, H, b = case(geom, n_el, p, smoother=igamg.SMOOTH_JACOBI, nu1=1, nu2=1, mu=mu)
+    L = len(H.levels) - 1
+    N = len(b)
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    xr = np.zeros(N)
+    for it in range(5):
+        s.vcycle(xg)
+        xr = mg.mu_cycle(H, L, b, xr, mg.SMOOTH_JACOBI, 1, 1, mu)
+        assert rel(host(xg), xr) < 1e-12, it
+
+
+@pytest.mark.parametrize("mu", [1, 2])
+@pytest.mark.parametrize("method", [igamg.EXTRAP_NONE, igamg.RRE, igamg.MPE])
+def test_paper_setting_solve(method, mu):
+    """Unit square, p = 2, weighted Jacobi V(1,1)/W(1,1), RRE(8) or MPE(8),
+    tolerance 1e-12: same V-cycle and restart counts as the oracle and the
+    same solution."""
+    geom, n_el, p = "square", 32, 2
+    s, H, b = case(geom, n_el, p, smoother=igamg.SMOOTH_JACOBI, nu1=1, nu2=1, mu=mu)
+    L = len(H.levels) - 1
+    N = len(b)
+    A = H.fine.A
+    nb = np.linalg.norm(b)
+    G = lambda x: mg.mu_cycle(H, L, b, x, mg.SMOOTH_JACOBI, 1, 1, mu)
+    rn = lambda x: np.linalg.norm(b - A @ x) / nb
+    om = {igamg.EXTRAP_NONE: None, igamg.RRE: ex.RRE, igamg.MPE: ex.MPE}[method]
+    xr, st_r, _ = ex.restarted_solve(G, rn, np.zeros(N), 8, om, tol=1e-12, max_restarts=2000)
+    assert st_r.converged
+    xg = torch.zeros(N, dtype=torch.float64, device=DEV)
+    st, _ = s.solve(xg, tol=1e-12, max_restarts=2000, method=method, q=8)
+    x = host(xg)
+    assert st.rel_residual <= 1e-12 and rn(x) <= 1.0000001e-12
+    assert st.vcycles == st_r.vcycles and st.restarts == st_r.restarts
+    assert rel(x, xr) < 1e-11
+
+
+def test_mu_argument_errors():
+    with pytest.raises(igamg.IgamgError):
+        igamg.Solver(igamg.UNIT_SQUARE, 16, 2, mu=0)
+    with pytest.raises(igamg.IgamgError):
+        igamg.Solver(igamg.UNIT_SQUARE, 16, 2, mu=5)
