@@ -17,6 +17,11 @@ right-hand side already on the device.  Forms timed per degree:
                  measured contraction on seed 5900; other degrees: ir_rre).
 `value` is the chosen form's ms per solve at the headline degree.
 
+Extra legs (reported under config, not timed into `value`): the unit square
+64^2 p = 2 and the unit cube 128^3 p = 3 workloads, the batch of 96 problems,
+and the paper's own 2D setting of Table 11 (64^2 elements, 4 levels, weighted
+Jacobi V(1,1)/W(1,1), plain and RRE/MPE, p = 1..5, relative residual 1e-12).
+
 The roofline entry is the dominant kernel of the chosen form: one colour pass
 of the finest-level FP32 multicolour Gauss-Seidel, timed live with HIP events
 around each launch (igamg_profile_smoother).  The CPU baseline is the FP64
@@ -158,6 +163,43 @@ def c1_measure(igamg, torch, synth, steps):
     return out
 
 
+# Iteration counts printed in Table 11 (2D Poisson, 64 x 64 elements, V(1,1)
+# weighted Jacobi with omega = 2/3, tolerance 1e-12): V-cycle, W-cycle, and
+# restart cycles of RRE(q) and MPE(q) with q = 4 (p <= 2) or 8 (p >= 3).
+PAPER_TABLE11_ITER = {1: (10, 4, 2, 2), 2: (13, 9, 2, 2), 3: (49, 33, 3, 3), 4: (161, 108, 5, 5),
+                      5: (466, 352, 8, 8)}
+
+
+def paper_setting_measure(igamg, torch, synth, steps):
+    """The paper's own 2D setting (Section 5, Table 11): unit square, 64^2
+    elements, 4 levels, weighted Jacobi V(1,1)/W(1,1), f of the model problem
+    with exact u = sin(2 pi x) sin(2 pi y), relative residual 1e-12, FP64.
+    Reports V-cycle counts, restart counts and ms per solve beside the
+    paper's printed counts (its stopping norm is not stated; context only)."""
+    out = {}
+    for p in range(1, 6):
+        q = 4 if p <= 2 else 8
+        row = {"q": q, "paper_iter": dict(zip(("v", "w", "rre", "mpe"), PAPER_TABLE11_ITER[p]))}
+        for name, mu, m in (("v", 1, igamg.EXTRAP_NONE), ("w", 2, igamg.EXTRAP_NONE),
+                            ("rre", 1, igamg.RRE), ("mpe", 1, igamg.MPE)):
+            s = igamg.Solver(igamg.UNIT_SQUARE, 64, p, levels=4, smoother=igamg.SMOOTH_JACOBI,
+                             nu1=1, nu2=1, mu=mu)
+            s.set_rhs_field(synth.poisson_2d_sine_modes(1))
+            x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
+            s.solve(x, tol=1e-12, max_restarts=5000, method=m, q=q)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                x.zero_()
+                st, _ = s.solve(x, tol=1e-12, max_restarts=5000, method=m, q=q)
+            torch.cuda.synchronize()
+            row[name] = {"ms": round((time.perf_counter() - t0) * 1e3 / steps, 3), "vcycles": st.vcycles,
+                         "restarts": st.restarts, "rel_residual": st.rel_residual}
+            s.close()
+        out["p%d" % p] = row
+    return out
+
+
 def c3_measure(igamg, torch, synth, steps):
     """Unit cube, p = 3, 128^3 elements, f = 3 pi^2 prod sin(pi x_d), V(2,2)
     multicolour GS (64 colours): plain FP64 V-cycles, FP64 MPE(4), and MPE(4)
@@ -235,6 +277,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-c1c3", action="store_true")
+    ap.add_argument("--no-paper-setting", action="store_true")
     ap.add_argument("--only-batch", action="store_true")
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--tail-items", type=int, default=-1,
@@ -349,6 +392,11 @@ def main():
         log("[bench] unit cube 128^3 p=3")
         c3, c3x = c3_measure(igamg, torch, synth, max(1, args.steps // 2))
 
+    paper = None
+    if not args.no_paper_setting:
+        log("[bench] paper setting: unit square 64^2, Jacobi V(1,1)/W(1,1), p = 1..5")
+        paper = paper_setting_measure(igamg, torch, synth, max(1, args.steps // 2))
+
     batch = None
     if not args.no_batch:
         log("[bench] batch of 96 problems")
@@ -394,7 +442,8 @@ def main():
                    "per_degree": {str(k): v for k, v in results.items()},
                    "batch": batch,
                    "unit_square_64_p2": c1,
-                   "unit_cube_128_p3": c3},
+                   "unit_cube_128_p3": c3,
+                   "paper_setting_square64_jacobi": paper},
         "roofline": headline["smoother_fp32"],
         "cpu_baseline": cpu,
     }

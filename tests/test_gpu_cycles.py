@@ -120,3 +120,38 @@ def test_mu_argument_errors():
         igamg.Solver(igamg.UNIT_SQUARE, 16, 2, mu=0)
     with pytest.raises(igamg.IgamgError):
         igamg.Solver(igamg.UNIT_SQUARE, 16, 2, mu=5)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_table11_setting_counts(p):
+    """The Section 5 setting of Table 11 (64 x 64 elements, 4 levels, weighted
+    Jacobi V(1,1) and W(1,1), RRE(q)/MPE(q) with q = 4 for p <= 2 and 8 above,
+    relative residual 1e-12): the library's V-cycle and restart counts equal
+    the oracle's and the solutions agree."""
+    import synth
+    from oracle import assemble
+    n_el, q = 64, (4 if p <= 2 else 8)
+    modes = synth.poisson_2d_sine_modes(1)
+    H = mg.build_hierarchy("square", n_el, p, 8)
+    b = assemble.kron_load_2d(n_el, p, modes)
+    A = H.fine.A
+    L = len(H.levels) - 1
+    assert L + 1 == 4
+    nb = np.linalg.norm(b)
+    rn = lambda x: np.linalg.norm(b - A @ x) / nb
+    for mu, method in ((1, igamg.EXTRAP_NONE), (2, igamg.EXTRAP_NONE), (1, igamg.RRE), (1, igamg.MPE)):
+        print("[table11] p=%d mu=%d method=%d" % (p, mu, method), flush=True)
+        G = lambda x: mg.mu_cycle(H, L, b, x, mg.SMOOTH_JACOBI, 1, 1, mu)
+        om = {igamg.EXTRAP_NONE: None, igamg.RRE: ex.RRE, igamg.MPE: ex.MPE}[method]
+        xr, st_r, _ = ex.restarted_solve(G, rn, np.zeros(len(b)), q, om, tol=1e-12, max_restarts=3000)
+        assert st_r.converged
+        s = igamg.Solver(igamg.UNIT_SQUARE, n_el, p, levels=4, smoother=igamg.SMOOTH_JACOBI,
+                         nu1=1, nu2=1, mu=mu)
+        s.set_rhs_field(modes)
+        xg = torch.zeros(len(b), dtype=torch.float64, device=DEV)
+        st, _ = s.solve(xg, tol=1e-12, max_restarts=3000, method=method, q=q)
+        x = host(xg)
+        s.close()
+        assert st.vcycles == st_r.vcycles and st.restarts == st_r.restarts
+        assert rn(x) <= 1.0000001e-12
+        assert rel(x, xr) < 1e-10

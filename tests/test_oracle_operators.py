@@ -1,9 +1,11 @@
 """Pins of the oracle's 2D/3D operators and load vectors.
 
 Paper: Section 2 (A SPD, eq. (2); Galerkin operator eq. (4)); Section 4.2
-(2D Poisson, eq. (12)); Section 4.3 (quarter annulus as a B-spline surface).
+(2D Poisson, eq. (12)); Section 4.3 (quarter annulus as a B-spline surface);
+Section 5 (Table 11: 2D discretisation errors).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -152,3 +154,54 @@ def test_galerkin_square_equals_rediscretisation():
     H = multigrid.build_hierarchy("square", 16, 3)
     Ac = assemble.kron_operator_2d(8, 3)
     assert abs(H.levels[-2].A - Ac).max() < 1e-12 * abs(Ac).max()
+
+
+def _l2_error_2d(n_el, p, modes, exact):
+    """L2 error of the exact discrete solution (p+3 Gauss points per direction)."""
+    A = assemble.kron_operator_2d(n_el, p)
+    b = assemble.kron_load_2d(n_el, p, modes)
+    u = spla.spsolve(A.tocsc(), b)
+    n = n_el + p - 2
+    U = np.zeros((n + 2, n + 2))
+    U[1:-1, 1:-1] = u.reshape(n, n)
+    xq, wq, V, _ = bspline.local_basis_tables(n_el, p, p + 3)
+    err = 0.0
+    for ey in range(n_el):
+        for ex in range(n_el):
+            c = U[ey:ey + p + 1, ex:ex + p + 1]
+            uh = np.einsum("qa,rb,ba->rq", V[ex], V[ey], c)   # [qy, qx]
+            ue = exact(xq[ex][None, :], xq[ey][:, None])
+            err += np.sum(wq[ey][:, None] * wq[ex][None, :] * (uh - ue) ** 2)
+    return math.sqrt(err)
+
+
+def test_table11_l2_errors_reproduced():
+    """Table 11's L2-err column for the Section 5 model problem on 64 x 64
+    elements: reproduced to 3 % for p = 3, 4, 5.  For p = 1, 2 the printed
+    values are 15-20 % below the exact 2D discrete solution's error (for p = 2..5
+    they equal the 1D values of Table 1 at 64 elements, which the 2D error of
+    this product solution approaches only as the error shrinks); there the
+    error is required to be within 25 % and above the printed value."""
+    golden = os.path.join(os.path.dirname(__file__), "golden", "table11_l2err_2d.txt")
+    rows = [l.split() for l in open(golden) if l.strip() and not l.startswith("#")]
+    exact = lambda x, y: np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+    modes = synth.poisson_2d_sine_modes(1)
+    for ne, p, v in rows:
+        ne, p, v = int(ne), int(p), float(v)
+        e = _l2_error_2d(ne, p, modes, exact)
+        if p >= 3:
+            assert abs(e / v - 1) < 0.03, (p, v, e)
+        else:
+            assert 1.0 < e / v < 1.25, (p, v, e)
+
+
+def test_poisson_2d_modes_reproduce_f():
+    """The mode table of the Section 5 model problem evaluates to
+    f = 2 (2 k pi)^2 sin(2 k pi x) sin(2 k pi y)."""
+    rng = np.random.default_rng(3)
+    x, y = rng.uniform(0, 1, 100), rng.uniform(0, 1, 100)
+    for k in (1, 2):
+        m = synth.poisson_2d_sine_modes(k)
+        f = sum(a * np.sin(np.pi * (kx * x + ky * y) + ph) for a, kx, ky, ph in m)
+        ref = 2 * (2 * k * np.pi) ** 2 * np.sin(2 * k * np.pi * x) * np.sin(2 * k * np.pi * y)
+        np.testing.assert_allclose(f, ref, atol=1e-12)
