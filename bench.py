@@ -22,9 +22,10 @@ Extra legs (reported under config, not timed into `value`): the unit square
 and the paper's own 2D setting of Table 11 (64^2 elements, 4 levels, weighted
 Jacobi V(1,1)/W(1,1), plain and RRE/MPE, p = 1..5, relative residual 1e-12).
 
-The roofline entry is the dominant kernel of the chosen form: one colour pass
-of the finest-level FP32 multicolour Gauss-Seidel, timed live with HIP events
-around each launch (igamg_profile_smoother).  The CPU baseline is the FP64
+The roofline entry is the dominant kernel of the chosen form: one row-class
+launch of the finest-level FP32 multicolour Gauss-Seidel (the p+1 colours of
+the rows j = r mod p+1), timed live with HIP events around a replayed graph of
+sweeps (igamg_profile_smoother).  The CPU baseline is the FP64
 oracle's own restarted RRE(5) solve of the same workload on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -40,10 +41,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Counter-derived HBM traffic per launch of the finest-level colour pass (FETCH_SIZE x 2.0 +
-# WRITE_SIZE, calibrated on a 1 GiB copy), from profiles/gs_colour_annulus1024_p3.md.
-# Valid only for the kernel as profiled; entries are removed when the kernel changes.
-MEASURED_TRAFFIC = {(3, "double"): 38.53e6, (3, "float"): 19.29e6}
+# Counter-derived HBM traffic per launch of the finest-level row-class sweep (FETCH_SIZE x 2.0
+# + WRITE_SIZE, calibrated on a 1 GiB copy), from the committed counter profile of that
+# kernel.  Valid only for the kernel as profiled; entries are removed when the kernel changes.
+MEASURED_TRAFFIC = {}
 TOL = 1e-10
 Q = 5
 N_EL = 1024
@@ -88,7 +89,8 @@ def smoother_roofline(s, igamg, precision, nsweeps=8):
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": MEASURED_TRAFFIC.get((s.degree, tname)),
-            "kernel": "k_gs_colour_sliced<Stencil2D<%d,%s>> (finest level)" % (s.degree, tname),
+            "kernel": "k_gs_rowclass<Stencil2D<%d,%s>> (finest level; the p+1 colours of a row "
+                      "class per launch)" % (s.degree, tname),
             "avg_launch_us": round(ms * 1e3, 3), "bytes_per_launch": int(by), "launches": n}
 
 

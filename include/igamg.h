@@ -100,6 +100,10 @@ typedef struct {
                             l-1's cycle mu times on the same coarse right-hand
                             side (1: V-cycle, 2: W-cycle; 1..4; default 1).
                             Batches and smoother training need mu = 1.       */
+    int row_sweeps;      /* stored stencils: sweep the p+1 colours of a row
+                            class (rows j = r mod p+1) in one launch, one
+                            workgroup per row (default 1); 0: one launch per
+                            colour.  Both give the same iterates.            */
     void* stream;        /* hipStream_t or NULL                               */
 } igamg_options;
 

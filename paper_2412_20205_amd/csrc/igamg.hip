@@ -263,24 +263,73 @@ struct igamg_ctx {
                 copy(v.r<T>(), x, v.N);
                 continue;
             }
-            // coefficients of levels up to kCachedCoefBytes are re-read from
-            // cache by the next sweep; larger levels stream them
-            const bool stream_coef = coef_bytes(l, sizeof(T)) > kCachedCoefBytes;
-            with_op<T>(l, [&](auto op) {
-                using Op = decltype(op);
-                for (int c = 0; c < v.ncol; ++c) {
-                    int cs = colour_size_host(v.n, p, dim, c);
-                    if (cs == 0) continue;
-                    if (stream_coef)
-                        hipLaunchKernelGGL((k_gs_colour_sliced<Op, true>), dim3((cs + 63) / 64),
-                                           dim3(64 * Op::NW), 0, stream, op, bb, x, c);
-                    else
-                        hipLaunchKernelGGL((k_gs_colour_sliced<Op, false>), dim3((cs + 63) / 64),
-                                           dim3(64 * Op::NW), 0, stream, op, bb, x, c);
-                }
-            });
-            check_launch();
+            mc_sweep<T>(l, bb, x);
         }
+    }
+
+    // Stored-stencil levels narrow enough for the LDS row store sweep the p+1
+    // colours of a row class in one launch.
+    // Stored-stencil levels narrow enough for the LDS row store (and with at
+    // most kRowThreads points per colour and row) sweep the p+1 colours of a
+    // row class in one launch.
+    // (the kernel addresses a level's coefficients with 32-bit byte offsets)
+    bool row_sweeps(int l) const {
+        return opt.row_sweeps && kind == OP_STENCIL2D && row_fits(p, lv[l].n) &&
+               coef_bytes(l, sizeof(double)) < (1LL << 32);
+    }
+    // One multicolour Gauss-Seidel sweep of level l (multi-block launches).
+    // Returns the number of launches; *bytes (when given) receives the
+    // algorithmic bytes: per updated point its coefficients, b, and x read
+    // and written.
+    template <typename T>
+    int mc_sweep(int l, const T* bb, T* x, double* bytes = nullptr) {
+        Level& v = lv[l];
+        // coefficients of levels up to kCachedCoefBytes are re-read from
+        // cache by the next sweep; larger levels stream them
+        const bool stream_coef = coef_bytes(l, sizeof(T)) > kCachedCoefBytes;
+        const int W = 2 * p + 1;
+        const long long S = (dim == 2) ? W * W : (long long)W * W * W;
+        const double per_point = (kind == OP_STENCIL2D ? (double)S : 0.0) * sizeof(T) + 3.0 * sizeof(T);
+        int launches = 0;
+        with_op<T>(l, [&](auto op) {
+            using Op = decltype(op);
+            if constexpr (Op::kColourOrder) {
+                if constexpr (row_kernel_ok<Op>()) {
+                    if (row_sweeps(l)) {
+                        const int th = row_threads(p, v.n);
+                        for (int r = 0; r <= p; ++r) {
+                            const int nj = (v.n - r + p) / (p + 1);
+                            if (nj <= 0) continue;
+                            if (stream_coef)
+                                hipLaunchKernelGGL((k_gs_rowclass<Op, true>), dim3(nj), dim3(th), 0, stream,
+                                                   op, bb, x, r);
+                            else
+                                hipLaunchKernelGGL((k_gs_rowclass<Op, false>), dim3(nj), dim3(th), 0, stream,
+                                                   op, bb, x, r);
+                            ++launches;
+                            if (bytes)
+                                for (int s = 0; s <= p; ++s)
+                                    *bytes += colour_size_host(v.n, p, dim, s + (p + 1) * r) * per_point;
+                        }
+                        return;
+                    }
+                }
+            }
+            for (int c = 0; c < v.ncol; ++c) {
+                int cs = colour_size_host(v.n, p, dim, c);
+                if (cs == 0) continue;
+                if (stream_coef)
+                    hipLaunchKernelGGL((k_gs_colour_sliced<Op, true>), dim3((cs + 63) / 64),
+                                       dim3(64 * Op::NW), 0, stream, op, bb, x, c);
+                else
+                    hipLaunchKernelGGL((k_gs_colour_sliced<Op, false>), dim3((cs + 63) / 64),
+                                       dim3(64 * Op::NW), 0, stream, op, bb, x, c);
+                ++launches;
+                if (bytes) *bytes += cs * per_point;
+            }
+        });
+        check_launch();
+        return launches;
     }
 
     // bc = R rf; xc (optional) zeroed in the same pass
@@ -730,28 +779,13 @@ struct igamg_ctx {
         fill(x, v.N);
         hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(v.N)), dim3(kBlock), 0, stream, bb, (T)1, v.N);
         check_launch();
-        const int W = 2 * p + 1;
-        long long S = (dim == 2) ? W * W : (long long)W * W * W;
-        double per_point = (kind == OP_STENCIL2D ? (double)S : 0.0) * sizeof(T) + 3.0 * sizeof(T);
         int total = 0;
         double tot_bytes = 0.0;
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         IGAMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         try {
-            with_op<T>(l, [&](auto op) {
-                using Op = decltype(op);
-                for (int sw = 0; sw < nsweeps; ++sw)
-                    for (int c = 0; c < v.ncol; ++c) {
-                        int cs = colour_size_host(v.n, p, dim, c);
-                        if (cs == 0) continue;
-                        hipLaunchKernelGGL((k_gs_colour_sliced<Op>), dim3((cs + 63) / 64), dim3(64 * Op::NW),
-                                           0, stream, op, (const T*)bb, x, c);
-                        tot_bytes += cs * per_point;
-                        ++total;
-                    }
-            });
-            check_launch();
+            for (int sw = 0; sw < nsweeps; ++sw) total += mc_sweep<T>(l, bb, x, &tot_bytes);
         } catch (...) {
             (void)hipStreamEndCapture(stream, &g);
             if (g) (void)hipGraphDestroy(g);
@@ -1876,6 +1910,7 @@ void igamg_options_default(igamg_options* opt) {
     opt->tail_items = 32;
     opt->stored_stencil = 0;
     opt->mu = 1;
+    opt->row_sweeps = 1;
     opt->stream = nullptr;
 }
 

@@ -386,6 +386,156 @@ __global__ void __launch_bounds__(64 * Op::NW) k_gs_colour_sliced(Op A,
     gs_colour_body<Op, kStream>(A, b, x, c, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
+// ---- row-class multicolour Gauss-Seidel (stored 2D stencils) ---------------
+//
+// The colours (ci, r), ci = 0..p, of one row class r are the points of the
+// rows j = r (mod p+1).  Rows of one class lie p+1 apart, beyond the stencil's
+// reach, so colour (ci, r) meets the values updated earlier in the class only
+// along its own row, and no row that it reads from another class is written
+// while the class is swept.  One workgroup per row of the class therefore runs
+// the p+1 colour steps in order, separated by workgroup barriers, with the
+// iterates of rows j-p..j+p staged in LDS: the result is that of p+1 separate
+// colour passes (same products and sums in the same order), in one launch.
+//
+// One lane per point keeps every coefficient load a contiguous 64-value
+// segment.  The coefficients of the next kRowDepth colour steps are loaded
+// ahead into a ring of register sets and stay in flight across the LDS-only
+// barriers, as far as the register file allows.
+
+constexpr int kRowThreads = 512;
+constexpr int kRowPadL = 8;          // zero columns left of column 0 (>= p)
+constexpr int kRowMaxStride = 1056;  // LDS row stride limit: n <= kRowMaxStride - 2 kRowPadL
+
+__host__ __device__ constexpr int row_stride(int n) { return (n + 2 * kRowPadL + 3) & ~3; }
+__host__ __device__ constexpr int row_max_n() { return kRowMaxStride - 2 * kRowPadL; }
+__host__ __device__ constexpr int row_points(int p, int n) { return (n + p) / (p + 1); }
+// One point of every colour step per lane, in one workgroup.
+__host__ __device__ constexpr bool row_fits(int p, int n) {
+    return n <= row_max_n() && row_points(p, n) <= kRowThreads;
+}
+__host__ __device__ constexpr int row_threads(int p, int n) { return ((row_points(p, n) + 63) / 64) * 64; }
+
+template <class Op>
+struct RowRegs {
+    typename Op::T cv[Op::S];
+    typename Op::T bv;
+};
+// Degrees where one launch per row class was measured faster than one per
+// colour on the 1024^2 annulus hierarchy (p <= 4, both precisions; at p = 5
+// the per-point coefficient registers leave no room to load ahead and the
+// per-colour launches are as fast or faster).
+template <class Op>
+constexpr bool row_kernel_ok() {
+    return Op::kP <= 4 && (Op::S + 1) * (int)sizeof(typename Op::T) / 4 <= 170;
+}
+// Colour steps loaded ahead of the one being updated (register budget of the
+// ring: about half of the 256 registers a lane has at 512 threads).
+template <class Op>
+constexpr int row_depth() {
+    constexpr int per = (Op::S + 1) * (int)sizeof(typename Op::T) / 4;
+    constexpr int d = 120 / per - 1;
+    return d < 0 ? 0 : (d > Op::kP ? Op::kP : d);
+}
+
+// Loads of colour step s for point ii of the row: unconditional (threads past
+// the colour's points load a valid entry they do not use), so each wait
+// counts only the loads issued before it.  32-bit byte offsets from the
+// uniform coefficient base (the host keeps a level's coefficients below
+// 4 GiB) need one register per load in flight.
+template <class Op, bool kStream>
+__device__ __forceinline__ void row_fetch(const Op& A, const typename Op::T* bj, int r, int jj, int s, int ii,
+                                          RowRegs<Op>& q) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, S = Op::S;
+    const int n = A.n, ni = (n - s + P) / (P + 1);
+    const int iic = min(ii, max(ni - 1, 0));
+    const int c = s + (P + 1) * r;
+    const char* base = (const char*)A.coef;
+    const unsigned pt_off = (unsigned)(((size_t)c * S * A.ncp + (size_t)ni * jj + iic) * sizeof(T));
+    const unsigned col = (unsigned)(A.ncp * sizeof(T));
+#pragma unroll
+    for (int o = 0; o < S; ++o) {
+        const T* ptr = (const T*)(base + (pt_off + (unsigned)o * col));
+        q.cv[o] = kStream ? stream_load(ptr) : *ptr;
+    }
+    q.bv = bj[min(s + (P + 1) * iic, n - 1)];
+}
+
+// Gauss-Seidel update of point ii of colour step s of the staged row.
+template <class Op>
+__device__ __forceinline__ void row_update(const typename Op::T* xs, typename Op::T* xrow, int RS, int s,
+                                           int ii, int ni, const RowRegs<Op>& q) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W;
+    if (ii >= ni) return;
+    const int i = s + (P + 1) * ii;
+    T acc = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const T* xr = xs + w * RS + kRowPadL + i - P;
+        T sl = 0;
+#pragma unroll
+        for (int a = 0; a < W; ++a) sl = fma(q.cv[w * W + a], xr[a], sl);
+        acc += sl;
+    }
+    xrow[i] = xrow[i] + (q.bv - acc) / q.cv[P * W + P];
+}
+
+// Rows j-P..j+P of x into the LDS row store (zero outside the grid and in
+// the pads), kRowStageBatch values per thread at a time: the loads of a
+// batch are issued together (clamped addresses), then stored.
+constexpr int kRowStageBatch = 8;
+template <typename T, int P>
+__device__ __forceinline__ void row_stage(const T* __restrict__ x, int n, int j, int RS, T* xs) {
+    constexpr int W = 2 * P + 1;
+    const int total = W * RS, bd = blockDim.x;
+    for (int e0 = threadIdx.x; e0 < total; e0 += kRowStageBatch * bd) {
+        T v[kRowStageBatch];
+        bool ok[kRowStageBatch];
+#pragma unroll
+        for (int k = 0; k < kRowStageBatch; ++k) {
+            const int e = min(e0 + k * bd, total - 1);
+            const int w = e / RS, i = e - w * RS - kRowPadL, jr = j + w - P;
+            ok[k] = jr >= 0 && jr < n && i >= 0 && i < n;
+            const unsigned off = (unsigned)(clampi(jr, 0, n - 1) * n + clampi(i, 0, n - 1)) * (unsigned)sizeof(T);
+            v[k] = *(const T*)((const char*)x + off);
+        }
+#pragma unroll
+        for (int k = 0; k < kRowStageBatch; ++k) {
+            const int e = e0 + k * bd;
+            if (e < total) xs[e] = ok[k] ? v[k] : (T)0;
+        }
+    }
+}
+
+template <class Op, bool kStream = true>
+__global__ void __launch_bounds__(kRowThreads) k_gs_rowclass(Op A, const typename Op::T* __restrict__ b,
+                                                             typename Op::T* __restrict__ x, int r) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W, D = row_depth<Op>();
+    __shared__ __align__(16) T xs[W * kRowMaxStride];
+    const int n = A.n, RS = row_stride(n);
+    const int jj = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int j = r + (P + 1) * jj;
+    const T* bj = b + (size_t)j * n;
+    const int t = threadIdx.x;
+    RowRegs<Op> q[D + 1];
+#pragma unroll
+    for (int s = 0; s <= D; ++s) row_fetch<Op, kStream>(A, bj, r, jj, s, t, q[s]);
+    row_stage<T, P>(x, n, j, RS, xs);
+    __syncthreads();
+    T* xrow = xs + P * RS + kRowPadL;
+#pragma unroll
+    for (int s = 0; s <= P; ++s) {
+        const int ni = (n - s + P) / (P + 1);
+        row_update<Op>(xs, xrow, RS, s, t, ni, q[s % (D + 1)]);
+        if (s + D + 1 <= P) row_fetch<Op, kStream>(A, bj, r, jj, s + D + 1, t, q[s % (D + 1)]);
+        __syncthreads();
+    }
+    T* xj = x + (size_t)j * n;
+    for (int i = t; i < n; i += blockDim.x) xj[i] = xrow[i];
+}
+
 template <class Op, typename Tout>
 __device__ __forceinline__ void residual_body(const Op& A, const typename Op::T* __restrict__ b,
                                               const typename Op::T* __restrict__ x,

@@ -34,7 +34,7 @@ class Options(ctypes.Structure):
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("n_el_coarsest", ctypes.c_int), ("use_graphs", ctypes.c_int),
                 ("tail_items", ctypes.c_int), ("stored_stencil", ctypes.c_int),
-                ("mu", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("mu", ctypes.c_int), ("row_sweeps", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):

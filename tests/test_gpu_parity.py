@@ -369,3 +369,25 @@ def test_lexicographic_c1_solve(method):
     st, _ = s.solve(x, tol=1e-10, max_restarts=200, method=method, q=5)
     assert st.vcycles == st_r.vcycles
     assert rel(host(x), xo) < 1e-11
+
+
+@pytest.mark.parametrize("geom,n_el,p,extra", [("annulus", 64, 1, {}), ("annulus", 64, 2, {}),
+                                               ("annulus", 128, 3, {}), ("annulus", 32, 4, {}),
+                                               ("annulus", 64, 5, {}), ("square", 64, 2, {"stored_stencil": 1}),
+                                               ("annulus", 1024, 3, {})])
+@pytest.mark.parametrize("prec", [igamg.FP64, igamg.FP32_IR])
+def test_row_class_sweeps_equal_colour_passes(geom, n_el, p, extra, prec):
+    """Sweeping the p+1 colours of a row class in one launch gives the same
+    V-cycle iterates, bit for bit, as one launch per colour (every level
+    multi-block, so every level's sweeps go through the kernel under test)."""
+    out = []
+    for rows in (0, 1):
+        print("[rows] %s n_el=%d p=%d prec=%d rows=%d" % (geom, n_el, p, prec, rows), flush=True)
+        s = igamg.Solver(GEOM[geom], n_el, p, tail_items=0, precision=prec, row_sweeps=rows, **extra)
+        s.set_rhs_field(modes_for(geom, 2000 + p))
+        x = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+        for _ in range(2 if n_el >= 1024 else 3):
+            s.vcycle(x)
+        out.append(host(x))
+        s.close()
+    assert np.array_equal(out[0], out[1])
