@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # Counter-derived HBM traffic per launch of the finest-level row-class sweep (FETCH_SIZE x 2.0
 # + WRITE_SIZE, calibrated on a 1 GiB copy), from the committed counter profile of that
 # kernel.  Valid only for the kernel as profiled; entries are removed when the kernel changes.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {(3, "double"): 119.67e6, (3, "float"): 58.65e6}
 TOL = 1e-10
 Q = 5
 N_EL = 1024
@@ -285,6 +285,8 @@ def main():
     ap.add_argument("--tail-items", type=int, default=-1,
                     help="single-workgroup V-cycle threshold (0 = one launch per step everywhere, "
                          "-1 = autotuned per precision)")
+    ap.add_argument("--colour-launches", action="store_true",
+                    help="with --only-smoother: one launch per colour instead of per row class")
     ap.add_argument("--only-smoother", action="store_true",
                     help="setup + finest-level smoother sweeps only (for kernel profiling)")
     args = ap.parse_args()
@@ -306,10 +308,13 @@ def main():
 
     if args.only_smoother:
         p = args.degree
-        s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p)
+        s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p, row_sweeps=0 if args.colour_launches else 1)
         out = {}
         for prec, name in ((igamg.FP64, "fp64"), (igamg.FP32_IR, "fp32")):
             out[name] = smoother_roofline(s, igamg, prec, nsweeps=16)
+            if args.colour_launches:
+                out[name]["kernel"] = "k_gs_colour_sliced (one launch per colour)"
+                out[name]["traffic"] = None
         # a plain copy of known size (calibration of the traffic counters)
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
         bcopy = torch.empty_like(a)
