@@ -1483,91 +1483,123 @@ __device__ __forceinline__ void pf_point(const f4v (&cq)[rec_len(P) / 4], const 
     d = cq[(P * W + P) / 4][(P * W + P) % 4];
 }
 
-template <int P, int S0 = 0>
-__device__ __forceinline__ void pf_point_phase(const f4v (&cq)[rec_len(P) / 4], const float* xr, int RS,
-                                               int s0, float& acc, float& d) {
-    if constexpr (S0 < 3) {
-        if (s0 != S0) {
-            pf_point_phase<P, S0 + 1>(cq, xr, RS, s0, acc, d);
-            return;
-        }
-    }
-    pf_point<P, S0>(cq, xr + (S0 - s0), RS, acc, d);
+// Register sets of the prefetching sequence: colours c and c + R - 1 are
+// loaded into slots c % R and (c + R - 1) % R.  R divides the colour count,
+// so a colour uses the same slot in every sweep and the slot of each step is
+// known at compile time; R - 1 colours are in flight while one is updated,
+// as far as the register file allows (p = 4: none).
+template <int P>
+constexpr int pf_ring() {
+    return P == 1 ? 4 : (P == 2 ? 3 : (P == 3 ? 2 : (P == 4 ? 1 : 2)));
 }
+template <int P>
+struct PfRegs {
+    f4v q[rec_len(P) / 4];
+    float bv;
+    int i, j;
+    bool has;
+};
 
-// Records, right-hand side value and position of this thread's point of the
-// colour of step s (has = false when the colour is smaller than the block).
+// Records, right-hand side value and position of this thread's point of
+// colour c.  The loads are unconditional (threads past the colour's points
+// load the colour's last record and do not use it), so a wait counts only
+// the loads issued before it.
 template <int P>
 __device__ __forceinline__ void pf_fetch(const Stencil2D<P, float>& A, const float* __restrict__ rec,
-                                         const float* __restrict__ b, int s, f4v (&q)[rec_len(P) / 4],
-                                         float& bv, int& i, int& j, bool& has) {
-    constexpr int NC = (P + 1) * (P + 1), RL = rec_len(P);
-    const int n = A.n, k = threadIdx.x;
-    const int c = s % NC, ci = c % (P + 1), cj = c / (P + 1);
+                                         const float* __restrict__ b, int c, PfRegs<P>& g) {
+    constexpr int RL = rec_len(P), S = (2 * P + 1) * (2 * P + 1);
+    const int n = A.n, ci = c % (P + 1), cj = c / (P + 1);
     const int ni = (n - ci + P) / (P + 1), nj = (n - cj + P) / (P + 1);
-    has = k < ni * nj;
-    if (has) {
-        const int jj = k / ni, ii = k - jj * ni;
-        i = ci + (P + 1) * ii;
-        j = cj + (P + 1) * jj;
-        const auto src = as_global(reinterpret_cast<const f4v*>(rec + ((size_t)c * A.ncp + k) * RL));
+    const int k = min((int)threadIdx.x, max(ni * nj - 1, 0));
+    g.has = (int)threadIdx.x < ni * nj;
+    const int jj = k / ni, ii = k - jj * ni;
+    g.i = ci + (P + 1) * ii;
+    g.j = cj + (P + 1) * jj;
+    const float* rp = rec + ((size_t)c * A.ncp + k) * RL;
+    const auto src = as_global(reinterpret_cast<const f4v*>(rp));
+    // S = (2p+1)^2 = 1 (mod 4): S/4 full vectors and one value (loading the
+    // last vector whole would leave loaded values unused, whose registers the
+    // compiler reuses at once, making the next use wait for this load)
 #pragma unroll
-        for (int m = 0; m < RL / 4; ++m) q[m] = src[m];
-        bv = as_global(b)[i + (size_t)n * j];
+    for (int m = 0; m < S / 4; ++m) g.q[m] = src[m];
+    g.q[S / 4][0] = as_global(rp)[S - 1];
+    g.bv = as_global(b)[min(g.i + (size_t)n * g.j, (size_t)n * n - 1)];
+}
+
+// Colour c (compile time) of a sweep with its prefetched data: Gauss-Seidel
+// update (gs) or residual.
+template <int P, int C>
+__device__ __forceinline__ void pf_colour(const Stencil2D<P, float>& A, float* xl, float* __restrict__ r,
+                                          bool gs, const PfRegs<P>& g) {
+    constexpr int PADL = tl_padl(P, 4);
+    const int n = A.n, RS = tl_stride(P, 4, n);
+    if (!g.has) return;
+    const int sc = PADL - P + g.i;  // first window column
+    float acc, d;
+    if constexpr ((P + 1) % 4 == 0) {
+        constexpr int S0 = (PADL - P + C % (P + 1)) % 4;  // window phase of the colour
+        pf_point<P, S0>(g.q, xl + (size_t)g.j * RS + sc - S0, RS, acc, d);
+    } else {
+        pf_point<P, -1>(g.q, xl + (size_t)g.j * RS + sc, RS, acc, d);  // scalar window reads
+    }
+    if (gs) {
+        float* xp = xl + (size_t)(g.j + P) * RS + PADL + g.i;
+        *xp = *xp + (g.bv - acc) / d;
+    } else {
+        as_global(r)[g.i + (size_t)n * g.j] = g.bv - acc;
     }
 }
 
-// Step s of a sequence with its prefetched data: Gauss-Seidel colour
-// (s < ngs, barrier after) or residual colour (barrier after the last step).
+// Colours per unrolled group: a multiple of the ring size and of p+1, so that
+// the slot and the window phase of a colour are known at compile time.
 template <int P>
-__device__ __forceinline__ void pf_step(const Stencil2D<P, float>& A, float* xl, float* __restrict__ r,
-                                        int s, int ngs, int total, const f4v (&q)[rec_len(P) / 4],
-                                        float bq, int pi, int pj, bool ok) {
-    constexpr int NC = (P + 1) * (P + 1), PADL = tl_padl(P, 4);
-    const int n = A.n, RS = tl_stride(P, 4, n);
-    if (ok) {
-        const int c = s % NC;
-        const int sc = PADL - P + pi;  // first window column
-        float acc, d;
-        if constexpr ((P + 1) % 4 == 0) {
-            const int s0 = (PADL - P + c % (P + 1)) % 4;  // window phase of the colour
-            pf_point_phase<P>(q, xl + (size_t)pj * RS + sc - s0, RS, s0, acc, d);
-        } else {
-            pf_point<P, -1>(q, xl + (size_t)pj * RS + sc, RS, acc, d);  // scalar window reads
-        }
-        if (s < ngs) {
-            float* xp = xl + (size_t)(pj + P) * RS + PADL + pi;
-            *xp = *xp + (bq - acc) / d;
-        } else {
-            as_global(r)[pi + (size_t)n * pj] = bq - acc;
-        }
-    }
-    if (s < ngs || s == total - 1) __syncthreads();
+constexpr int pf_group() {
+    constexpr int R = pf_ring<P>();
+    int u = P + 1;
+    while (u % R != 0) u += P + 1;
+    return u;
+}
+
+template <int P, int U = 0>
+__device__ __forceinline__ void pf_group_colours(const Stencil2D<P, float>& A, const float* __restrict__ rec,
+                                                 const float* __restrict__ b, float* xl,
+                                                 float* __restrict__ r, bool gs, int c0,
+                                                 PfRegs<P> (&ring)[pf_ring<P>()]) {
+    constexpr int NC = (P + 1) * (P + 1), R = pf_ring<P>();
+    const int c = c0 + U;
+    pf_fetch<P>(A, rec, b, (c + R - 1) % NC, ring[(U + R - 1) % R]);
+    pf_colour<P, U>(A, xl, r, gs, ring[U % R]);
+    if (gs || c == NC - 1) __syncthreads();
+    if constexpr (U + 1 < pf_group<P>()) pf_group_colours<P, U + 1>(A, rec, b, xl, r, gs, c0, ring);
+}
+
+// One sweep: groups of pf_group colours, the groups in a (not unrolled) loop.
+template <int P>
+__device__ __forceinline__ void pf_sweep(const Stencil2D<P, float>& A, const float* __restrict__ rec,
+                                         const float* __restrict__ b, float* xl, float* __restrict__ r,
+                                         bool gs, PfRegs<P> (&ring)[pf_ring<P>()]) {
+    constexpr int NC = (P + 1) * (P + 1), R = pf_ring<P>(), U = pf_group<P>();
+    static_assert(NC % R == 0 && NC % U == 0 && U % (P + 1) == 0, "colour grouping");
+#pragma unroll 1
+    for (int c0 = 0; c0 < NC; c0 += U) pf_group_colours<P>(A, rec, b, xl, r, gs, c0, ring);
 }
 
 // nsw Gauss-Seidel sweeps (a barrier after every colour), then, if resid,
-// r = b - A x over all colours (one barrier at the end).  The records of step
-// s + 1 are loaded before step s computes, into the other of two register
-// sets, and stay in flight across the LDS-only barriers.
+// r = b - A x over all colours (one barrier at the end).  The records of the
+// next R - 1 colours are in flight while a colour is updated, across the
+// LDS-only barriers (after the last colour they fetch colours of a sweep
+// that does not come; the loads are valid and unused).
 template <int P>
 __device__ void pf_sequence(const Stencil2D<P, float>& A, const float* __restrict__ rec,
                             const float* __restrict__ b, float* xl, float* __restrict__ r, int nsw,
                             bool resid) {
-    constexpr int NC = (P + 1) * (P + 1), NQ = rec_len(P) / 4;
-    const int ngs = nsw * NC, total = ngs + (resid ? NC : 0);
-    if (total == 0) return;
-    f4v qa[NQ], qb[NQ];
-    float ba = 0.f, bb = 0.f;
-    int ia = 0, ja = 0, ib = 0, jb = 0;
-    bool oka = false, okb = false;
-    pf_fetch<P>(A, rec, b, 0, qa, ba, ia, ja, oka);
-    for (int s = 0; s < total; s += 2) {
-        if (s + 1 < total) pf_fetch<P>(A, rec, b, s + 1, qb, bb, ib, jb, okb);
-        pf_step<P>(A, xl, r, s, ngs, total, qa, ba, ia, ja, oka);
-        if (s + 1 >= total) break;
-        if (s + 2 < total) pf_fetch<P>(A, rec, b, s + 2, qa, ba, ia, ja, oka);
-        pf_step<P>(A, xl, r, s + 1, ngs, total, qb, bb, ib, jb, okb);
-    }
+    constexpr int R = pf_ring<P>();
+    const int nsweeps = nsw + (resid ? 1 : 0);
+    if (nsweeps == 0) return;
+    PfRegs<P> ring[R];
+#pragma unroll
+    for (int c = 0; c + 1 < R; ++c) pf_fetch<P>(A, rec, b, c, ring[c]);
+    for (int sw = 0; sw < nsweeps; ++sw) pf_sweep<P>(A, rec, b, xl, r, sw < nsw, ring);
 }
 
 template <int P, typename T>
