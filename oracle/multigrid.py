@@ -83,7 +83,13 @@ class Hierarchy:
             levels.insert(0, Level(Ac, ne, p, dim))
         self.levels = levels
         A0 = levels[0].A.toarray()
-        self.coarse_chol = sla.cho_factor(A0, lower=True)
+        # Cholesky for the symmetric operators, LU with partial pivoting for
+        # the nonsymmetric ones (convection terms of the full elliptic problem)
+        self.symmetric = np.allclose(A0, A0.T, rtol=0.0, atol=1e-13 * np.abs(A0).max())
+        if self.symmetric:
+            self.coarse_chol = sla.cho_factor(A0, lower=True)
+        else:
+            self.coarse_lu = sla.lu_factor(A0)
         self.p = p
         self.dim = dim
 
@@ -92,8 +98,18 @@ class Hierarchy:
         return self.levels[-1]
 
     def coarse_solve(self, b):
-        """Direct solve on the coarsest grid by dense Cholesky (Algorithm 2)."""
-        return sla.cho_solve(self.coarse_chol, b)
+        """Direct solve on the coarsest grid (Algorithm 2): dense Cholesky, or LU
+        for a nonsymmetric operator."""
+        if self.symmetric:
+            return sla.cho_solve(self.coarse_chol, b)
+        return sla.lu_solve(self.coarse_lu, b)
+
+
+def build_elliptic_hierarchy(kind, n_el, p, cset, r_in=1.0, r_out=2.0, n_el_coarsest=4):
+    """Hierarchy of the full elliptic operator of Section 5 (oracle.elliptic)."""
+    from . import elliptic
+    A = elliptic.assemble(n_el, p, kind, cset, r_in, r_out)
+    return Hierarchy(A, n_el, p, 2, n_el_coarsest)
 
 
 def build_hierarchy(geometry, n_el, p, n_el_coarsest=4):
