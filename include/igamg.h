@@ -48,20 +48,37 @@ typedef enum {
     IGAMG_ENONFINITE = -7   /* NaN or Inf met in the data or the iteration      */
 } igamg_status;
 
-/* Geometry of Section 4: the unit square and cube use Kronecker operators
- * built from 1D stiffness and mass matrices; the quarter annulus (radii 1 and
- * 2) is the degree-2 B-spline surface F(xi, eta) = (1 + xi)(1 - eta^2, 2 eta - eta^2)
- * and stores (2p+1)^2 stencil coefficients per unknown. */
+/* Geometry of Sections 4 and 5: the unit square and cube use Kronecker
+ * operators built from 1D stiffness and mass matrices (for the Poisson
+ * operator); the quarter annulus of radii r_in < r_out is the degree-2 B-spline
+ * surface F(xi, eta) = (r_in + (r_out - r_in) xi)(1 - eta^2, 2 eta - eta^2)
+ * (radii 1 and 2 by default) and stores (2p+1)^2 stencil coefficients per
+ * unknown; QUARTER_ANNULUS_EXACT is its rational (NURBS) counterpart, weights
+ * (1, 1/sqrt 2, 1) in eta, whose arcs are exact circles. */
 typedef enum {
     IGAMG_UNIT_SQUARE = 0,
     IGAMG_QUARTER_ANNULUS = 1,
-    IGAMG_UNIT_CUBE = 2
+    IGAMG_UNIT_CUBE = 2,
+    IGAMG_QUARTER_ANNULUS_EXACT = 3
 } igamg_geom_kind;
 
 typedef struct {
-    int kind;   /* igamg_geom_kind                               */
-    int n_el;   /* elements per direction on the finest level    */
+    int kind;      /* igamg_geom_kind                                        */
+    int n_el;      /* elements per direction on the finest level             */
+    double r_in;   /* annulus radii (both 0: 1 and 2); ignored otherwise     */
+    double r_out;
 } igamg_geometry;
+
+/* Operator (Section 5).  POISSON: -Laplace.  ELLIPTIC_1 and ELLIPTIC_2:
+ * -div(A grad u) + B . grad u + c u with
+ *   A = [[(2 + cos x)(1 + y), cos(x+y) sin(x+y)], [cos(x+y) sin(x+y), (2 + sin y)(1 + x)]],
+ *   ELLIPTIC_1 (the unit-square problem): B = (11 + sin x + y sin x - 2 cos^2(x+y),
+ *              -9 - cos y - x cos y - 2 cos^2(x+y)), c = 1;
+ *   ELLIPTIC_2 (the quarter-annulus problem): B = (-5y, 5x), c = xy;
+ * row I of the matrix is a(phi_J, phi_I), a(u, v) = int A grad u.grad v +
+ * (B.grad u) v + c u v: nonsymmetric.  2D only; these operators are assembled
+ * as stored stencils on either geometry. */
+typedef enum { IGAMG_PDE_POISSON = 0, IGAMG_PDE_ELLIPTIC_1 = 1, IGAMG_PDE_ELLIPTIC_2 = 2 } igamg_pde;
 
 /* Smoothers of Algorithm 2.  MCGS: multicolour Gauss-Seidel with (p+1)^d
  * colours c(I) = sum_d (i_d mod (p+1)) (p+1)^d swept in increasing order;
@@ -100,6 +117,8 @@ typedef struct {
                             l-1's cycle mu times on the same coarse right-hand
                             side (1: V-cycle, 2: W-cycle; 1..4; default 1).
                             Batches and smoother training need mu = 1.       */
+    int pde;             /* igamg_pde (default POISSON); batches and the
+                            learned smoother need POISSON                     */
     int row_sweeps;      /* stored stencils: sweep the p+1 colours of a row
                             class (rows j = r mod p+1) in one launch, one
                             workgroup per row (default 1); 0: one launch per
@@ -146,6 +165,12 @@ igamg_status igamg_level_ndof(const igamg_ctx* ctx, int level, long long* n);
  * (a, k, l, m, phi) in 3D (host memory).  get_rhs copies b to a device buffer. */
 igamg_status igamg_set_rhs(igamg_ctx* ctx, const double* b, int b_on_device);
 igamg_status igamg_set_rhs_field(igamg_ctx* ctx, const double* modes, int n_modes);
+/* Right-hand side of the context's Section 5 problem, assembled like
+ * set_rhs_field: ELLIPTIC_1: f = 1; ELLIPTIC_2: f = -div(A grad u) + B.grad u + c u
+ * of the manufactured solution u = (x^2 + y^2 - 0.2^2)(x^2 + y^2 - 1) sin x sin y
+ * (which vanishes on the boundary of QUARTER_ANNULUS_EXACT with radii 0.2 and
+ * 1).  EINVAL for the Poisson operator. */
+igamg_status igamg_set_rhs_builtin(igamg_ctx* ctx);
 igamg_status igamg_get_rhs(igamg_ctx* ctx, double* b_dev);
 
 /* Switches the form of G between FP64 and FP32_IR (both operator copies are

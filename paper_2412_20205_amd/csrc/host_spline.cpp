@@ -339,6 +339,40 @@ std::vector<double> inverse_from_cholesky(const std::vector<double>& L, int n) {
     return X;
 }
 
+bool inverse_lu(const std::vector<double>& A, int n, std::vector<double>& inv) {
+    std::vector<double> M(A);
+    inv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    double scale = 0.0;
+    for (double v : A) scale = std::max(scale, std::fabs(v));
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(M[(size_t)i * n + k]) > std::fabs(M[(size_t)piv * n + k])) piv = i;
+        const double d = M[(size_t)piv * n + k];
+        if (!(std::fabs(d) > 1e-14 * scale)) return false;
+        if (piv != k)
+            for (int j = 0; j < n; ++j) {
+                std::swap(M[(size_t)k * n + j], M[(size_t)piv * n + j]);
+                std::swap(inv[(size_t)k * n + j], inv[(size_t)piv * n + j]);
+            }
+        for (int j = 0; j < n; ++j) {
+            M[(size_t)k * n + j] /= d;
+            inv[(size_t)k * n + j] /= d;
+        }
+        for (int i = 0; i < n; ++i) {
+            if (i == k) continue;
+            const double f = M[(size_t)i * n + k];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                M[(size_t)i * n + j] -= f * M[(size_t)k * n + j];
+                inv[(size_t)i * n + j] -= f * inv[(size_t)k * n + j];
+            }
+        }
+    }
+    return true;
+}
+
 }  // namespace igamg
 
 // ---------------------------------------------------------------------------

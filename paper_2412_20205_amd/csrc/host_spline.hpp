@@ -74,5 +74,8 @@ Band1D galerkin_band(const Band1D& Af, const TransferTables& T, int p);
 bool cholesky_inplace(std::vector<double>& A, int n);
 // A^{-1} from its Cholesky factor (row-major n x n).
 std::vector<double> inverse_from_cholesky(const std::vector<double>& L, int n);
+// Inverse of a dense row-major n x n matrix by Gauss-Jordan elimination with
+// partial pivoting (nonsymmetric coarsest operators); false if singular.
+bool inverse_lu(const std::vector<double>& A, int n, std::vector<double>& inv);
 
 }  // namespace igamg

@@ -80,6 +80,19 @@ int colour_size_host(int n, int p, int dim, int c) {
 
 struct igamg_ctx {
     int geom = 0, p = 0, dim = 2, L = 0;
+    double r_in = 1.0, r_out = 2.0;  // annulus radii
+    // geometry and operator for the quadrature kernels
+    GeomParams geom_params() const {
+        GeomParams g;
+        g.kind = geom == IGAMG_QUARTER_ANNULUS ? 1 : (geom == IGAMG_QUARTER_ANNULUS_EXACT ? 2 : 0);
+        g.pde = opt.pde;
+        g.r_in = r_in;
+        g.r_out = r_out;
+        return g;
+    }
+    bool assembled() const {  // stored stencil assembled from quadrature
+        return geom == IGAMG_QUARTER_ANNULUS || geom == IGAMG_QUARTER_ANNULUS_EXACT || opt.pde != 0;
+    }
     OpKind kind = OP_STENCIL2D;
     igamg_options opt{};
     hipStream_t stream = nullptr;
@@ -364,7 +377,7 @@ struct igamg_ctx {
         (void)hipGetDevice(&dev);
         std::string arch = "?";
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
-        return arch + "/" + std::to_string(geom) + "/" + std::to_string(p) + "/" +
+        return arch + "/" + std::to_string(geom) + "/" + std::to_string(opt.pde) + "/" + std::to_string(p) + "/" +
                std::to_string(lv[L].n_el) + "/" + std::to_string(opt.precision);
     }
     void choose_tail() {
@@ -945,8 +958,13 @@ void igamg_ctx::setup_annulus() {
     G.wdet = alloc<double>(nqp);
     G.X = alloc<double>(nqp);
     G.Y = alloc<double>(nqp);
-    hipLaunchKernelGGL(k_geometry_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream, geom, NQ, tabPts,
-                       tabWts, G);
+    if (opt.pde != IGAMG_PDE_POISSON) {
+        G.Bx = alloc<double>(nqp);
+        G.By = alloc<double>(nqp);
+        G.Cw = alloc<double>(nqp);
+    }
+    hipLaunchKernelGGL(k_geometry_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream, geom_params(), NQ,
+                       tabPts, tabWts, G);
     check_launch();
     std::vector<double*> stage(L + 1, nullptr);
     stage[L] = alloc<double>((size_t)f.N * Sn);
@@ -956,7 +974,8 @@ void igamg_ctx::setup_annulus() {
                            f.n_el, nq, tabV, tabD, G, stage[L]);
     });
     check_launch();
-    for (double* a : {G.D11, G.D12, G.D22, G.wdet, G.X, G.Y}) release(a);
+    for (double* a : {G.D11, G.D12, G.D22, G.wdet, G.X, G.Y, G.Bx, G.By, G.Cw})
+        if (a) release(a);
     // Galerkin coarse operators, separable: x pass then y pass
     for (int l = L; l >= 1; --l) {
         Level& fl = lv[l];
@@ -1003,6 +1022,12 @@ void igamg_ctx::setup_annulus() {
             if (i2 < 0 || i2 >= c.n || j2 < 0 || j2 >= c.n) continue;
             A[(size_t)I * n0 + i2 + c.n * j2] = st[(size_t)I * Sn + o];
         }
+    }
+    if (opt.pde != IGAMG_PDE_POISSON) {  // nonsymmetric: LU with partial pivoting
+        std::vector<double> inv;
+        if (!inverse_lu(A, n0, inv)) throw Error(IGAMG_ENOTSPD, "coarsest operator is singular");
+        Ainv0 = upload(inv);
+        return;
     }
     if (!cholesky_inplace(A, n0)) throw Error(IGAMG_ENOTSPD, "coarsest operator is not SPD");
     Ainv0 = upload(inverse_from_cholesky(A, n0));
@@ -1081,9 +1106,15 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
     if (geom == IGAMG_UNIT_SQUARE) {
         kind = OP_KRON2D;
         dim = 2;
-    } else if (geom == IGAMG_QUARTER_ANNULUS) {
+    } else if (geom == IGAMG_QUARTER_ANNULUS || geom == IGAMG_QUARTER_ANNULUS_EXACT) {
         kind = OP_STENCIL2D;
         dim = 2;
+        if (g.r_in != 0.0 || g.r_out != 0.0) {
+            if (!(std::isfinite(g.r_in) && std::isfinite(g.r_out) && g.r_in > 0.0 && g.r_out > g.r_in))
+                throw Error(IGAMG_EINVAL, "annulus radii must satisfy 0 < r_in < r_out");
+            r_in = g.r_in;
+            r_out = g.r_out;
+        }
     } else if (geom == IGAMG_UNIT_CUBE) {
         kind = OP_KRON3D;
         dim = 3;
@@ -1100,15 +1131,19 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
         throw Error(IGAMG_EINVAL, "lexicographic Gauss-Seidel is 2D only");
     if (opt.precision != IGAMG_FP64 && opt.precision != IGAMG_FP32_IR)
         throw Error(IGAMG_EINVAL, "bad precision");
+    if (opt.pde != IGAMG_PDE_POISSON && opt.pde != IGAMG_PDE_ELLIPTIC_1 && opt.pde != IGAMG_PDE_ELLIPTIC_2)
+        throw Error(IGAMG_EINVAL, "unknown operator");
+    if (opt.pde != IGAMG_PDE_POISSON && dim != 2)
+        throw Error(IGAMG_EINVAL, "the full elliptic operators are 2D");
     if (opt.stream) {
         stream = (hipStream_t)opt.stream;
     } else {
         IGAMG_HIP(hipStreamCreateWithFlags(&stream, hipStreamDefault));  // orders against the legacy stream
         own_stream = true;
     }
-    if (kind == OP_KRON2D && opt.stored_stencil) kind = OP_STENCIL2D;
+    if (kind == OP_KRON2D && (opt.stored_stencil || opt.pde != IGAMG_PDE_POISSON)) kind = OP_STENCIL2D;
     setup_levels(g.n_el, levels);
-    if (geom == IGAMG_QUARTER_ANNULUS) {
+    if (assembled()) {
         setup_annulus();
     } else {
         setup_kron();
@@ -1142,12 +1177,14 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
     setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// n_modes < 0: the built-in right-hand side of the context's Section 5 problem.
 void igamg_ctx::set_rhs_field(const double* modes, int n_modes) {
     Level& f = lv[L];
-    std::vector<double> md(modes, modes + (size_t)n_modes * (dim + 2));
+    std::vector<double> md;
+    if (n_modes >= 0) md.assign(modes, modes + (size_t)n_modes * (dim + 2));
     for (double v : md)
         if (!std::isfinite(v)) throw Error(IGAMG_ENONFINITE, "non-finite mode table");
-    double* dmodes = upload(md);
+    double* dmodes = md.empty() ? nullptr : upload(md);
     if (dim == 2) {
         int q = p + 1;
         ElementTables E = element_tables(f.n_el, p, q);
@@ -1164,10 +1201,16 @@ void igamg_ctx::set_rhs_field(const double* modes, int n_modes) {
         G.X = alloc<double>(nqp);
         G.Y = alloc<double>(nqp);
         double* fq = alloc<double>(nqp);
-        hipLaunchKernelGGL(k_geometry_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream,
-                           geom == IGAMG_QUARTER_ANNULUS ? 1 : 0, NQ, pts, wts, G);
-        hipLaunchKernelGGL(k_load_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream, nqp, G, dmodes,
-                           n_modes, fq);
+        GeomParams gp = geom_params();
+        gp.pde = IGAMG_PDE_POISSON;  // only the geometry is needed
+        hipLaunchKernelGGL(k_geometry_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream, gp, NQ, pts, wts,
+                           G);
+        if (n_modes >= 0)
+            hipLaunchKernelGGL(k_load_qp, dim3(grid_for(nqp)), dim3(kBlock), 0, stream, nqp, G, dmodes,
+                               n_modes, fq);
+        else
+            hipLaunchKernelGGL(k_load_qp_builtin, dim3(grid_for(nqp)), dim3(kBlock), 0, stream, nqp, G,
+                               opt.pde, fq);
         hipLaunchKernelGGL(k_assemble_load2d, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, f.n_el, p,
                            q, V, fq, b);
         check_launch();
@@ -1185,7 +1228,7 @@ void igamg_ctx::set_rhs_field(const double* modes, int n_modes) {
         sync();
         for (double* a : {V, pts, wts}) release(a);
     }
-    release(dmodes);
+    if (dmodes) release(dmodes);
     set_bnorm(vector_norm(b, f.N));
 }
 
@@ -1910,6 +1953,7 @@ void igamg_options_default(igamg_options* opt) {
     opt->tail_items = 32;
     opt->stored_stencil = 0;
     opt->mu = 1;
+    opt->pde = IGAMG_PDE_POISSON;
     opt->row_sweeps = 1;
     opt->stream = nullptr;
 }
@@ -1977,6 +2021,14 @@ igamg_status igamg_set_rhs_field(igamg_ctx* ctx, const double* modes, int n_mode
     return guarded([&] {
         need(ctx && modes && n_modes > 0, "bad mode table");
         ctx->set_rhs_field(modes, n_modes);
+    });
+}
+
+igamg_status igamg_set_rhs_builtin(igamg_ctx* ctx) {
+    return guarded([&] {
+        need(ctx, "null argument");
+        need(ctx->opt.pde != IGAMG_PDE_POISSON, "the Poisson operator has no built-in right-hand side");
+        ctx->set_rhs_field(nullptr, -1);
     });
 }
 
@@ -2258,6 +2310,7 @@ igamg_status igamg_setup_batch(int count, const igamg_geometry* geoms, const int
         else
             igamg_options_default(&o);
         need(o.mu == 1, "batched solves run V-cycles (mu = 1)");
+        need(o.pde == IGAMG_PDE_POISSON, "batched solves take the Poisson operator");
         if (o.stream) {
             B->stream = (hipStream_t)o.stream;
         } else {
@@ -2393,6 +2446,7 @@ igamg_status igamg_train_smoother(igamg_ctx* ctx, const igamg_train_options* o,
     return guarded([&] {
         need(ctx && o, "null argument");
         need(ctx->opt.mu == 1, "the smoother is trained on V-cycles (mu = 1)");
+        need(ctx->opt.pde == IGAMG_PDE_POISSON, "the smoother is trained for the Poisson operator");
         igamg_train_report rep{};
         ctx->train(*o, rep);
         if (report) *report = rep;

@@ -1775,10 +1775,23 @@ __global__ void k_to_records(const float* __restrict__ coef, int ncp, int ncol, 
 // setup kernels (FP64): mapped assembly of the finest stencil, load vector,
 // Galerkin products on stencils, colour-blocked layout
 
-// Quarter annulus as the degree-2 B-spline surface on one element with control
-// net rho_a * {(1,0), (1,1), (0,1)}_b, rho = (1, 1.5, 2).  At every quadrature
-// point stores w |det J| (J^T J)^{-1} (3 entries) and w |det J| (for loads) and
-// the physical point.
+// Geometry and coefficients of a 2D problem assembled from quadrature.
+// kind 0: unit square (identity map); 1: quarter annulus as the polynomial
+// degree-2 B-spline surface on one element with control net
+// rho_a * {(1,0), (1,1), (0,1)}_b, rho = (r_in, (r_in + r_out)/2, r_out);
+// 2: the same net with weights (1, 1/sqrt 2, 1) in eta (rational quadratic,
+// exact circular arcs).  pde 0: -Laplace; 1, 2: -div(A grad u) + B.grad u + c u
+// with the two coefficient sets of Section 5 (unit square: B of its first
+// problem, c = 1; quarter annulus: B = (-5y, 5x), c = xy; the same A).
+struct GeomParams {
+    int kind;
+    int pde;
+    double r_in, r_out;
+};
+
+// At every quadrature point: w |det J| J^-1 A J^-T (D11, D12, D22; A = I for
+// the Laplace operator), w |det J| (for loads), the physical point, and for
+// pde > 0 the reference convection w |det J| J^-1 B (Bx, By) and w |det J| c.
 struct GeomQP {
     double* D11;
     double* D12;
@@ -1786,7 +1799,28 @@ struct GeomQP {
     double* wdet;
     double* X;
     double* Y;
+    double* Bx;  // null for pde 0
+    double* By;
+    double* Cw;
 };
+
+// Coefficients of the Section 5 problems at a physical point (pde 1 or 2).
+__device__ inline void pde_coefficients(int pde, double x, double y, double& a11, double& a12, double& a22,
+                                        double& b1, double& b2, double& c) {
+    a11 = (2.0 + cos(x)) * (1.0 + y);
+    a12 = cos(x + y) * sin(x + y);
+    a22 = (2.0 + sin(y)) * (1.0 + x);
+    if (pde == 1) {
+        const double cc = cos(x + y) * cos(x + y);
+        b1 = 11.0 + sin(x) + y * sin(x) - 2.0 * cc;
+        b2 = -9.0 - cos(y) - x * cos(y) - 2.0 * cc;
+        c = 1.0;
+    } else {
+        b1 = -5.0 * y;
+        b2 = 5.0 * x;
+        c = x * y;
+    }
+}
 
 __device__ inline void bernstein2(double u, double* B, double* dB) {
     B[0] = (1 - u) * (1 - u);
@@ -1797,15 +1831,15 @@ __device__ inline void bernstein2(double u, double* B, double* dB) {
     dB[2] = 2 * u;
 }
 
-__global__ void k_geometry_qp(int geom, int NQ, const double* __restrict__ pts,
+__global__ void k_geometry_qp(GeomParams gp, int NQ, const double* __restrict__ pts,
                               const double* __restrict__ wts, GeomQP G) {
     long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (long long)NQ * NQ) return;
     int qy = (int)(t / NQ), qx = (int)(t - (long long)qy * NQ);
     double xi = pts[qx], eta = pts[qy];
     double J00, J01, J10, J11, X, Y;
-    if (geom == 1) {
-        const double rho[3] = {1.0, 1.5, 2.0};
+    if (gp.kind == 1) {
+        const double rho[3] = {gp.r_in, 0.5 * (gp.r_in + gp.r_out), gp.r_out};
         const double cx[3] = {1.0, 1.0, 0.0}, cy[3] = {0.0, 1.0, 1.0};
         double Bu[3], dBu[3], Bv[3], dBv[3];
         bernstein2(xi, Bu, dBu);
@@ -1821,6 +1855,35 @@ __global__ void k_geometry_qp(int geom, int NQ, const double* __restrict__ pts,
                 J10 += dBu[a] * Bv[b] * py;
                 J11 += Bu[a] * dBv[b] * py;
             }
+    } else if (gp.kind == 2) {
+        // rho(xi) C(eta), C = sum_b w_b B_b (eta) P_b / sum_b w_b B_b(eta)
+        const double rho[3] = {gp.r_in, 0.5 * (gp.r_in + gp.r_out), gp.r_out};
+        const double cx[3] = {1.0, 1.0, 0.0}, cy[3] = {0.0, 1.0, 1.0};
+        const double wb[3] = {1.0, 0.70710678118654752440, 1.0};
+        double Bu[3], dBu[3], Bv[3], dBv[3];
+        bernstein2(xi, Bu, dBu);
+        bernstein2(eta, Bv, dBv);
+        double r = 0.0, dr = 0.0, nx = 0.0, ny = 0.0, dnx = 0.0, dny = 0.0, den = 0.0, dden = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            r += Bu[a] * rho[a];
+            dr += dBu[a] * rho[a];
+        }
+        for (int b = 0; b < 3; ++b) {
+            nx += wb[b] * Bv[b] * cx[b];
+            ny += wb[b] * Bv[b] * cy[b];
+            dnx += wb[b] * dBv[b] * cx[b];
+            dny += wb[b] * dBv[b] * cy[b];
+            den += wb[b] * Bv[b];
+            dden += wb[b] * dBv[b];
+        }
+        const double Cx = nx / den, Cy = ny / den;
+        const double dCx = (dnx - Cx * dden) / den, dCy = (dny - Cy * dden) / den;
+        X = r * Cx;
+        Y = r * Cy;
+        J00 = dr * Cx;
+        J01 = r * dCx;
+        J10 = dr * Cy;
+        J11 = r * dCy;
     } else {
         X = xi;
         Y = eta;
@@ -1830,12 +1893,27 @@ __global__ void k_geometry_qp(int geom, int NQ, const double* __restrict__ pts,
         J11 = 1.0;
     }
     double det = J00 * J11 - J01 * J10;
-    double a = J00 * J00 + J10 * J10, b = J00 * J01 + J10 * J11, c = J01 * J01 + J11 * J11;
     double w = wts[qx] * wts[qy] * fabs(det);
-    double id = 1.0 / (a * c - b * b);
-    G.D11[t] = w * c * id;
-    G.D12[t] = -w * b * id;
-    G.D22[t] = w * a * id;
+    if (gp.pde == 0) {
+        double a = J00 * J00 + J10 * J10, b = J00 * J01 + J10 * J11, c = J01 * J01 + J11 * J11;
+        double id = 1.0 / (a * c - b * b);
+        G.D11[t] = w * c * id;
+        G.D12[t] = -w * b * id;
+        G.D22[t] = w * a * id;
+    } else {
+        // J^-1 = [[J11, -J01], [-J10, J00]] / det; K = J^-1 A J^-T, bh = J^-1 B
+        double a11, a12, a22, b1, b2, cr;
+        pde_coefficients(gp.pde, X, Y, a11, a12, a22, b1, b2, cr);
+        const double i00 = J11 / det, i01 = -J01 / det, i10 = -J10 / det, i11 = J00 / det;
+        const double m00 = i00 * a11 + i01 * a12, m01 = i00 * a12 + i01 * a22;  // J^-1 A
+        const double m10 = i10 * a11 + i11 * a12, m11 = i10 * a12 + i11 * a22;
+        G.D11[t] = w * (m00 * i00 + m01 * i01);
+        G.D12[t] = w * (m00 * i10 + m01 * i11);
+        G.D22[t] = w * (m10 * i10 + m11 * i11);
+        G.Bx[t] = w * (i00 * b1 + i01 * b2);
+        G.By[t] = w * (i10 * b1 + i11 * b2);
+        G.Cw[t] = w * cr;
+    }
     G.wdet[t] = w;
     G.X[t] = X;
     G.Y[t] = Y;
@@ -1880,10 +1958,43 @@ __global__ void k_assemble_stencil(int ne, int nq, const double* __restrict__ V,
                         double gx2 = di2 * vj2, gy2 = vi2 * dj2;
                         acc += G.D11[qi] * gx1 * gx2 + G.D12[qi] * (gx1 * gy2 + gy1 * gx2) +
                                G.D22[qi] * gy1 * gy2;
+                        if (G.Bx) {  // (B . grad phi_{I+o}) phi_I + c phi_{I+o} phi_I
+                            const double v1 = vi * vj, v2 = vi2 * vj2;
+                            acc += (G.Bx[qi] * gx2 + G.By[qi] * gy2) * v1 + G.Cw[qi] * v1 * v2;
+                        }
                     }
             }
     }
     out[t] = acc;
+}
+
+// Built-in right-hand sides of the Section 5 problems at the quadrature points,
+// premultiplied by w |det J|: pde 1: f = 1; pde 2: f of the manufactured solution
+// u = (x^2 + y^2 - 0.2^2)(x^2 + y^2 - 1) sin x sin y, i.e.
+// f = -div(A grad u) + B.grad u + c u written out with u = g s,
+// g = (r^2 - 0.04)(r^2 - 1), s = sin x sin y.
+__global__ void k_load_qp_builtin(long long nqp, GeomQP G, int pde, double* __restrict__ fq) {
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nqp) return;
+    const double x = G.X[t], y = G.Y[t];
+    double f = 1.0;
+    if (pde == 2) {
+        const double r2 = x * x + y * y, h = 2.0 * r2 - 1.04, g = (r2 - 0.04) * (r2 - 1.0);
+        const double gx = 2.0 * x * h, gy = 2.0 * y * h;
+        const double gxx = 8.0 * x * x + 2.0 * h, gyy = 8.0 * y * y + 2.0 * h, gxy = 8.0 * x * y;
+        const double sxv = sin(x), cxv = cos(x), syv = sin(y), cyv = cos(y);
+        const double s = sxv * syv, sx = cxv * syv, sy = sxv * cyv, sxy = cxv * cyv;
+        const double u = g * s, ux = gx * s + g * sx, uy = gy * s + g * sy;
+        const double uxx = gxx * s + 2.0 * gx * sx - g * s, uyy = gyy * s + 2.0 * gy * sy - g * s;
+        const double uxy = gxy * s + gx * sy + gy * sx + g * sxy;
+        double a11, a12, a22, b1, b2, c;
+        pde_coefficients(2, x, y, a11, a12, a22, b1, b2, c);
+        const double a11x = -sxv * (1.0 + y), a12d = cos(2.0 * (x + y)), a22y = cyv * (1.0 + x);
+        const double div = a11x * ux + a11 * uxx + a12d * uy + 2.0 * a12 * uxy + a12d * ux + a22y * uy +
+                           a22 * uyy;
+        f = -div + b1 * ux + b2 * uy + c * u;
+    }
+    fq[t] = f * G.wdet[t];
 }
 
 // f at the quadrature points: f = sum_m a_m sin(pi (k_m x + l_m y) + phi_m),

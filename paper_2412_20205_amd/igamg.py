@@ -19,14 +19,16 @@ LIB_PATH = os.path.join(_HERE, "libigamg.so")
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EBREAKDOWN, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
                 -5: "EBREAKDOWN", -6: "ENOCONV", -7: "ENONFINITE"}
-UNIT_SQUARE, QUARTER_ANNULUS, UNIT_CUBE = 0, 1, 2
+UNIT_SQUARE, QUARTER_ANNULUS, UNIT_CUBE, QUARTER_ANNULUS_EXACT = 0, 1, 2, 3
+PDE_POISSON, PDE_ELLIPTIC_1, PDE_ELLIPTIC_2 = 0, 1, 2
 SMOOTH_MCGS, SMOOTH_LEXGS, SMOOTH_JACOBI, SMOOTH_LEARNED = 0, 1, 2, 3
 EXTRAP_NONE, RRE, MPE = 0, 1, 2
 FP64, FP32_IR = 0, 1
 
 
 class Geometry(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("n_el", ctypes.c_int)]
+    _fields_ = [("kind", ctypes.c_int), ("n_el", ctypes.c_int), ("r_in", ctypes.c_double),
+                ("r_out", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -34,7 +36,8 @@ class Options(ctypes.Structure):
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("n_el_coarsest", ctypes.c_int), ("use_graphs", ctypes.c_int),
                 ("tail_items", ctypes.c_int), ("stored_stencil", ctypes.c_int),
-                ("mu", ctypes.c_int), ("row_sweeps", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("mu", ctypes.c_int), ("pde", ctypes.c_int), ("row_sweeps", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -90,6 +93,7 @@ _SIGNATURES = {
     "igamg_level_ndof": (_i, [_P, _i, ctypes.POINTER(_ll)]),
     "igamg_set_rhs": (_i, [_P, _P, _i]),
     "igamg_set_rhs_field": (_i, [_P, _P, _i]),
+    "igamg_set_rhs_builtin": (_i, [_P]),
     "igamg_get_rhs": (_i, [_P, _P]),
     "igamg_vcycle": (_i, [_P, _P]),
     "igamg_set_precision": (_i, [_P, _i]),
@@ -184,7 +188,7 @@ def default_options(**kw):
 class Solver:
     """One solver context (owns its device data; see include/igamg.h)."""
 
-    def __init__(self, geometry, n_el, degree, levels=0, stream=None, **opts):
+    def __init__(self, geometry, n_el, degree, levels=0, stream=None, radii=(0.0, 0.0), **opts):
         import torch
         if stream is None:
             cs = torch.cuda.current_stream()
@@ -194,7 +198,7 @@ class Solver:
         o = default_options(**opts)
         o.stream = stream
         self._stream_ptr = stream
-        g = Geometry(geometry, n_el)
+        g = Geometry(geometry, n_el, radii[0], radii[1])
         h = _P()
         _check(lib().igamg_setup(ctypes.byref(g), degree, levels, ctypes.byref(o),
                                  ctypes.byref(h)), "igamg_setup")
@@ -252,6 +256,9 @@ class Solver:
         modes = np.ascontiguousarray(modes, dtype=np.float64)
         _check(lib().igamg_set_rhs_field(self._h, _np_ptr(modes), modes.shape[0]),
                "igamg_set_rhs_field")
+
+    def set_rhs_builtin(self):
+        _check(lib().igamg_set_rhs_builtin(self._h), "igamg_set_rhs_builtin")
 
     def get_rhs(self, out):
         _check(lib().igamg_get_rhs(self._h, _ptr(out)), "igamg_get_rhs")
@@ -404,7 +411,7 @@ class Batch:
             cs = torch.cuda.current_stream()
             stream = None if cs.cuda_stream == 0 else cs.cuda_stream
         n = len(problems)
-        geoms = (Geometry * n)(*[Geometry(g, e) for g, e, _ in problems])
+        geoms = (Geometry * n)(*[Geometry(g, e, 0.0, 0.0) for g, e, _ in problems])
         degs = (ctypes.c_int * n)(*[d for _, _, d in problems])
         o = default_options()
         o.stream = stream
