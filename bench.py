@@ -20,7 +20,8 @@ right-hand side already on the device.  Forms timed per degree:
 Extra legs (reported under config, not timed into `value`): the unit square
 64^2 p = 2 and the unit cube 128^3 p = 3 workloads, the batch of 96 problems,
 and the paper's own 2D setting of Table 11 (64^2 elements, 4 levels, weighted
-Jacobi V(1,1)/W(1,1), plain and RRE/MPE, p = 1..5, relative residual 1e-12).
+Jacobi V(1,1)/W(1,1), plain and RRE/MPE, p = 1..5, relative residual 1e-12),
+and the full elliptic problems of Section 5 (Tables 13 and 15; RRE(8)).
 
 The roofline entry is the dominant kernel of the chosen form: one row-class
 launch of the finest-level FP32 multicolour Gauss-Seidel (the p+1 colours of
@@ -202,6 +203,62 @@ def paper_setting_measure(igamg, torch, synth, steps):
     return out
 
 
+# Restart cycles printed in Tables 13 and 15 (RRE(8), tolerance 1e-12), per grid
+# (16, 32, 64 elements per direction) and degree p = 1..5.
+PAPER_TABLE13 = {16: (2, 3, 4, 6, 9), 32: (3, 3, 4, 8, 9), 64: (4, 4, 5, 9, 10)}
+PAPER_TABLE15 = {16: (2, 2, 2, 4, 9), 32: (2, 2, 2, 4, 7), 64: (2, 2, 3, 5, 6)}
+
+
+def elliptic_measure(igamg, torch, steps):
+    """The full elliptic problems of Section 5: the unit square with the first
+    coefficient set and f = 1 (Table 13), and the quarter annulus with exact arcs,
+    radii 0.2 and 1, the second coefficient set and the manufactured solution
+    (Table 15); RRE(8) around FP64 V(2,2) multicolour Gauss-Seidel cycles,
+    relative residual 1e-12; restart cycles and ms per solve beside the paper's
+    counts.  Also the annulus problem at 1024^2, p = 3, RRE(8) around FP32
+    V-cycles in FP64 refinement, relative residual 1e-10."""
+    out = {}
+    probs = (("table13_square", igamg.UNIT_SQUARE, igamg.PDE_ELLIPTIC_1, (0.0, 0.0), PAPER_TABLE13),
+             ("table15_annulus", igamg.QUARTER_ANNULUS_EXACT, igamg.PDE_ELLIPTIC_2, (0.2, 1.0), PAPER_TABLE15))
+    for name, g, pde, radii, paper in probs:
+        rows = {}
+        for ne in (16, 32, 64):
+            row = {}
+            for p in range(1, 6):
+                s = igamg.Solver(g, ne, p, radii=radii, pde=pde)
+                s.set_rhs_builtin()
+                x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
+                s.solve(x, tol=1e-12, max_restarts=500, method=igamg.RRE, q=8)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    x.zero_()
+                    st, _ = s.solve(x, tol=1e-12, max_restarts=500, method=igamg.RRE, q=8)
+                torch.cuda.synchronize()
+                row["p%d" % p] = {"restarts": st.restarts, "vcycles": st.vcycles,
+                                  "ms": round((time.perf_counter() - t0) * 1e3 / steps, 3),
+                                  "paper_restarts": paper[ne][p - 1]}
+                s.close()
+            rows["n_el_%d" % ne] = row
+        out[name] = rows
+    s = igamg.Solver(igamg.QUARTER_ANNULUS_EXACT, N_EL, 3, radii=(0.2, 1.0), pde=igamg.PDE_ELLIPTIC_2,
+                     precision=igamg.FP32_IR)
+    s.set_rhs_builtin()
+    x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
+    s.solve(x, tol=TOL, max_restarts=500, method=igamg.RRE, q=8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        st, _ = s.solve(x, tol=TOL, max_restarts=500, method=igamg.RRE, q=8)
+    torch.cuda.synchronize()
+    out["annulus_1024_p3_fp32ir_rre8"] = {"ms": round((time.perf_counter() - t0) * 1e3 / steps, 3),
+                                          "vcycles": st.vcycles, "restarts": st.restarts,
+                                          "rel_residual": st.rel_residual}
+    s.close()
+    return out
+
+
 def c3_measure(igamg, torch, synth, steps):
     """Unit cube, p = 3, 128^3 elements, f = 3 pi^2 prod sin(pi x_d), V(2,2)
     multicolour GS (64 colours): plain FP64 V-cycles, FP64 MPE(4), and MPE(4)
@@ -280,6 +337,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-c1c3", action="store_true")
     ap.add_argument("--no-paper-setting", action="store_true")
+    ap.add_argument("--no-elliptic", action="store_true")
     ap.add_argument("--only-batch", action="store_true")
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--tail-items", type=int, default=-1,
@@ -404,6 +462,11 @@ def main():
         log("[bench] paper setting: unit square 64^2, Jacobi V(1,1)/W(1,1), p = 1..5")
         paper = paper_setting_measure(igamg, torch, synth, max(1, args.steps // 2))
 
+    elliptic = None
+    if not args.no_elliptic:
+        log("[bench] full elliptic problems (Tables 13, 15)")
+        elliptic = elliptic_measure(igamg, torch, max(1, args.steps // 2))
+
     batch = None
     if not args.no_batch:
         log("[bench] batch of 96 problems")
@@ -450,7 +513,8 @@ def main():
                    "batch": batch,
                    "unit_square_64_p2": c1,
                    "unit_cube_128_p3": c3,
-                   "paper_setting_square64_jacobi": paper},
+                   "paper_setting_square64_jacobi": paper,
+                   "full_elliptic": elliptic},
         "roofline": headline["smoother_fp32"],
         "cpu_baseline": cpu,
     }
