@@ -207,24 +207,27 @@ def paper_setting_measure(igamg, torch, synth, steps):
 # (16, 32, 64 elements per direction) and degree p = 1..5.
 PAPER_TABLE13 = {16: (2, 3, 4, 6, 9), 32: (3, 3, 4, 8, 9), 64: (4, 4, 5, 9, 10)}
 PAPER_TABLE15 = {16: (2, 2, 2, 4, 9), 32: (2, 2, 2, 4, 7), 64: (2, 2, 3, 5, 6)}
+PAPER_TABLE14 = {16: (2, 2, 4, 6), 32: (2, 2, 4, 5), 64: (2, 2, 3, 6)}   # p = 1..4
 
 
 def elliptic_measure(igamg, torch, steps):
     """The full elliptic problems of Section 5: the unit square with the first
-    coefficient set and f = 1 (Table 13), and the quarter annulus with exact arcs,
+    coefficient set and f = 1 (Table 13), the quarter annulus with exact arcs,
     radii 0.2 and 1, the second coefficient set and the manufactured solution
-    (Table 15); RRE(8) around FP64 V(2,2) multicolour Gauss-Seidel cycles,
+    (Table 15), and the advection-diffusion problem with f = 1 (Table 14); RRE(8) around FP64 V(2,2) multicolour Gauss-Seidel cycles,
     relative residual 1e-12; restart cycles and ms per solve beside the paper's
     counts.  Also the annulus problem at 1024^2, p = 3, RRE(8) around FP32
     V-cycles in FP64 refinement, relative residual 1e-10."""
     out = {}
     probs = (("table13_square", igamg.UNIT_SQUARE, igamg.PDE_ELLIPTIC_1, (0.0, 0.0), PAPER_TABLE13),
-             ("table15_annulus", igamg.QUARTER_ANNULUS_EXACT, igamg.PDE_ELLIPTIC_2, (0.2, 1.0), PAPER_TABLE15))
+             ("table15_annulus", igamg.QUARTER_ANNULUS_EXACT, igamg.PDE_ELLIPTIC_2, (0.2, 1.0), PAPER_TABLE15),
+             ("table14_advection_diffusion", igamg.UNIT_SQUARE, igamg.PDE_ADVECTION_DIFFUSION, (0.0, 0.0),
+              PAPER_TABLE14))
     for name, g, pde, radii, paper in probs:
         rows = {}
         for ne in (16, 32, 64):
             row = {}
-            for p in range(1, 6):
+            for p in range(1, len(paper[ne]) + 1):
                 s = igamg.Solver(g, ne, p, radii=radii, pde=pde)
                 s.set_rhs_builtin()
                 x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")

@@ -75,10 +75,16 @@ typedef struct {
  *   ELLIPTIC_1 (the unit-square problem): B = (11 + sin x + y sin x - 2 cos^2(x+y),
  *              -9 - cos y - x cos y - 2 cos^2(x+y)), c = 1;
  *   ELLIPTIC_2 (the quarter-annulus problem): B = (-5y, 5x), c = xy;
+ *   ADVECTION_DIFFUSION: -0.1 Laplace u + (1, 1) . grad u (A = 0.1 I, c = 0);
  * row I of the matrix is a(phi_J, phi_I), a(u, v) = int A grad u.grad v +
  * (B.grad u) v + c u v: nonsymmetric.  2D only; these operators are assembled
  * as stored stencils on either geometry. */
-typedef enum { IGAMG_PDE_POISSON = 0, IGAMG_PDE_ELLIPTIC_1 = 1, IGAMG_PDE_ELLIPTIC_2 = 2 } igamg_pde;
+typedef enum {
+    IGAMG_PDE_POISSON = 0,
+    IGAMG_PDE_ELLIPTIC_1 = 1,
+    IGAMG_PDE_ELLIPTIC_2 = 2,
+    IGAMG_PDE_ADVECTION_DIFFUSION = 3
+} igamg_pde;
 
 /* Smoothers of Algorithm 2.  MCGS: multicolour Gauss-Seidel with (p+1)^d
  * colours c(I) = sum_d (i_d mod (p+1)) (p+1)^d swept in increasing order;
@@ -166,7 +172,7 @@ igamg_status igamg_level_ndof(const igamg_ctx* ctx, int level, long long* n);
 igamg_status igamg_set_rhs(igamg_ctx* ctx, const double* b, int b_on_device);
 igamg_status igamg_set_rhs_field(igamg_ctx* ctx, const double* modes, int n_modes);
 /* Right-hand side of the context's Section 5 problem, assembled like
- * set_rhs_field: ELLIPTIC_1: f = 1; ELLIPTIC_2: f = -div(A grad u) + B.grad u + c u
+ * set_rhs_field: ELLIPTIC_1 and ADVECTION_DIFFUSION: f = 1; ELLIPTIC_2: f = -div(A grad u) + B.grad u + c u
  * of the manufactured solution u = (x^2 + y^2 - 0.2^2)(x^2 + y^2 - 1) sin x sin y
  * (which vanishes on the boundary of QUARTER_ANNULUS_EXACT with radii 0.2 and
  * 1).  EINVAL for the Poisson operator. */

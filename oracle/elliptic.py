@@ -33,6 +33,7 @@ from . import bspline
 CSET_LAPLACE = "laplace"
 CSET_SQUARE = "square"     # Section 5, unit square: A, B of Table 13's problem, c = 1
 CSET_ANNULUS = "annulus"   # Section 5, quarter annulus: same A, B = (-5y, 5x), c = xy
+CSET_ADVDIFF = "advdiff"   # Section 5, advection-diffusion (Table 14): A = 0.1 I, B = (1, 1), c = 0
 
 
 def _A(x, y):
@@ -48,6 +49,9 @@ def coefficients(cset, x, y):
     z = np.zeros_like(x)
     if cset == CSET_LAPLACE:
         return np.ones_like(x), z, np.ones_like(x), z, z, z
+    if cset == CSET_ADVDIFF:
+        eps = np.full_like(x, 0.1)
+        return eps, z, eps, np.ones_like(x), np.ones_like(x), z
     a11, a12, a22 = _A(x, y)
     if cset == CSET_SQUARE:
         cc = np.cos(x + y) ** 2

@@ -1131,7 +1131,7 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
         throw Error(IGAMG_EINVAL, "lexicographic Gauss-Seidel is 2D only");
     if (opt.precision != IGAMG_FP64 && opt.precision != IGAMG_FP32_IR)
         throw Error(IGAMG_EINVAL, "bad precision");
-    if (opt.pde != IGAMG_PDE_POISSON && opt.pde != IGAMG_PDE_ELLIPTIC_1 && opt.pde != IGAMG_PDE_ELLIPTIC_2)
+    if (opt.pde < IGAMG_PDE_POISSON || opt.pde > IGAMG_PDE_ADVECTION_DIFFUSION)
         throw Error(IGAMG_EINVAL, "unknown operator");
     if (opt.pde != IGAMG_PDE_POISSON && dim != 2)
         throw Error(IGAMG_EINVAL, "the full elliptic operators are 2D");

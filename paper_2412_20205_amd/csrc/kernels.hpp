@@ -1782,7 +1782,8 @@ __global__ void k_to_records(const float* __restrict__ coef, int ncp, int ncol, 
 // 2: the same net with weights (1, 1/sqrt 2, 1) in eta (rational quadratic,
 // exact circular arcs).  pde 0: -Laplace; 1, 2: -div(A grad u) + B.grad u + c u
 // with the two coefficient sets of Section 5 (unit square: B of its first
-// problem, c = 1; quarter annulus: B = (-5y, 5x), c = xy; the same A).
+// problem, c = 1; quarter annulus: B = (-5y, 5x), c = xy; the same A); 3: the
+// advection-diffusion problem of Section 5, A = 0.1 I, B = (1, 1), c = 0.
 struct GeomParams {
     int kind;
     int pde;
@@ -1804,9 +1805,16 @@ struct GeomQP {
     double* Cw;
 };
 
-// Coefficients of the Section 5 problems at a physical point (pde 1 or 2).
+// Coefficients of the Section 5 problems at a physical point (pde 1, 2 or 3).
 __device__ inline void pde_coefficients(int pde, double x, double y, double& a11, double& a12, double& a22,
                                         double& b1, double& b2, double& c) {
+    if (pde == 3) {  // advection-diffusion: -0.1 Laplace + (1, 1) . grad
+        a11 = a22 = 0.1;
+        a12 = 0.0;
+        b1 = b2 = 1.0;
+        c = 0.0;
+        return;
+    }
     a11 = (2.0 + cos(x)) * (1.0 + y);
     a12 = cos(x + y) * sin(x + y);
     a22 = (2.0 + sin(y)) * (1.0 + x);
@@ -1969,7 +1977,7 @@ __global__ void k_assemble_stencil(int ne, int nq, const double* __restrict__ V,
 }
 
 // Built-in right-hand sides of the Section 5 problems at the quadrature points,
-// premultiplied by w |det J|: pde 1: f = 1; pde 2: f of the manufactured solution
+// premultiplied by w |det J|: pde 1 and 3: f = 1; pde 2: f of the manufactured solution
 // u = (x^2 + y^2 - 0.2^2)(x^2 + y^2 - 1) sin x sin y, i.e.
 // f = -div(A grad u) + B.grad u + c u written out with u = g s,
 // g = (r^2 - 0.04)(r^2 - 1), s = sin x sin y.

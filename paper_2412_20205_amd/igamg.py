@@ -20,7 +20,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EBREAKDOWN, ENOCONV, ENONFINITE = 0, -1, -2, 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
                 -5: "EBREAKDOWN", -6: "ENOCONV", -7: "ENONFINITE"}
 UNIT_SQUARE, QUARTER_ANNULUS, UNIT_CUBE, QUARTER_ANNULUS_EXACT = 0, 1, 2, 3
-PDE_POISSON, PDE_ELLIPTIC_1, PDE_ELLIPTIC_2 = 0, 1, 2
+PDE_POISSON, PDE_ELLIPTIC_1, PDE_ELLIPTIC_2, PDE_ADVECTION_DIFFUSION = 0, 1, 2, 3
 SMOOTH_MCGS, SMOOTH_LEXGS, SMOOTH_JACOBI, SMOOTH_LEARNED = 0, 1, 2, 3
 EXTRAP_NONE, RRE, MPE = 0, 1, 2
 FP64, FP32_IR = 0, 1

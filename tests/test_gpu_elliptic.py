@@ -28,6 +28,8 @@ PROBLEMS = {
                (0.2, 1.0), el.manufactured_f),
     "poly2": (igamg.QUARTER_ANNULUS, "annulus", el.CSET_ANNULUS, igamg.PDE_ELLIPTIC_2, (0.0, 0.0),
               el.manufactured_f),
+    "advdiff": (igamg.UNIT_SQUARE, "square", el.CSET_ADVDIFF, igamg.PDE_ADVECTION_DIFFUSION, (0.0, 0.0),
+                lambda x, y: np.ones_like(x)),
 }
 _cache = {}
 
@@ -47,7 +49,8 @@ def case(name, n_el, p, **opts):
 
 
 CASES = [("square1", 16, 1), ("square1", 16, 2), ("square1", 32, 3), ("square1", 16, 4), ("square1", 16, 5),
-         ("exact2", 16, 2), ("exact2", 32, 3), ("exact2", 16, 4), ("exact2", 16, 5), ("poly2", 16, 3)]
+         ("exact2", 16, 2), ("exact2", 32, 3), ("exact2", 16, 4), ("exact2", 16, 5), ("poly2", 16, 3),
+         ("advdiff", 16, 2), ("advdiff", 32, 4)]
 
 
 @pytest.mark.parametrize("name,n_el,p", CASES)
@@ -103,7 +106,7 @@ def test_sweeps_and_vcycle_iterates(name, n_el, p):
 
 
 @pytest.mark.parametrize("name,n_el,p", [("square1", 32, 1), ("square1", 32, 4), ("exact2", 32, 2),
-                                         ("exact2", 64, 3), ("exact2", 32, 5)])
+                                         ("exact2", 64, 3), ("exact2", 32, 5), ("advdiff", 64, 3)])
 def test_rre8_solve_matches_oracle(name, n_el, p):
     """RRE(8), relative residual 1e-12 (the setting of Tables 13 and 15)."""
     s, H, b = case(name, n_el, p)

@@ -35,6 +35,16 @@ def test_divergence_free_convection_is_skew_on_the_square(p):
     assert abs(C).max() > 1e-3
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_advection_diffusion_parts(p):
+    """A = 0.1 I, B = (1, 1): the diffusion part is 0.1 times the Laplace
+    assembly, the constant convection is exactly skew-symmetric."""
+    D = el.assemble(6, p, "square", el.CSET_ADVDIFF, terms=("diffusion",))
+    assert abs(D - 0.1 * assemble.kron_operator_2d(6, p)).max() < 1e-15
+    C = el.assemble(6, p, "square", el.CSET_ADVDIFF, terms=("convection",)).toarray()
+    assert abs(C + C.T).max() < 1e-14 * abs(C).max()
+
+
 @pytest.mark.parametrize("p", [1, 2, 4])
 def test_reaction_with_c_one_integrates_the_area(p):
     """c = 1 over all functions: sum_IJ int phi_I phi_J = int 1 = 1 (partition of unity)."""
