@@ -107,6 +107,25 @@ def extrapolate(S, method):
     return t, gamma, info
 
 
+def generalized_residual(S, gamma):
+    """Generalised residual of t (Section 3, eq. (11)): r~(t) = t~ - t with
+    t = sum_j gamma_j s_j and t~ = sum_j gamma_j s_{j+1}, i.e. sum_j gamma_j Delta s_j."""
+    S = [np.asarray(x, dtype=np.float64) for x in S]
+    q1 = len(gamma)
+    t = sum(gamma[j] * S[j] for j in range(q1))
+    tt = sum(gamma[j] * S[j + 1] for j in range(q1))
+    return tt - t
+
+
+def generalized_residual_closed(S, method):
+    """The closed form of eq. (11): Delta s_0 - Delta^2 S (Y^T Delta^2 S)^{-1} Y^T Delta s_0
+    with Y = Delta^2 S (RRE) or Delta S (MPE), q columns each."""
+    U = differences(S)
+    d2S = U[:, 1:] - U[:, :-1]
+    Y = d2S if method == RRE else U[:, :-1]
+    return U[:, 0] - d2S @ np.linalg.solve(Y.T @ d2S, Y.T @ U[:, 0])
+
+
 def extrapolate_schur(S, method):
     """Closed form eq. (9): t = s_0 - Delta S (Y^T Delta^2 S)^{-1} Y^T Delta s_0.
 

@@ -150,3 +150,33 @@ def test_paper_qualitative_degree_robustness():
     assert counts[4][0] > 4 * counts[2][0]
     assert counts[4][1] <= 4 and counts[2][1] <= 2
     assert counts[4][1] * 9 < counts[4][0]
+
+
+@pytest.mark.parametrize("method", [ex.RRE, ex.MPE])
+@pytest.mark.parametrize("q", [2, 5, 8])
+def test_generalized_residual_is_one_step_of_the_map(method, q):
+    """Section 3, eq. (11): r~(t) = t~ - t.  On an affine map s -> B s + c with
+    sum gamma_j = 1, t~ = B t + c, so r~(t) = G(t) - t; it also equals the
+    closed form Delta s_0 - Delta^2 S (Y^T Delta^2 S)^-1 Y^T Delta s_0."""
+    B, c, S = _linear_sequence(N=60, q=q, seed=3)
+    t, gamma, info = ex.extrapolate(S, method)
+    assert info == "ok"
+    r = ex.generalized_residual(S, gamma)
+    g = B @ t + c - t
+    assert np.linalg.norm(r - g) < 1e-10 * np.linalg.norm(g)
+    rc = ex.generalized_residual_closed(S, method)
+    assert np.linalg.norm(r - rc) < 1e-10 * np.linalg.norm(rc)
+
+
+def test_rre_generalized_residual_is_the_constrained_minimum():
+    """RRE's gamma minimises ||sum gamma_j Delta s_j|| subject to sum gamma_j = 1:
+    no other weights (random, summing to one) give a smaller generalised residual."""
+    _, _, S = _linear_sequence(N=50, q=5, seed=4)
+    _, gamma, _ = ex.extrapolate(S, ex.RRE)
+    best = np.linalg.norm(ex.generalized_residual(S, gamma))
+    U = ex.differences(S)
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        w = rng.standard_normal(len(gamma))
+        w += (1.0 - w.sum()) / len(w)
+        assert np.linalg.norm(U @ w) >= best * (1 - 1e-12)
