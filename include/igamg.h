@@ -123,6 +123,12 @@ typedef struct {
                             l-1's cycle mu times on the same coarse right-hand
                             side (1: V-cycle, 2: W-cycle; 1..4; default 1).
                             Batches and smoother training need mu = 1.       */
+    int monitor;         /* RRE/MPE solves: 0 (default) test ||b - A t|| after
+                            every restart cycle (Algorithm 5); 1 evaluate it
+                            only when the generalised residual, scaled by the
+                            ratio measured at the last evaluation, predicts
+                            at most 4 tol (always after the first cycle);
+                            the returned x passes the same test either way   */
     int pde;             /* igamg_pde (default POISSON); batches and the
                             learned smoother need POISSON                     */
     int row_sweeps;      /* stored stencils: sweep the p+1 colours of a row
@@ -138,6 +144,10 @@ typedef struct {
     int breakdowns;      /* cycles whose extrapolation broke down             */
     int learned_fallbacks;
     double rel_residual; /* ||b - A x||_2 / ||b||_2 of the returned x          */
+    double gen_residual; /* RRE/MPE: generalised residual ||t~ - t|| (Section 3,
+                            eq. (11)) of the last cycle over ||s_1 - s_0|| of
+                            the first; 0 for plain multigrid                  */
+    int residual_checks; /* evaluations of ||b - A x|| during the solve       */
     double setup_ms;     /* time spent in igamg_setup                         */
     double solve_ms;     /* wall time of the solve call                       */
 } igamg_stats;
@@ -198,6 +208,12 @@ igamg_status igamg_vcycle(igamg_ctx* ctx, double* x_dev);
  * x = s_{q+1} and returns EBREAKDOWN. */
 igamg_status igamg_extrapolate(igamg_ctx* ctx, int method, int q, double* x_dev,
                                double* iterates_dev, double* gamma);
+/* Generalised residual ||t~ - t|| = ||sum_j gamma_j (s_{j+1} - s_j)|| of the last
+ * extrapolation (igamg_extrapolate or the last restart cycle of igamg_solve),
+ * computed from the R factor of the differences (||R gamma||), with no product
+ * with A (Section 3, eq. (11)).  NaN after a breakdown; EINVAL before any
+ * extrapolation. */
+igamg_status igamg_generalized_residual(const igamg_ctx* ctx, double* gres);
 
 /* Algorithm 5: restarted RRE(q)/MPE(q) from the initial guess in x_dev until
  * ||b - A x||_2 / ||b||_2 <= tol (tested on t only); method EXTRAP_NONE runs

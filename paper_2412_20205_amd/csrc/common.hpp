@@ -40,6 +40,8 @@ struct ExtrapCoeffs {
     double alpha[kMaxCols];
     int info;  // 0 regular, 1 lucky breakdown, -1 lambda ~ 0, -2 non-finite
     int lucky_col;
+    double gres;  // ||sum_j gamma_j Delta s_j|| = ||R gamma|| (generalised residual; NaN on breakdown)
+    double d0;    // ||Delta s_0|| = |R_00|
 };
 
 }  // namespace igamg

@@ -119,6 +119,9 @@ struct igamg_ctx {
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_method = -1, graph_q = -1;
+    bool graph_resnorm = true;          // the captured cycle ends with ||b - A t||
+    ExtrapCoeffs last_coeffs{};          // of the last extrapolation read back
+    bool have_coeffs = false;
     int tail_top = 0;  // levels 0..tail_top run in the single-workgroup kernel
     bool tail_auto = false;  // tail_items < 0 at setup: take the tuned split of each precision
     // learned smoother
@@ -651,6 +654,8 @@ struct igamg_ctx {
         IGAMG_HIP(hipMemcpyAsync(host_coeffs, coeffs, sizeof(ExtrapCoeffs), hipMemcpyDeviceToHost, stream));
         IGAMG_HIP(hipStreamSynchronize(stream));
         c = *host_coeffs;
+        last_coeffs = c;
+        have_coeffs = true;
         return host_scal[0];
     }
 
@@ -701,8 +706,9 @@ struct igamg_ctx {
     }
 
     // One restart cycle (Algorithm 5 body) on the iterate buffers: S[0] holds
-    // s_0 on entry and t on exit; the residual norm of t goes to scal[0].
-    void restart_cycle(int method, int q) {
+    // s_0 on entry and t on exit; the residual norm of t goes to scal[0]
+    // (unless with_resnorm is false).
+    void restart_cycle(int method, int q, bool with_resnorm = true) {
         long long N = lv[L].N;
         for (int j = 0; j <= q; ++j) {
             copy(S[j], S[j + 1], N);
@@ -713,7 +719,7 @@ struct igamg_ctx {
         hipLaunchKernelGGL(k_extrap_combine, dim3(grid_for(N)), dim3(kBlock), 0, stream, it, q, N,
                            (const ExtrapCoeffs*)coeffs, S[0]);
         check_launch();
-        resnorm_async(S[0]);
+        if (with_resnorm) resnorm_async(S[0]);
     }
 
     // Plain multigrid step on S[0]: one application of G and the residual norm.
@@ -722,15 +728,16 @@ struct igamg_ctx {
         resnorm_async(S[0]);
     }
 
-    void run_restart_cycle(int method, int q) {
+    void run_restart_cycle(int method, int q, bool with_resnorm = true) {
+        if (method == IGAMG_EXTRAP_NONE) with_resnorm = true;
         if (!opt.use_graphs) {
             if (method == IGAMG_EXTRAP_NONE)
                 plain_cycle();
             else
-                restart_cycle(method, q);
+                restart_cycle(method, q, with_resnorm);
             return;
         }
-        if (!graph_exec || graph_method != method || graph_q != q) {
+        if (!graph_exec || graph_method != method || graph_q != q || graph_resnorm != with_resnorm) {
             if (graph_exec) {
                 (void)hipGraphExecDestroy(graph_exec);
                 graph_exec = nullptr;
@@ -744,7 +751,7 @@ struct igamg_ctx {
                 if (method == IGAMG_EXTRAP_NONE)
                     plain_cycle();
                 else
-                    restart_cycle(method, q);
+                    restart_cycle(method, q, with_resnorm);
             } catch (...) {
                 hipGraph_t g;
                 (void)hipStreamEndCapture(stream, &g);
@@ -755,6 +762,7 @@ struct igamg_ctx {
             IGAMG_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
             graph_method = method;
             graph_q = q;
+            graph_resnorm = with_resnorm;
         }
         IGAMG_HIP(hipGraphLaunch(graph_exec, stream));
     }
@@ -767,6 +775,8 @@ struct igamg_ctx {
     ExtrapCoeffs read_coeffs() {
         IGAMG_HIP(hipMemcpyAsync(host_coeffs, coeffs, sizeof(ExtrapCoeffs), hipMemcpyDeviceToHost, stream));
         IGAMG_HIP(hipStreamSynchronize(stream));
+        last_coeffs = *host_coeffs;
+        have_coeffs = true;
         return *host_coeffs;
     }
     void sync() { IGAMG_HIP(hipStreamSynchronize(stream)); }
@@ -1954,6 +1964,7 @@ void igamg_options_default(igamg_options* opt) {
     opt->stored_stencil = 0;
     opt->mu = 1;
     opt->pde = IGAMG_PDE_POISSON;
+    opt->monitor = 0;
     opt->row_sweeps = 1;
     opt->stream = nullptr;
 }
@@ -2101,6 +2112,14 @@ igamg_status igamg_extrapolate(igamg_ctx* ctx, int method, int q, double* x_dev,
     });
 }
 
+igamg_status igamg_generalized_residual(const igamg_ctx* ctx, double* gres) {
+    return guarded([&] {
+        need(ctx && gres, "null argument");
+        need(ctx->have_coeffs, "no extrapolation yet");
+        *gres = ctx->last_coeffs.gres;
+    });
+}
+
 igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int method, int q,
                          double* x_dev, igamg_stats* stats) {
     igamg_stats st{};
@@ -2120,6 +2139,7 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
                 double rel = ctx->read_scal();
                 st.vcycles++;
                 st.restarts++;
+                st.residual_checks++;
                 st.rel_residual = rel;
                 if (!std::isfinite(rel)) {
                     ctx->copy(ctx->S[0], x_dev, N);
@@ -2139,10 +2159,33 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
             ctx->copy(x_dev, ctx->S[0], N);
             double prev = 1.0;
             bool learned_at_start = ctx->learned_on;
+            // generalised-residual monitor: ||b - A t|| is evaluated when
+            // ratio * g <= 4 tol, ratio = rel/g at the last evaluation
+            const bool monitor = ctx->opt.monitor != 0;
+            double d0_first = 0.0, ratio = -1.0;
             for (int k = 0; k < max_restarts; ++k) {
-                ctx->run_restart_cycle(method, q);
                 ExtrapCoeffs c;
-                double rel = ctx->read_cycle(c);
+                double rel;
+                if (!monitor) {
+                    ctx->run_restart_cycle(method, q);
+                    rel = ctx->read_cycle(c);
+                    st.residual_checks++;
+                } else {
+                    ctx->run_restart_cycle(method, q, false);
+                    c = ctx->read_coeffs();
+                    if (k == 0) d0_first = c.d0 > 0.0 ? c.d0 : 1.0;
+                    const double g = c.gres / d0_first;
+                    if (ratio < 0.0 || !std::isfinite(g) || ratio * g <= 4.0 * tol || k + 1 == max_restarts) {
+                        ctx->resnorm_async(ctx->S[0]);
+                        rel = ctx->read_scal();
+                        st.residual_checks++;
+                        if (std::isfinite(g) && g > 0.0) ratio = rel / g;
+                    } else {
+                        rel = ratio * g;  // estimate (above 4 tol): not converged
+                    }
+                }
+                if (std::isfinite(c.gres) && d0_first == 0.0 && c.d0 > 0.0) d0_first = c.d0;
+                st.gen_residual = d0_first > 0.0 ? c.gres / d0_first : c.gres;
                 // learned-smoother fallback: a cycle contracting worse than plain
                 // V-cycles would (measured at training) switches back to Gauss-Seidel
                 if (ctx->learned_on && ctx->rho_plain_ref > 0.0 && std::isfinite(rel) && k > 0 &&

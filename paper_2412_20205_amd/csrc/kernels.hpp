@@ -974,6 +974,8 @@ __global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int me
     for (int i = 0; i < kMaxCols; ++i) c.gamma[i] = c.alpha[i] = 0.0;
     c.info = 0;
     c.lucky_col = -1;
+    c.gres = __builtin_nan("");
+    c.d0 = fabs(Rg[0]);
     if (!finite) {
         c.info = -2;
         *out = c;
@@ -1033,6 +1035,14 @@ __global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int me
         acc -= c.gamma[j];
         c.alpha[j] = acc;
     }
+    // generalised residual t~ - t = sum_j gamma_j Delta s_j = Q (R gamma)
+    double g2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double v = 0.0;
+        for (int k = i; k < n; ++k) v += R[i][k] * c.gamma[k];
+        g2 += v * v;
+    }
+    c.gres = sqrt(g2);
     *out = c;
 }
 

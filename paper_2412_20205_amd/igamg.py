@@ -36,14 +36,16 @@ class Options(ctypes.Structure):
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("n_el_coarsest", ctypes.c_int), ("use_graphs", ctypes.c_int),
                 ("tail_items", ctypes.c_int), ("stored_stencil", ctypes.c_int),
-                ("mu", ctypes.c_int), ("pde", ctypes.c_int), ("row_sweeps", ctypes.c_int),
+                ("mu", ctypes.c_int), ("monitor", ctypes.c_int), ("pde", ctypes.c_int),
+                ("row_sweeps", ctypes.c_int),
                 ("stream", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("restarts", ctypes.c_int), ("vcycles", ctypes.c_int),
                 ("breakdowns", ctypes.c_int), ("learned_fallbacks", ctypes.c_int),
-                ("rel_residual", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("rel_residual", ctypes.c_double), ("gen_residual", ctypes.c_double),
+                ("residual_checks", ctypes.c_int), ("setup_ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double)]
 
     def as_dict(self):
@@ -98,6 +100,7 @@ _SIGNATURES = {
     "igamg_vcycle": (_i, [_P, _P]),
     "igamg_set_precision": (_i, [_P, _i]),
     "igamg_extrapolate": (_i, [_P, _i, _i, _P, _P, _P]),
+    "igamg_generalized_residual": (_i, [_P, ctypes.POINTER(_d)]),
     "igamg_solve": (_i, [_P, _d, _i, _i, _i, _P, ctypes.POINTER(Stats)]),
     "igamg_residual": (_i, [_P, _P, ctypes.POINTER(_d)]),
     "igamg_get_operator_rows": (_i, [_P, _i, _P, _i, _P]),
@@ -276,6 +279,12 @@ class Solver:
         st = lib().igamg_extrapolate(self._h, method, q, _ptr(x), _ptr(iterates), _np_ptr(gamma))
         _check(st, "igamg_extrapolate")
         return gamma
+
+    def generalized_residual(self):
+        """||t~ - t|| of the last extrapolation (from its R factor)."""
+        g = _d()
+        _check(lib().igamg_generalized_residual(self._h, ctypes.byref(g)), "igamg_generalized_residual")
+        return g.value
 
     def solve(self, x, tol=1e-10, max_restarts=100, method=RRE, q=5, check=True):
         st = Stats()
