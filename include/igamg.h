@@ -208,6 +208,20 @@ igamg_status igamg_vcycle(igamg_ctx* ctx, double* x_dev);
  * x = s_{q+1} and returns EBREAKDOWN. */
 igamg_status igamg_extrapolate(igamg_ctx* ctx, int method, int q, double* x_dev,
                                double* iterates_dev, double* gamma);
+/* Flexible GMRES(m) on A x = b (restarted every m <= 30 steps), right-
+ * preconditioned by the multigrid cycle: VCYCLE one FP64 V-cycle from zero;
+ * RRE / MPE one restart cycle of Algorithm 5 (q+1 cycles of the context's
+ * precision from zero, then the extrapolation) for A z = v, which depends
+ * nonlinearly on v, hence the flexible variant (the paper presents the
+ * extrapolated cycle as usable as a preconditioner: Section 1, conclusions).
+ * Arnoldi by classical Gram-Schmidt applied twice.  Stops when
+ * ||b - A x||_2 <= tol ||b||_2 at a restart; x is the initial guess on entry.
+ * stats: restarts = GMRES iterations, vcycles = V-cycles applied,
+ * residual_checks = true residual evaluations.  ENOCONV after max_iters. */
+typedef enum { IGAMG_PRECOND_VCYCLE = 0, IGAMG_PRECOND_RRE = 1, IGAMG_PRECOND_MPE = 2 } igamg_precond;
+igamg_status igamg_solve_fgmres(igamg_ctx* ctx, double tol, int max_iters, int m, int precond, int q,
+                                double* x_dev, igamg_stats* stats);
+
 /* Generalised residual ||t~ - t|| = ||sum_j gamma_j (s_{j+1} - s_j)|| of the last
  * extrapolation (igamg_extrapolate or the last restart cycle of igamg_solve),
  * computed from the R factor of the differences (||R gamma||), with no product

@@ -29,6 +29,13 @@ constexpr int kQrRows = 512;      // rows of one tall-skinny QR panel (LDS <= 37
 constexpr int kMaxQ = 8;          // largest restart number q
 constexpr int kMaxCols = kMaxQ + 1;
 
+constexpr int kMaxKrylov = 30;    // largest restart length of flexible GMRES
+
+// Basis vectors passed by value to the Krylov kernels.
+struct VecPtrs {
+    const double* v[kMaxKrylov + 1];
+};
+
 // Iterate pointers s_0 .. s_{q+1} passed by value to the extrapolation kernels.
 struct IterPtrs {
     const double* s[kMaxQ + 2];

@@ -120,6 +120,12 @@ struct igamg_ctx {
     hipGraph_t graph = nullptr;
     int graph_method = -1, graph_q = -1;
     bool graph_resnorm = true;          // the captured cycle ends with ||b - A t||
+    // flexible GMRES work space
+    std::vector<double*> kry_V, kry_Z;
+    double* kry_w = nullptr;
+    double* kry_h = nullptr;
+    double* kry_partial = nullptr;
+    double* bsave = nullptr;
     ExtrapCoeffs last_coeffs{};          // of the last extrapolation read back
     bool have_coeffs = false;
     int tail_top = 0;  // levels 0..tail_top run in the single-workgroup kernel
@@ -852,6 +858,8 @@ struct igamg_ctx {
     double measure_rho(int vcycles, bool learned);
 
     void autotune(int* best_items, double* best_ms);
+    void precond_apply(int precond, int q, const double* v, double* z);
+    void fgmres(double tol, int max_iters, int m, int precond, int q, double* x, igamg_stats& st);
 
     void setup(const igamg_geometry& g, int degree, int levels);
     void setup_levels(int n_el, int levels);
@@ -1244,6 +1252,130 @@ void igamg_ctx::set_rhs_field(const double* modes, int n_modes) {
 
 // ---------------------------------------------------------------------------
 // autotuning of the multi-block / single-workgroup split
+
+// ---------------------------------------------------------------------------
+// flexible GMRES with the (extrapolated) multigrid cycle as preconditioner
+
+// z = M(v): one FP64 V-cycle from zero, or one RRE/MPE(q) restart cycle for
+// A z = v from zero (the context's right-hand side is replaced by v for the
+// cycle; the captured restart graph reads it from the same buffer).
+void igamg_ctx::precond_apply(int precond, int q, const double* v, double* z) {
+    const long long N = lv[L].N;
+    if (precond == IGAMG_PRECOND_VCYCLE) {
+        fill(z, N);
+        vcycle<double>(v, z);
+        return;
+    }
+    copy(v, b, N);
+    ensure_iterates(q);
+    fill(S[0], N);
+    run_restart_cycle(precond == IGAMG_PRECOND_RRE ? IGAMG_RRE : IGAMG_MPE, q, false);
+    copy(S[0], z, N);
+}
+
+// Right-preconditioned flexible GMRES(m) on the finest level: Arnoldi with
+// classical Gram-Schmidt applied twice, Givens rotations on the host, the
+// preconditioned directions Z kept for the update x += Z y.  Stops when
+// ||b - A x|| <= tol ||b|| at a restart (the Arnoldi estimate ends a cycle early).
+void igamg_ctx::fgmres(double tol, int max_iters, int m, int precond, int q, double* x, igamg_stats& st) {
+    const long long N = lv[L].N;
+    while ((int)kry_V.size() < m + 1) kry_V.push_back(alloc<double>(N));
+    while ((int)kry_Z.size() < m) kry_Z.push_back(alloc<double>(N));
+    const unsigned nbk = (unsigned)std::min<long long>(grid_for(N), 512);
+    if (!kry_w) kry_w = alloc<double>(N);
+    if (!kry_h) kry_h = alloc<double>(kMaxKrylov + 2);
+    if (!kry_partial) kry_partial = alloc<double>((size_t)512 * (kMaxKrylov + 1));
+    if (!bsave) bsave = alloc<double>(N);
+    copy(b, bsave, N);
+    const double nb = bnorm > 0.0 ? bnorm : 1.0;
+    int iters = 0;
+    bool converged = false;
+    auto restore = [&]() { copy(bsave, b, N); sync(); };
+    try {
+        for (;;) {
+            residual<double, double>(L, bsave, x, kry_w, 0, nullptr);
+            const double beta = vector_norm(kry_w, N);
+            st.residual_checks++;
+            st.rel_residual = beta / nb;
+            if (!std::isfinite(beta)) throw Error(IGAMG_ENONFINITE, "non-finite residual");
+            if (beta <= tol * nb) {
+                converged = true;
+                break;
+            }
+            if (iters >= max_iters) break;
+            hipLaunchKernelGGL(k_scaled_copy, dim3(grid_for(N)), dim3(kBlock), 0, stream, kry_w, kry_V[0],
+                               1.0 / beta, N);
+            check_launch();
+            std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+            auto Hat = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+            g[0] = beta;
+            int k = 0;
+            for (int j = 0; j < m && iters < max_iters; ++j) {
+                precond_apply(precond, q, kry_V[j], kry_Z[j]);
+                st.vcycles += (precond == IGAMG_PRECOND_VCYCLE) ? 1 : q + 1;
+                residual<double, double>(L, nullptr, kry_Z[j], kry_w, 1, nullptr);  // w = A z_j
+                VecPtrs Vp{};
+                for (int i = 0; i <= j; ++i) Vp.v[i] = kry_V[i];
+                std::vector<double> h(j + 1, 0.0), hp(j + 1);
+                for (int pass = 0; pass < 2; ++pass) {
+                    hipLaunchKernelGGL(k_dots_partial, dim3(nbk), dim3(kBlock), 0, stream, (const double*)kry_w,
+                                       Vp, j + 1, N, kry_partial);
+                    hipLaunchKernelGGL(k_dots_finalize, dim3(1), dim3(64), 0, stream,
+                                       (const double*)kry_partial, (int)nbk, j + 1, kry_h);
+                    hipLaunchKernelGGL(k_axpy_multi, dim3(grid_for(N)), dim3(kBlock), 0, stream, kry_w, Vp,
+                                       (const double*)kry_h, j + 1, -1.0, N);
+                    check_launch();
+                    IGAMG_HIP(hipMemcpyAsync(hp.data(), kry_h, (j + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                                             stream));
+                    sync();
+                    for (int i = 0; i <= j; ++i) h[i] += hp[i];
+                }
+                const double hn = vector_norm(kry_w, N);
+                for (int i = 0; i <= j; ++i) Hat(i, j) = h[i];
+                Hat(j + 1, j) = hn;
+                if (hn > 0.0) {
+                    hipLaunchKernelGGL(k_scaled_copy, dim3(grid_for(N)), dim3(kBlock), 0, stream, kry_w,
+                                       kry_V[j + 1], 1.0 / hn, N);
+                    check_launch();
+                }
+                for (int i = 0; i < j; ++i) {  // previous rotations on column j
+                    const double a = Hat(i, j), c2 = Hat(i + 1, j);
+                    Hat(i, j) = cs[i] * a + sn[i] * c2;
+                    Hat(i + 1, j) = -sn[i] * a + cs[i] * c2;
+                }
+                const double r = std::hypot(Hat(j, j), Hat(j + 1, j));
+                cs[j] = r > 0.0 ? Hat(j, j) / r : 1.0;
+                sn[j] = r > 0.0 ? Hat(j + 1, j) / r : 0.0;
+                Hat(j, j) = r;
+                Hat(j + 1, j) = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                k = j + 1;
+                ++iters;
+                if (!std::isfinite(g[j + 1])) throw Error(IGAMG_ENONFINITE, "non-finite Arnoldi step");
+                if (std::fabs(g[j + 1]) <= tol * nb || hn == 0.0) break;
+            }
+            std::vector<double> y(k, 0.0);
+            for (int i = k - 1; i >= 0; --i) {
+                double s = g[i];
+                for (int l = i + 1; l < k; ++l) s -= Hat(i, l) * y[l];
+                y[i] = s / Hat(i, i);
+            }
+            IGAMG_HIP(hipMemcpyAsync(kry_h, y.data(), k * sizeof(double), hipMemcpyHostToDevice, stream));
+            VecPtrs Zp{};
+            for (int i = 0; i < k; ++i) Zp.v[i] = kry_Z[i];
+            hipLaunchKernelGGL(k_axpy_multi, dim3(grid_for(N)), dim3(kBlock), 0, stream, x, Zp,
+                               (const double*)kry_h, k, 1.0, N);
+            check_launch();
+        }
+    } catch (...) {
+        restore();
+        throw;
+    }
+    restore();
+    st.restarts = iters;
+    if (!converged) throw Error(IGAMG_ENOCONV, "tolerance not reached within max_iters");
+}
 
 void igamg_ctx::autotune(int* best_items, double* best_ms) {
     const int cand[] = {0, 8, 16, 32, 64, 128, 256, 512};
@@ -2215,6 +2347,26 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
             }
         }
         if (!converged) throw Error(IGAMG_ENOCONV, "tolerance not reached within max_restarts");
+    });
+    st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return s;
+}
+
+igamg_status igamg_solve_fgmres(igamg_ctx* ctx, double tol, int max_iters, int m, int precond, int q,
+                                double* x_dev, igamg_stats* stats) {
+    igamg_stats st{};
+    auto t0 = std::chrono::steady_clock::now();
+    igamg_status s = guarded([&] {
+        need(ctx && x_dev, "null argument");
+        need(tol > 0 && max_iters > 0, "bad tolerance or max_iters");
+        need(m >= 1 && m <= kMaxKrylov, "restart length m must be in 1..30");
+        need(precond == IGAMG_PRECOND_VCYCLE || precond == IGAMG_PRECOND_RRE || precond == IGAMG_PRECOND_MPE,
+             "bad preconditioner");
+        need(precond == IGAMG_PRECOND_VCYCLE || (q >= 1 && q <= kMaxQ), "q must be in 1..8");
+        st.setup_ms = ctx->setup_ms;
+        ctx->fgmres(tol, max_iters, m, precond, q, x_dev, st);
+        ctx->sync();
     });
     st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;

@@ -694,6 +694,47 @@ __global__ void __launch_bounds__(kBlock) k_sumsq(const T* __restrict__ v, long 
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// Krylov kernels (flexible GMRES): per-block partial dot products of w with
+// v_0 .. v_{k-1}, partial[blk * k + i]; their sums in block order; and
+// w += sign * sum_i h_i v_i.
+__global__ void __launch_bounds__(kBlock) k_dots_partial(const double* __restrict__ w, VecPtrs V, int k,
+                                                         long long N, double* __restrict__ partial) {
+    __shared__ double red[kBlock / 64];
+    for (int i = 0; i < k; ++i) {
+        const double* __restrict__ v = V.v[i];
+        double s = 0.0;
+        for (long long I = (long long)blockIdx.x * kBlock + threadIdx.x; I < N; I += (long long)gridDim.x * kBlock)
+            s = fma(w[I], v[I], s);
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * k + i] = s;
+    }
+}
+
+__global__ void k_dots_finalize(const double* __restrict__ partial, int nb, int k, double* __restrict__ out) {
+    const int i = threadIdx.x;
+    if (i >= k) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(size_t)b * k + i];
+    out[i] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_axpy_multi(double* __restrict__ w, VecPtrs V,
+                                                       const double* __restrict__ h, int k, double sign,
+                                                       long long N) {
+    long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (I >= N) return;
+    double acc = 0.0;
+    for (int i = 0; i < k; ++i) acc = fma(h[i], V.v[i][I], acc);
+    w[I] += sign * acc;
+}
+
+// v = w / s (s on the host side of the call)
+__global__ void __launch_bounds__(kBlock) k_scaled_copy(const double* __restrict__ w, double* __restrict__ v,
+                                                        double inv, long long N) {
+    long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (I < N) v[I] = w[I] * inv;
+}
+
 // ---------------------------------------------------------------------------
 // elementwise kernels
 

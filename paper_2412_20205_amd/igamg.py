@@ -23,6 +23,7 @@ UNIT_SQUARE, QUARTER_ANNULUS, UNIT_CUBE, QUARTER_ANNULUS_EXACT = 0, 1, 2, 3
 PDE_POISSON, PDE_ELLIPTIC_1, PDE_ELLIPTIC_2, PDE_ADVECTION_DIFFUSION = 0, 1, 2, 3
 SMOOTH_MCGS, SMOOTH_LEXGS, SMOOTH_JACOBI, SMOOTH_LEARNED = 0, 1, 2, 3
 EXTRAP_NONE, RRE, MPE = 0, 1, 2
+PRECOND_VCYCLE, PRECOND_RRE, PRECOND_MPE = 0, 1, 2
 FP64, FP32_IR = 0, 1
 
 
@@ -101,6 +102,7 @@ _SIGNATURES = {
     "igamg_set_precision": (_i, [_P, _i]),
     "igamg_extrapolate": (_i, [_P, _i, _i, _P, _P, _P]),
     "igamg_generalized_residual": (_i, [_P, ctypes.POINTER(_d)]),
+    "igamg_solve_fgmres": (_i, [_P, _d, _i, _i, _i, _i, _P, ctypes.POINTER(Stats)]),
     "igamg_solve": (_i, [_P, _d, _i, _i, _i, _P, ctypes.POINTER(Stats)]),
     "igamg_residual": (_i, [_P, _P, ctypes.POINTER(_d)]),
     "igamg_get_operator_rows": (_i, [_P, _i, _P, _i, _P]),
@@ -279,6 +281,15 @@ class Solver:
         st = lib().igamg_extrapolate(self._h, method, q, _ptr(x), _ptr(iterates), _np_ptr(gamma))
         _check(st, "igamg_extrapolate")
         return gamma
+
+    def solve_fgmres(self, x, tol=1e-10, max_iters=200, m=20, precond=PRECOND_RRE, q=3, check=True):
+        """Flexible GMRES(m) preconditioned by the multigrid cycle; x is the
+        initial guess and the result.  Returns (stats, status)."""
+        st = Stats()
+        status = lib().igamg_solve_fgmres(self._h, tol, max_iters, m, precond, q, _ptr(x), ctypes.byref(st))
+        if check:
+            _check(status, "igamg_solve_fgmres")
+        return st, status
 
     def generalized_residual(self):
         """||t~ - t|| of the last extrapolation (from its R factor)."""
