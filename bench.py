@@ -216,8 +216,10 @@ def elliptic_measure(igamg, torch, steps):
     radii 0.2 and 1, the second coefficient set and the manufactured solution
     (Table 15), and the advection-diffusion problem with f = 1 (Table 14); RRE(8) around FP64 V(2,2) multicolour Gauss-Seidel cycles,
     relative residual 1e-12; restart cycles and ms per solve beside the paper's
-    counts.  Also the annulus problem at 1024^2, p = 3, RRE(8) around FP32
-    V-cycles in FP64 refinement, relative residual 1e-10."""
+    counts.  Also flexible GMRES(20) on the annulus problem preconditioned by one
+    V-cycle or one RRE(3) restart cycle (relative residual 1e-10), and the
+    annulus problem at 1024^2, p = 3, RRE(8) around FP32 V-cycles in FP64
+    refinement, relative residual 1e-10."""
     out = {}
     probs = (("table13_square", igamg.UNIT_SQUARE, igamg.PDE_ELLIPTIC_1, (0.0, 0.0), PAPER_TABLE13),
              ("table15_annulus", igamg.QUARTER_ANNULUS_EXACT, igamg.PDE_ELLIPTIC_2, (0.2, 1.0), PAPER_TABLE15),
@@ -244,6 +246,25 @@ def elliptic_measure(igamg, torch, steps):
                 s.close()
             rows["n_el_%d" % ne] = row
         out[name] = rows
+    # flexible GMRES(20) preconditioned by one V-cycle or one RRE(3) restart cycle
+    fg = {}
+    for ne, p in ((64, 4), (256, 3)):
+        s = igamg.Solver(igamg.QUARTER_ANNULUS_EXACT, ne, p, radii=(0.2, 1.0), pde=igamg.PDE_ELLIPTIC_2)
+        s.set_rhs_builtin()
+        for pname, pc in (("vcycle", igamg.PRECOND_VCYCLE), ("rre3", igamg.PRECOND_RRE)):
+            x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
+            s.solve_fgmres(x, tol=1e-10, max_iters=300, m=20, precond=pc, q=3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                x.zero_()
+                st, _ = s.solve_fgmres(x, tol=1e-10, max_iters=300, m=20, precond=pc, q=3)
+            torch.cuda.synchronize()
+            fg["annulus_%d_p%d_%s" % (ne, p, pname)] = {
+                "iterations": st.restarts, "vcycles": st.vcycles, "rel_residual": st.rel_residual,
+                "ms": round((time.perf_counter() - t0) * 1e3 / steps, 3)}
+        s.close()
+    out["fgmres_table15_problem"] = fg
     s = igamg.Solver(igamg.QUARTER_ANNULUS_EXACT, N_EL, 3, radii=(0.2, 1.0), pde=igamg.PDE_ELLIPTIC_2,
                      precision=igamg.FP32_IR)
     s.set_rhs_builtin()
