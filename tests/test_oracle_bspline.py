@@ -110,40 +110,6 @@ def test_mass_stiffness_spd(p):
         assert np.linalg.eigvalsh(A).min() > 0
 
 
-def _l2_error_1d(n_el, p):
-    """Exact discrete solution of -u'' = (2 pi)^2 sin(2 pi x) and its L2 error,
-    with p+1 Gauss points per element for assembly and for the error norm."""
-    K, _ = bspline.stiffness_mass_1d(n_el, p)
-    xq, wq, V, _ = bspline.local_basis_tables(n_el, p, p + 1)
-    f = (2 * np.pi) ** 2 * np.sin(2 * np.pi * xq)
-    b = np.zeros(n_el + p)
-    for e in range(n_el):
-        b[e:e + p + 1] += V[e].T @ (wq[e] * f[e])
-    u = np.zeros(n_el + p)
-    u[1:-1] = np.linalg.solve(K, b[1:-1])
-    uh = np.einsum("eqa,ea->eq", V, np.array([u[e:e + p + 1] for e in range(n_el)]))
-    return math.sqrt(np.sum(wq * (uh - np.sin(2 * np.pi * xq)) ** 2))
-
-
-def test_table1_l2_errors_reproduced():
-    """Table 1's L2-err column (printed to 3 digits) is reproduced to 1.5 %.
-
-    Entries at or below 1e-13 sit at the paper's solver-tolerance floor and are
-    only required to be at that floor."""
-    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_l2err_1d.txt"))
-            if l.strip() and not l.startswith("#")]
-    checked = 0
-    for ne, p, v in rows:
-        ne, p, v = int(ne), int(p), float(v)
-        e = _l2_error_1d(ne, p)
-        if v > 1e-13:
-            assert abs(e / v - 1) < 0.015, (ne, p, v, e)
-            checked += 1
-        else:
-            assert e < 2e-13
-    assert checked == 22
-
-
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_prolongation_interior_columns_binomial(p):
     """Midpoint knot insertion: interior columns of P1 are 2^-p C(p+1, k)."""
