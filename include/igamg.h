@@ -366,6 +366,69 @@ igamg_status igamg_batch_instance(igamg_batch* batch, int i, igamg_ctx** ctx);
 igamg_status igamg_solve_batch(igamg_batch* batch, double tol, int max_restarts, int q,
                                double* const* x_dev, igamg_stats* stats);
 
+/* ---- 1D model problems ----------------------------------------------------
+ * The model problem of Section 2.4, eq. (6): -u'' = (2 pi)^2 sin(2 pi x) on
+ * (0, 1), u(0) = u(1) = 0, exact solution u = sin(2 pi x), discretised as in
+ * Section 2 with B-splines of degree 1..9 on n_el uniform elements (interior
+ * unknowns n = n_el + degree - 2, x index order), stiffness and load by Gauss
+ * quadrature with degree+1 points per element, `levels` grids (the coarsest
+ * has n_el / 2^(levels-1) elements; Table 1's nlevels = 4) with Galerkin
+ * coarse matrices (eq. (4)) and a direct coarsest solve.  A set holds `count`
+ * independent problems; every call runs each problem in one workgroup of one
+ * launch (Algorithm 5 around mu-cycles of Algorithm 2, all of it on the
+ * device, FP64), so a set of many problems fills the chip.  The level vectors
+ * of a problem live in LDS: 3 * sum_l n_l <= 16384 (EINVAL otherwise).  All
+ * work is on the stream given to igamg_setup_1d (NULL: the set creates a
+ * blocking stream); the calls synchronise it before returning. */
+typedef struct {
+    int n_el;       /* elements, a multiple of 2^(levels-1)                     */
+    int degree;     /* 1..9                                                     */
+    int levels;     /* 1..16                                                    */
+    int smoother;   /* IGAMG_SMOOTH_JACOBI (weighted, omega) or _MCGS (p+1
+                       colours i mod (p+1))                                     */
+    int nu1, nu2;   /* pre- and post-smoothing sweeps (0..64)                   */
+    int mu;         /* cycle index: 1 V-cycle, 2 W-cycle (1..4)                 */
+    double omega;   /* Jacobi weight in (0, 2)                                  */
+    int method;     /* igamg_extrap: NONE (plain cycles), RRE or MPE            */
+    int q;          /* restart number 1..8 (RRE/MPE)                            */
+} igamg_problem1d;
+/* Section 4.1's setting: 64 elements, degree 2, 4 levels, weighted Jacobi
+ * V(1,1) with omega = 2/3, no extrapolation, q = 4. */
+void igamg_problem1d_default(igamg_problem1d* pr);
+
+typedef struct {
+    int restarts;         /* restart cycles (V-cycles for method NONE)           */
+    int vcycles;          /* cycles of Algorithm 2                               */
+    int breakdowns;       /* restarts with no extrapolation (t = s_{q+1})        */
+    int converged;        /* 1 if ||b - A x|| / ||b|| <= tol                     */
+    double rel_residual;  /* ||b - A x|| / ||b|| of the returned x               */
+    double l2_error;      /* ||u_h - sin(2 pi x)||_L2, degree+1 Gauss points
+                             per element (the model right-hand side)            */
+    double solve_ms;      /* host wall time of the call (all problems)          */
+} igamg_stats1d;
+
+typedef struct igamg_set1d igamg_set1d;
+/* Builds every problem (bands, transfer tables, coarsest inverse, element
+ * tables, the load vector of f = (2 pi)^2 sin(2 pi x)).  Errors: EINVAL (bad
+ * fields, too large for LDS), ENOTSPD, ENOMEM, EHIP. */
+igamg_status igamg_setup_1d(int count, const igamg_problem1d* probs, void* stream, igamg_set1d** out);
+void igamg_destroy_1d(igamg_set1d* set);
+/* Unknowns of problem i, or -1 for a bad set or index. */
+long long igamg_ndof_1d(const igamg_set1d* set, int i);
+/* Replace / read problem i's right-hand side (device FP64, ndof entries). */
+igamg_status igamg_set_rhs_1d(igamg_set1d* set, int i, const double* b_dev);
+igamg_status igamg_get_rhs_1d(igamg_set1d* set, int i, double* b_dev);
+/* ncycles mu-cycles on every problem: x_dev[i] (device FP64, ndof entries,
+ * caller-owned) is the initial guess and receives the result. */
+igamg_status igamg_cycles_1d(igamg_set1d* set, int ncycles, double* const* x_dev);
+/* Algorithm 5 with RRE(q) / MPE(q) (or plain cycles) from the initial guesses
+ * x_dev[i] until ||b - A x|| / ||b|| <= tol, tested on t after every restart
+ * (after every cycle for NONE), at most max_iters restarts (cycles); x_dev[i]
+ * receives the last accepted iterate and stats[i] (may be NULL) its counts.
+ * Returns ENOCONV if any problem did not converge, ENONFINITE on NaN/Inf. */
+igamg_status igamg_solve_1d(igamg_set1d* set, double tol, int max_iters, double* const* x_dev,
+                            igamg_stats1d* stats);
+
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* igamg_last_error(void);
 

@@ -55,8 +55,8 @@ void gauss_legendre(int m, std::vector<double>& x, std::vector<double>& w) {
 
 void basis_and_derivs(const std::vector<double>& t, int p, int s, double u, double* N,
                       double* dN) {
-    // ndu[j][r]: triangle of basis values of increasing degree j (p <= 7)
-    double ndu[8][8], left[8], right[8];
+    // ndu[j][r]: triangle of basis values of increasing degree j (p <= 9)
+    double ndu[10][10], left[10], right[10];
     ndu[0][0] = 1.0;
     for (int j = 1; j <= p; ++j) {
         left[j] = u - t[s + 1 - j];
@@ -394,7 +394,7 @@ int igamg_host_gauss_legendre(int m, double* x, double* w) {
 }
 
 int igamg_host_basis(int ne, int p, double u, double* N, double* dN, int* first) {
-    if (ne < 1 || p < 0 || p > 7 || !N || !dN || !first || !(u >= 0.0 && u <= 1.0)) return -1;
+    if (ne < 1 || p < 0 || p > 9 || !N || !dN || !first || !(u >= 0.0 && u <= 1.0)) return -1;
     std::vector<int> span;
     std::vector<double> V, D;
     igamg::eval_at_points(ne, p, std::vector<double>{u}, span, V, D);
@@ -407,7 +407,7 @@ int igamg_host_basis(int ne, int p, double u, double* N, double* dN, int* first)
 }
 
 int igamg_host_prolongation_1d(int ne_coarse, int p, double* out) {
-    if (ne_coarse < 1 || p < 1 || p > 7 || !out) return -1;
+    if (ne_coarse < 1 || p < 1 || p > 9 || !out) return -1;
     igamg::Prolong1D P = igamg::prolongation_boehm(ne_coarse, p);
     for (size_t k = 0; k < (size_t)P.nf_fun * P.nc_fun; ++k) out[k] = 0.0;
     for (int J = 0; J < P.nc_fun; ++J)
@@ -417,7 +417,7 @@ int igamg_host_prolongation_1d(int ne_coarse, int p, double* out) {
 }
 
 int igamg_host_bands(int ne, int ne_coarsest, int level, int p, double* K, double* M) {
-    if (ne < 1 || ne_coarsest < 1 || ne % ne_coarsest || p < 1 || p > 7 || !K || !M) return -1;
+    if (ne < 1 || ne_coarsest < 1 || ne % ne_coarsest || p < 1 || p > 9 || !K || !M) return -1;
     int nlev = 1;
     for (int m = ne / ne_coarsest; m > 1; m /= 2) {
         if (m % 2) return -1;

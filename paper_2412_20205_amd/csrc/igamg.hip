@@ -24,6 +24,7 @@
 #include "kernels.hpp"
 #include "learned.hpp"
 #include "batch.hpp"
+#include "solve1d.hpp"
 
 using namespace igamg;
 
@@ -2737,6 +2738,236 @@ igamg_status igamg_smoother_loss_grad(igamg_ctx* ctx, int level, const float* z,
         *loss = ctx->host_scal[5] / (double)v.N;
         for (void* a : {(void*)dit, (void*)gpart, (void*)lpart, (void*)g, (void*)ls}) ctx->release(a);
     });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// 1D model problems (Section 2.4): one workgroup per problem, one launch per call
+
+struct igamg_set1d {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<igamg_problem1d> prob;
+    std::vector<Desc1D> desc;
+    std::vector<void*> mem;
+    Desc1D* d_desc = nullptr;
+    double** d_x = nullptr;
+    Out1D* d_out = nullptr;
+    Out1D* h_out = nullptr;
+
+    template <typename T>
+    T* alloc(size_t n) {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+            throw Error(IGAMG_ENOMEM, "device allocation failed");
+        mem.push_back(p);
+        return (T*)p;
+    }
+    template <typename T>
+    T* upload(const std::vector<T>& v) {
+        T* d = alloc<T>(v.size());
+        IGAMG_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return d;
+    }
+    ~igamg_set1d() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* p : mem) (void)hipFree(p);
+        if (h_out) (void)hipHostFree(h_out);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+    // x_dev[i] of every problem, then one launch of k_solve1d
+    void run(int mode, int iters, double tol, double* const* x_dev) {
+        const int count = (int)prob.size();
+        for (int i = 0; i < count; ++i) need(x_dev[i] != nullptr, "null iterate");
+        IGAMG_HIP(hipMemcpyAsync(d_x, x_dev, count * sizeof(double*), hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(k_solve1d, dim3(count), dim3(kBlock), 0, stream, (const Desc1D*)d_desc,
+                           (double* const*)d_x, mode, iters, tol, d_out);
+        IGAMG_HIP(hipGetLastError());
+        IGAMG_HIP(hipMemcpyAsync(h_out, d_out, count * sizeof(Out1D), hipMemcpyDeviceToHost, stream));
+        IGAMG_HIP(hipStreamSynchronize(stream));
+    }
+};
+
+namespace {
+
+void setup_problem1d(igamg_set1d& S, const igamg_problem1d& pr, Desc1D& D) {
+    const int p = pr.degree, ne = pr.n_el, nlev = pr.levels;
+    need(p >= 1 && p <= kMax1DDegree, "1D degree must be in 1..9");
+    need(nlev >= 1 && nlev <= kMax1DLevels, "1D levels must be in 1..16");
+    need(ne >= 1 && ne <= (1 << 20), "1D n_el out of range");
+    const int ne0 = ne >> (nlev - 1);
+    need(ne0 >= 1 && (ne0 << (nlev - 1)) == ne, "n_el must be a multiple of 2^(levels-1)");
+    need(pr.smoother == IGAMG_SMOOTH_JACOBI || pr.smoother == IGAMG_SMOOTH_MCGS,
+         "1D smoother must be weighted Jacobi or multicolour Gauss-Seidel");
+    need(pr.nu1 >= 0 && pr.nu2 >= 0 && pr.nu1 <= 64 && pr.nu2 <= 64, "sweep counts must be in 0..64");
+    need(pr.mu >= 1 && pr.mu <= kMaxMu, "mu must be in 1..4");
+    need(pr.method == IGAMG_EXTRAP_NONE || pr.method == IGAMG_RRE || pr.method == IGAMG_MPE, "bad method");
+    need(pr.method == IGAMG_EXTRAP_NONE || (pr.q >= 1 && pr.q <= kMaxQ), "q must be in 1..8");
+    need(pr.omega > 0.0 && pr.omega < 2.0, "omega must be in (0, 2)");
+    D = Desc1D{};
+    D.p = p;
+    D.L = nlev - 1;
+    D.n_el = ne;
+    D.nq = p + 1;
+    D.smoother = pr.smoother;
+    D.nu1 = pr.nu1;
+    D.nu2 = pr.nu2;
+    D.mu = pr.mu;
+    D.method = pr.method;
+    D.q = pr.method == IGAMG_EXTRAP_NONE ? 1 : pr.q;
+    D.omega = pr.omega;
+    long long lds = 0;
+    for (int l = 0; l < nlev; ++l) {
+        D.n[l] = (ne0 << l) + p - 2;
+        need(D.n[l] >= 1, "a level has no interior unknowns");
+        D.off[l] = (int)lds;
+        lds += 3LL * D.n[l];
+    }
+    need(lds <= kLds1D, "1D problem too large for one workgroup's LDS");
+    // finest band by quadrature, coarser ones by the Galerkin product (eq. (4))
+    std::vector<Band1D> K(nlev);
+    Band1D M;
+    stiffness_mass_bands(ne, p, K[D.L], M);
+    for (int l = D.L; l >= 1; --l) {
+        TransferTables T = transfer_tables(prolongation_boehm(ne0 << (l - 1), p));
+        if (T.nf != D.n[l] || T.nc != D.n[l - 1]) throw Error(IGAMG_EINVAL, "transfer size mismatch");
+        K[l - 1] = galerkin_band(K[l], T, p);
+        D.rs[l] = S.upload(T.r_start);
+        D.rw[l] = S.upload(T.r_w);
+        D.RW[l] = T.RW;
+        D.ps[l] = S.upload(T.p_start);
+        D.pw[l] = S.upload(T.p_w);
+        D.PW[l] = T.PW;
+    }
+    for (int l = 0; l < nlev; ++l) D.K[l] = S.upload(K[l].v);
+    // coarsest inverse from the Cholesky factor
+    const int n0 = D.n[0], W = 2 * p + 1;
+    std::vector<double> A((size_t)n0 * n0, 0.0);
+    for (int i = 0; i < n0; ++i)
+        for (int d = -p; d <= p; ++d)
+            if (i + d >= 0 && i + d < n0) A[(size_t)i * n0 + i + d] = K[0].v[(size_t)i * W + d + p];
+    if (!cholesky_inplace(A, n0)) throw Error(IGAMG_ENOTSPD, "coarsest 1D operator is not SPD");
+    D.Ainv0 = S.upload(inverse_from_cholesky(A, n0));
+    ElementTables E = element_tables(ne, p, p + 1);
+    D.V = S.upload(E.V);
+    D.wq = S.upload(E.wts);
+    D.xq = S.upload(E.pts);
+    const int nL = D.n[D.L];
+    double* b = S.alloc<double>(nL);
+    hipLaunchKernelGGL(k_load1d, dim3((nL + kBlock - 1) / kBlock), dim3(kBlock), 0, S.stream, ne, p, p + 1,
+                       D.V, D.wq, D.xq, b);
+    IGAMG_HIP(hipGetLastError());
+    D.b = b;
+    D.S = S.alloc<double>((size_t)(D.q + 2) * nL);
+    D.Qm = S.alloc<double>((size_t)(D.q + 1) * nL);
+}
+
+igamg_set1d* checked_set(igamg_set1d* s, int i) {
+    need(s != nullptr, "null set");
+    need(i >= 0 && i < (int)s->prob.size(), "problem index out of range");
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void igamg_problem1d_default(igamg_problem1d* pr) {
+    if (!pr) return;
+    pr->n_el = 64;
+    pr->degree = 2;
+    pr->levels = 4;
+    pr->smoother = IGAMG_SMOOTH_JACOBI;
+    pr->nu1 = 1;
+    pr->nu2 = 1;
+    pr->mu = 1;
+    pr->omega = 2.0 / 3.0;
+    pr->method = IGAMG_EXTRAP_NONE;
+    pr->q = 4;
+}
+
+igamg_status igamg_setup_1d(int count, const igamg_problem1d* probs, void* stream, igamg_set1d** out) {
+    return guarded([&] {
+        need(count >= 1 && probs && out, "bad argument");
+        *out = nullptr;
+        std::unique_ptr<igamg_set1d> S(new igamg_set1d());
+        if (stream) {
+            S->stream = (hipStream_t)stream;
+        } else {
+            IGAMG_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamDefault));
+            S->own_stream = true;
+        }
+        S->prob.assign(probs, probs + count);
+        S->desc.resize(count);
+        for (int i = 0; i < count; ++i) setup_problem1d(*S, probs[i], S->desc[i]);
+        S->d_desc = S->upload(S->desc);
+        S->d_x = S->alloc<double*>(count);
+        S->d_out = S->alloc<Out1D>(count);
+        IGAMG_HIP(hipHostMalloc((void**)&S->h_out, count * sizeof(Out1D), hipHostMallocDefault));
+        IGAMG_HIP(hipStreamSynchronize(S->stream));
+        *out = S.release();
+    });
+}
+
+void igamg_destroy_1d(igamg_set1d* set) { delete set; }
+
+long long igamg_ndof_1d(const igamg_set1d* set, int i) {
+    if (!set || i < 0 || i >= (int)set->prob.size()) return -1;
+    return set->desc[i].n[set->desc[i].L];
+}
+
+igamg_status igamg_set_rhs_1d(igamg_set1d* set, int i, const double* b_dev) {
+    return guarded([&] {
+        checked_set(set, i);
+        need(b_dev != nullptr, "null argument");
+        const Desc1D& D = set->desc[i];
+        IGAMG_HIP(hipMemcpyAsync((void*)D.b, b_dev, D.n[D.L] * sizeof(double), hipMemcpyDeviceToDevice,
+                                 set->stream));
+        IGAMG_HIP(hipStreamSynchronize(set->stream));
+    });
+}
+
+igamg_status igamg_get_rhs_1d(igamg_set1d* set, int i, double* b_dev) {
+    return guarded([&] {
+        checked_set(set, i);
+        need(b_dev != nullptr, "null argument");
+        const Desc1D& D = set->desc[i];
+        IGAMG_HIP(hipMemcpyAsync(b_dev, D.b, D.n[D.L] * sizeof(double), hipMemcpyDeviceToDevice, set->stream));
+        IGAMG_HIP(hipStreamSynchronize(set->stream));
+    });
+}
+
+igamg_status igamg_cycles_1d(igamg_set1d* set, int ncycles, double* const* x_dev) {
+    return guarded([&] {
+        need(set && x_dev && ncycles >= 0, "bad argument");
+        set->run(1, ncycles, 0.0, x_dev);
+    });
+}
+
+igamg_status igamg_solve_1d(igamg_set1d* set, double tol, int max_iters, double* const* x_dev,
+                            igamg_stats1d* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    bool all = false;
+    igamg_status s = guarded([&] {
+        need(set && x_dev && tol > 0 && max_iters > 0, "bad argument");
+        set->run(0, max_iters, tol, x_dev);
+        all = true;
+        for (size_t i = 0; i < set->prob.size(); ++i) {
+            const Out1D& o = set->h_out[i];
+            if (o.status != 0) throw Error(o.status, "non-finite values in a 1D solve");
+            if (!o.converged) all = false;
+        }
+        if (!all) throw Error(IGAMG_ENOCONV, "some 1D problems did not converge");
+    });
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats && set && (s == IGAMG_OK || s == IGAMG_ENOCONV || s == IGAMG_ENONFINITE)) {
+        for (size_t i = 0; i < set->prob.size(); ++i) {
+            const Out1D& o = set->h_out[i];
+            stats[i] = igamg_stats1d{o.restarts, o.vcycles, o.breakdowns, o.converged, o.rel_residual, o.l2_error, ms};
+        }
+    }
+    return s;
 }
 
 }  // extern "C"

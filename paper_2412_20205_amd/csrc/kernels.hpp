@@ -1000,9 +1000,8 @@ __global__ void __launch_bounds__(kBlock) k_tsqr_node(const double* __restrict__
 // Breakdown rules: first column j with |R_jj| <= 1e-13 ||R_{:,j}|| -> use
 // columns 0..j with d = (-R_{<j}^{-1} R_{<j,j}, 1) (exact for a linear map);
 // |sum d| <= 1e-14 ||d||_1 -> info = -1 (no extrapolation).
-__global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int method,
-                                ExtrapCoeffs* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One thread; Rg row-major ncols x ncols (global or LDS).
+__device__ inline ExtrapCoeffs extrap_coefficients(const double* Rg, int ncols, int method) {
     double R[kMaxCols][kMaxCols], d[kMaxCols], y[kMaxCols];
     const int n = ncols, q = ncols - 1;
     bool finite = true;
@@ -1019,8 +1018,7 @@ __global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int me
     c.d0 = fabs(Rg[0]);
     if (!finite) {
         c.info = -2;
-        *out = c;
-        return;
+        return c;
     }
     for (int i = 0; i < n; ++i) d[i] = 0.0;
     int lucky = -1;
@@ -1067,8 +1065,7 @@ __global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int me
     }
     if (!isfinite(lam) || fabs(lam) <= 1e-14 * l1) {
         c.info = -1;
-        *out = c;
-        return;
+        return c;
     }
     double acc = 1.0;
     for (int i = 0; i < n; ++i) c.gamma[i] = d[i] / lam;
@@ -1084,7 +1081,13 @@ __global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int me
         g2 += v * v;
     }
     c.gres = sqrt(g2);
-    *out = c;
+    return c;
+}
+
+__global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int method,
+                                ExtrapCoeffs* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    *out = extrap_coefficients(Rg, ncols, method);
 }
 
 // t = s_0 + sum_{j<q} alpha_j (s_{j+1} - s_j); on breakdown t = s_{q+1}.

@@ -82,6 +82,20 @@ class IgamgError(RuntimeError):
 
 _lib = None
 _P = ctypes.c_void_p
+class Problem1D(ctypes.Structure):
+    _fields_ = [("n_el", ctypes.c_int), ("degree", ctypes.c_int), ("levels", ctypes.c_int),
+                ("smoother", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+                ("mu", ctypes.c_int), ("omega", ctypes.c_double), ("method", ctypes.c_int),
+                ("q", ctypes.c_int)]
+
+
+class Stats1D(ctypes.Structure):
+    _fields_ = [("restarts", ctypes.c_int), ("vcycles", ctypes.c_int),
+                ("breakdowns", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("l2_error", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
+
+
 _i = ctypes.c_int
 _d = ctypes.c_double
 _ll = ctypes.c_longlong
@@ -126,6 +140,14 @@ _SIGNATURES = {
     "igamg_batch_instance": (_i, [_P, _i, ctypes.POINTER(_P)]),
     "igamg_solve_batch": (_i, [_P, _d, _i, _i, _P, _P]),
     "igamg_autotune": (_i, [_P, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+    "igamg_problem1d_default": (None, [ctypes.POINTER(Problem1D)]),
+    "igamg_setup_1d": (_i, [_i, ctypes.POINTER(Problem1D), _P, ctypes.POINTER(_P)]),
+    "igamg_destroy_1d": (None, [_P]),
+    "igamg_ndof_1d": (_ll, [_P, _i]),
+    "igamg_set_rhs_1d": (_i, [_P, _i, _P]),
+    "igamg_get_rhs_1d": (_i, [_P, _i, _P]),
+    "igamg_cycles_1d": (_i, [_P, _i, _P]),
+    "igamg_solve_1d": (_i, [_P, _d, _i, _P, ctypes.POINTER(Stats1D)]),
     "igamg_last_error": (ctypes.c_char_p, []),
     "igamg_host_gauss_legendre": (_i, [_i, _P, _P]),
     "igamg_host_basis": (_i, [_i, _i, _d, _P, _P, ctypes.POINTER(_i)]),
@@ -468,6 +490,72 @@ class Batch:
                                      ctypes.cast(stats, _P))
         if check:
             _check(st, "igamg_solve_batch")
+        return [stats[i] for i in range(n)], st
+
+
+class Set1D:
+    """A set of independent 1D model problems (include/igamg.h, igamg_setup_1d),
+    each solved by one workgroup of one launch."""
+
+    def __init__(self, problems, stream=None):
+        """problems: list of dicts with any igamg_problem1d fields (others keep
+        igamg_problem1d_default's values)."""
+        import torch
+        if stream is None:
+            cs = torch.cuda.current_stream()
+            stream = None if cs.cuda_stream == 0 else cs.cuda_stream
+        n = len(problems)
+        arr = (Problem1D * n)()
+        for k, pr in enumerate(problems):
+            lib().igamg_problem1d_default(ctypes.byref(arr[k]))
+            for key, val in pr.items():
+                if not hasattr(arr[k], key):
+                    raise KeyError(key)
+                setattr(arr[k], key, val)
+        h = _P()
+        _check(lib().igamg_setup_1d(n, arr, stream, ctypes.byref(h)), "igamg_setup_1d")
+        self._h = h
+        self.problems = [dict((f, getattr(arr[k], f)) for f, _ in Problem1D._fields_) for k in range(n)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().igamg_destroy_1d(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def ndof(self, i):
+        return int(lib().igamg_ndof_1d(self._h, i))
+
+    def set_rhs(self, i, b):
+        _check(lib().igamg_set_rhs_1d(self._h, i, _ptr(b)), "igamg_set_rhs_1d")
+
+    def get_rhs(self, i, out):
+        _check(lib().igamg_get_rhs_1d(self._h, i, _ptr(out)), "igamg_get_rhs_1d")
+        return out
+
+    def cycles(self, xs, ncycles=1):
+        ptrs = (ctypes.c_void_p * len(xs))(*[_ptr(x).value for x in xs])
+        _check(lib().igamg_cycles_1d(self._h, ncycles, ctypes.cast(ptrs, _P)), "igamg_cycles_1d")
+        return xs
+
+    def solve(self, xs, tol=1e-12, max_iters=1000, check=True):
+        n = len(xs)
+        ptrs = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+        stats = (Stats1D * n)()
+        st = lib().igamg_solve_1d(self._h, tol, max_iters, ctypes.cast(ptrs, _P), stats)
+        if check:
+            _check(st, "igamg_solve_1d")
         return [stats[i] for i in range(n)], st
 
 
