@@ -203,6 +203,60 @@ def paper_setting_measure(igamg, torch, synth, steps):
     return out
 
 
+# Table 4 (1D, N = 64): V-cycle, W-cycle, RRE(q), MPE(q) iteration counts and the
+# paper's CPU seconds, p = 2..8 (q = 4 for p <= 3, 8 above).
+PAPER_TABLE4 = {2: ((6, 4, 2, 2), (0.27, 0.39, 0.30, 0.29)), 3: ((10, 7, 2, 2), (0.74, 1.01, 0.68, 0.71)),
+                4: ((20, 14, 2, 2), (2.21, 4.15, 1.79, 1.32)), 5: ((40, 27, 2, 3), (7.13, 9.28, 3.56, 3.83)),
+                6: ((81, 54, 4, 4), (19.31, 27.85, 6.37, 6.43)), 7: ((164, 109, 5, 5), (51.10, 71.94, 12.24, 12.72)),
+                8: ((347, 232, 7, 7), (141.41, 199.82, 23.86, 22.81))}
+# Table 1 (1D V-cycle(1,1), nlevels = 4): iterations per grid for p = 2..6.
+PAPER_TABLE1_ITER = {16: (6, 11, 22, 39, 87), 32: (6, 10, 20, 40, 81), 64: (6, 10, 20, 40, 81),
+                     128: (6, 10, 20, 39, 79), 256: (8, 13, 19, 38, 78)}
+
+
+def oned_measure(igamg, torch, steps):
+    """The 1D model problem of Section 2.4 (-u'' = (2 pi)^2 sin(2 pi x)), each
+    problem in one workgroup of one launch, FP64, weighted Jacobi (omega = 2/3)
+    V(1,1) on 4 levels, relative residual 1e-12.  Table 4: N = 64, p = 2..8,
+    V, W, RRE(q), MPE(q) solved one set per method (one launch), cycles /
+    restarts, L2 error and ms beside the paper's counts and CPU seconds
+    (other hardware, context only).  Table 1: its 25 problems (N = 16..256,
+    p = 2..6, plain V-cycles) as ONE set in one launch."""
+    def run(probs):
+        with igamg.Set1D(probs) as s:
+            xs = [torch.zeros(s.ndof(i), dtype=torch.float64, device="cuda:0") for i in range(len(probs))]
+            stats, _ = s.solve(xs, tol=1e-12, max_iters=5000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                for x in xs:
+                    x.zero_()
+                stats, _ = s.solve(xs, tol=1e-12, max_iters=5000)
+            torch.cuda.synchronize()
+            return stats, (time.perf_counter() - t0) * 1e3 / steps
+    t4 = {}
+    methods = (("v", 1, igamg.EXTRAP_NONE), ("w", 2, igamg.EXTRAP_NONE), ("rre", 1, igamg.RRE),
+               ("mpe", 1, igamg.MPE))
+    for k, (name, mu, m) in enumerate(methods):
+        probs = [dict(n_el=64, degree=p, levels=4, mu=mu, method=m, q=4 if p <= 3 else 8) for p in range(2, 9)]
+        # one problem per set, so each time is that problem's own solve
+        for p, pr in zip(range(2, 9), probs):
+            (st,), ms = run([pr])
+            row = t4.setdefault("p%d" % p, {"q": pr["q"]})
+            row[name] = {"iter": st.restarts, "vcycles": st.vcycles, "rel_residual": st.rel_residual,
+                         "l2_error": st.l2_error, "ms": round(ms, 3),
+                         "paper_iter": PAPER_TABLE4[p][0][k], "paper_cpu_s": PAPER_TABLE4[p][1][k]}
+    grids = sorted(PAPER_TABLE1_ITER)
+    probs = [dict(n_el=ne, degree=p, levels=4) for ne in grids for p in range(2, 7)]
+    stats, ms = run(probs)
+    t1 = {"ms_all_25_one_launch": round(ms, 3), "rows": {}}
+    for pr, st in zip(probs, stats):
+        t1["rows"]["N%d_p%d" % (pr["n_el"], pr["degree"])] = {
+            "iter": st.vcycles, "l2_error": st.l2_error,
+            "paper_iter": PAPER_TABLE1_ITER[pr["n_el"]][pr["degree"] - 2]}
+    return {"table4_n64": t4, "table1_set": t1}
+
+
 # Restart cycles printed in Tables 13 and 15 (RRE(8), tolerance 1e-12), per grid
 # (16, 32, 64 elements per direction) and degree p = 1..5.
 PAPER_TABLE13 = {16: (2, 3, 4, 6, 9), 32: (3, 3, 4, 8, 9), 64: (4, 4, 5, 9, 10)}
@@ -362,6 +416,7 @@ def main():
     ap.add_argument("--no-c1c3", action="store_true")
     ap.add_argument("--no-paper-setting", action="store_true")
     ap.add_argument("--no-elliptic", action="store_true")
+    ap.add_argument("--no-1d", action="store_true")
     ap.add_argument("--only-batch", action="store_true")
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--tail-items", type=int, default=-1,
@@ -491,6 +546,11 @@ def main():
         log("[bench] full elliptic problems (Tables 13, 15)")
         elliptic = elliptic_measure(igamg, torch, max(1, args.steps // 2))
 
+    oned = None
+    if not args.no_1d:
+        log("[bench] 1D model problem (Tables 1, 4)")
+        oned = oned_measure(igamg, torch, max(1, args.steps // 2))
+
     batch = None
     if not args.no_batch:
         log("[bench] batch of 96 problems")
@@ -538,7 +598,8 @@ def main():
                    "unit_square_64_p2": c1,
                    "unit_cube_128_p3": c3,
                    "paper_setting_square64_jacobi": paper,
-                   "full_elliptic": elliptic},
+                   "full_elliptic": elliptic,
+                   "poisson_1d": oned},
         "roofline": headline["smoother_fp32"],
         "cpu_baseline": cpu,
     }
