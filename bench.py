@@ -395,7 +395,11 @@ def cpu_baseline(p, gpu_restarts):
                                   max_restarts=max(gpu_restarts, 1))
     solve_s = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    # the same DOF-update count as the GPU forms: unknowns of every smoothed level
+    # x 4 sweeps (V(2,2)) x V-cycles
+    upd = sum(lev.A.shape[0] for lev in H.levels[1:]) * 4 * st.vcycles
     return x, {"value": round(solve_s * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+               "dof_updates_per_s": round(upd / solve_s, 1),
                "sample": "full FP64 restarted RRE(5) solve, quarter annulus p=%d 1024^2, x0=0, "
                          "tol 1e-10 (setup %.1f s excluded); restarts=%d vcycles=%d"
                          % (p, setup_s, st.restarts, st.vcycles),
