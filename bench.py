@@ -422,6 +422,8 @@ def main():
     ap.add_argument("--no-elliptic", action="store_true")
     ap.add_argument("--no-1d", action="store_true")
     ap.add_argument("--only-batch", action="store_true")
+    ap.add_argument("--only-1d", action="store_true",
+                    help="only the 1D model problem leg (Tables 1 and 4), printed as its own JSON line")
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--tail-items", type=int, default=-1,
                     help="single-workgroup V-cycle threshold (0 = one launch per step everywhere, "
@@ -469,6 +471,10 @@ def main():
     if args.only_batch:
         print(json.dumps({"batch": batch_measure(igamg, torch, synth, args.steps, args.warmup)}),
               flush=True)
+        return
+
+    if args.only_1d:
+        print(json.dumps({"poisson_1d": oned_measure(igamg, torch, args.steps)}), flush=True)
         return
 
     degrees = [int(v) for v in args.degrees.split(",")]
