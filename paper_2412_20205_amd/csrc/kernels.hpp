@@ -430,10 +430,14 @@ constexpr bool row_kernel_ok() {
 }
 // Colour steps loaded ahead of the one being updated (register budget of the
 // ring: about half of the 256 registers a lane has at 512 threads).
+// Measured on the 1024^2 annulus: FP32 at p = 4 gains from one step ahead
+// (21.9 against 22.8 us per finest launch, 205 registers) although its ring
+// exceeds the budget; two steps ahead at p = 3 (191 registers) lose (18.6
+// against 17.3 us).
 template <class Op>
 constexpr int row_depth() {
     constexpr int per = (Op::S + 1) * (int)sizeof(typename Op::T) / 4;
-    constexpr int d = 120 / per - 1;
+    constexpr int d = (Op::kP == 4 && sizeof(typename Op::T) == 4) ? 1 : 120 / per - 1;
     return d < 0 ? 0 : (d > Op::kP ? Op::kP : d);
 }
 
