@@ -522,6 +522,24 @@ def main():
                          "dof_updates_per_s": round(dof_updates(s, st.vcycles, 4) / (ms * 1e-3), 1)}
             res["setup_ms"] = round(st.setup_ms, 1)
             xsol[(p, name)] = x
+        if p == args.headline_degree and trained:
+            # held-out right-hand sides (seed 5900 decided the acceptance)
+            ev = {}
+            for seed in range(5901, 5910):
+                s.set_rhs_field(synth.random_field_modes(seed))
+                row = {}
+                for tag, learned in (("learned", True), ("plain_gs", False)):
+                    ms_e, st_e, _ = time_form(s, igamg, torch, igamg.RRE, igamg.FP32_IR, 1, 1, learned, True)
+                    row[tag] = {"ms": round(ms_e, 3), "vcycles": st_e.vcycles,
+                                "learned_fallbacks": st_e.learned_fallbacks}
+                ev[str(seed)] = row
+            res["learned_heldout"] = {
+                "seeds": ev,
+                "vcycles_learned": sum(r["learned"]["vcycles"] for r in ev.values()),
+                "vcycles_plain_gs": sum(r["plain_gs"]["vcycles"] for r in ev.values()),
+                "ms_learned": round(sum(r["learned"]["ms"] for r in ev.values()), 3),
+                "ms_plain_gs": round(sum(r["plain_gs"]["ms"] for r in ev.values()), 3)}
+            s.set_rhs_field(synth.random_field_modes(2000 + p))
         x64 = xsol[(p, "rre_fp64")]
         for name in ("ir_rre", "chosen"):
             res[name]["err_vs_fp64_rre"] = float(torch.linalg.norm(xsol[(p, name)] - x64) /
