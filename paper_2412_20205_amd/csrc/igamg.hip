@@ -2825,6 +2825,15 @@ void setup_problem1d(igamg_set1d& S, const igamg_problem1d& pr, Desc1D& D) {
         lds += 3LL * D.n[l];
     }
     need(lds <= kLds1D, "1D problem too large for one workgroup's LDS");
+    // the bands follow the vectors in LDS when they fit (read at LDS latency
+    // by every step of the cycle), else they are read through the caches
+    long long band_vals = 0;
+    for (int l = 0; l < nlev; ++l) band_vals += (2LL * p + 1) * D.n[l];
+    D.bands_lds = lds + band_vals <= kLds1D ? 1 : 0;
+    for (int l = 0; l < nlev && D.bands_lds; ++l) {
+        D.boff[l] = (int)lds;
+        lds += (2LL * p + 1) * D.n[l];
+    }
     // finest band by quadrature, coarser ones by the Galerkin product (eq. (4))
     std::vector<Band1D> K(nlev);
     Band1D M;

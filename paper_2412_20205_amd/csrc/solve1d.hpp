@@ -4,9 +4,9 @@
 // A 1D problem has at most a few thousand unknowns, far too few to fill the
 // chip, so each problem of a set is solved by ONE workgroup in ONE launch:
 // Algorithm 5 (restarted RRE/MPE, Algorithms 3 and 4) around mu-cycles of
-// Algorithm 2, with every level's iterate, right-hand side and residual in LDS
-// and the (2p+1)-wide bands, transfer tables and coarsest inverse read through
-// the caches.  The iterates s_0 .. s_{q+1} and the orthonormal columns of the
+// Algorithm 2, with every level's iterate, right-hand side and residual in LDS,
+// the (2p+1)-wide bands too when they fit beside them (staged once per launch),
+// and the transfer tables and coarsest inverse read through the caches.  The iterates s_0 .. s_{q+1} and the orthonormal columns of the
 // QR factorisation live in a per-problem global workspace, touched once per
 // cycle.  A set of problems occupies one workgroup per problem (one per CU).
 #pragma once
@@ -15,7 +15,7 @@ namespace igamg {
 
 constexpr int kMax1DLevels = 16;
 constexpr int kMax1DDegree = 9;
-constexpr int kLds1D = 16384;  // doubles of LDS for x, b, r of every level (128 KB)
+constexpr int kLds1D = 16384;  // doubles of LDS: x, b, r of every level, then the bands if they fit (128 KB)
 
 struct Desc1D {
     int p, L, n_el, nq;
@@ -23,6 +23,8 @@ struct Desc1D {
     double omega;
     int n[kMax1DLevels];    // unknowns of level l
     int off[kMax1DLevels];  // LDS offset of x_l; b_l and r_l follow, n_l each
+    int bands_lds;          // 1: every level's band is copied to LDS at boff[l]
+    int boff[kMax1DLevels];
     const double* K[kMax1DLevels];  // n_l x (2p+1) bands: K[i*(2p+1) + d + p] = A_l[i, i+d]
     const int* rs[kMax1DLevels];    // restriction of level l (to l-1): windows and weights
     const double* rw[kMax1DLevels];
@@ -122,6 +124,7 @@ struct Work1D {
     double* red;
 
     __device__ double* x(int l) const { return lds + D.off[l]; }
+    __device__ const double* band(int l) const { return D.bands_lds ? lds + D.boff[l] : D.K[l]; }
     __device__ double* b(int l) const { return lds + D.off[l] + D.n[l]; }
     __device__ double* r(int l) const { return lds + D.off[l] + 2 * D.n[l]; }
 
@@ -130,7 +133,7 @@ struct Work1D {
     // rows of one colour are more than p apart, so they do not couple).
     __device__ void smooth(int l, int nsweeps) const {
         const int n = D.n[l], p = D.p, W = 2 * p + 1;
-        const double* K = D.K[l];
+        const double* K = band(l);
         double *xl = x(l), *bl = b(l), *rl = r(l);
         for (int s = 0; s < nsweeps; ++s) {
             if (D.smoother == IGAMG_SMOOTH_JACOBI) {
@@ -152,7 +155,7 @@ struct Work1D {
     // r_l = b_l - A_l x_l; b_{l-1} = P_l^T r_l; x_{l-1} = 0.
     __device__ void restrict_residual(int l) const {
         const int n = D.n[l], nc = D.n[l - 1], p = D.p, RW = D.RW[l];
-        const double* K = D.K[l];
+        const double* K = band(l);
         double *xl = x(l), *bl = b(l), *rl = r(l);
         for (int i = threadIdx.x; i < n; i += kBlock) rl[i] = bl[i] - band_row(K, xl, i, n, p);
         __syncthreads();
@@ -243,7 +246,7 @@ struct Work1D {
     // ||b_L - A_L x_L||_2 (uses r_L as scratch).
     __device__ double residual_norm() const {
         const int L = D.L, n = D.n[L], p = D.p;
-        const double* K = D.K[L];
+        const double* K = band(L);
         const double *xl = x(L), *bl = b(L);
         double s = 0.0;
         for (int i = threadIdx.x; i < n; i += kBlock) {
@@ -278,6 +281,14 @@ __global__ void __launch_bounds__(kBlock) k_solve1d(const Desc1D* __restrict__ d
         for (int i = threadIdx.x; i < n; i += kBlock) {
             xl[i] = xg[i];
             bl[i] = D.b[i];
+        }
+        if (D.bands_lds) {
+            const int W = 2 * D.p + 1;
+            for (int l = 0; l <= L; ++l) {
+                double* dst = lds + D.boff[l];
+                const double* src = D.K[l];
+                for (int e = threadIdx.x; e < D.n[l] * W; e += kBlock) dst[e] = src[e];
+            }
         }
         __syncthreads();
     }
