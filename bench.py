@@ -403,7 +403,28 @@ def cpu_baseline(p, gpu_restarts):
                "sample": "full FP64 restarted RRE(5) solve, quarter annulus p=%d 1024^2, x0=0, "
                          "tol 1e-10 (setup %.1f s excluded); restarts=%d vcycles=%d"
                          % (p, setup_s, st.restarts, st.vcycles),
-               "converged": bool(st.converged)}
+               "converged": bool(st.converged),
+               "poisson_1d_n64_p8": cpu_baseline_1d()}
+
+
+def cpu_baseline_1d():
+    """The oracle on Table 4's p = 8 problem (N = 64, 4 levels, weighted Jacobi
+    V(1,1), relative residual 1e-12): RRE(8) and plain V-cycles, ms per solve."""
+    import numpy as np
+
+    from oracle import extrapolation as ex, multigrid as mg, poisson1d as p1
+    H = p1.hierarchy(64, 8, 4)
+    A = H.fine.A
+    b = p1.load(64, 8)
+    nb = np.linalg.norm(b)
+    G = lambda v: mg.mu_cycle(H, 3, b, v, mg.SMOOTH_JACOBI, 1, 1, 1)
+    rn = lambda v: np.linalg.norm(b - A @ v) / nb
+    out = {}
+    for name, method in (("rre8", ex.RRE), ("v_cycle", None)):
+        t0 = time.perf_counter()
+        _, st, _ = ex.restarted_solve(G, rn, np.zeros(len(b)), 8, method, tol=1e-12, max_restarts=5000)
+        out[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "vcycles": st.vcycles}
+    return out
 
 
 def main():
