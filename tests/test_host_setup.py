@@ -45,7 +45,7 @@ def test_gauss_legendre_matches_library_routine(m):
     np.testing.assert_allclose(w, wr, atol=1e-15)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 8, 9])
 def test_basis_matches_cox_de_boor(p):
     ne = 7
     t = bspline.open_uniform_knots(ne, p)
@@ -58,7 +58,7 @@ def test_basis_matches_cox_de_boor(p):
         assert abs(Nr.sum() - N.sum()) < 1e-14   # every nonzero function is in the window
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 9])
 @pytest.mark.parametrize("nc", [4, 5, 16])
 def test_knot_insertion_equals_collocation(p, nc):
     Pb = igamg.host_prolongation_1d(nc, p)
@@ -66,7 +66,7 @@ def test_knot_insertion_equals_collocation(p, nc):
     np.testing.assert_allclose(Pb, Pc, atol=1e-14)
 
 
-@pytest.mark.parametrize("p", [2, 3, 5])
+@pytest.mark.parametrize("p", [2, 3, 5, 8, 9])
 def test_galerkin_bands_match_oracle(p):
     ne, nc0 = 32, 4
     K, M = bspline.stiffness_mass_1d(ne, p)
@@ -87,3 +87,10 @@ def test_galerkin_bands_match_oracle(p):
                 mr = Mr[i, j] if 0 <= j < n else 0.0
                 assert abs(Kb[i, d + p] - kr) < 1e-12 * np.abs(Kr).max()
                 assert abs(Mb[i, d + p] - mr) < 1e-14
+
+
+def test_host_degree_limit():
+    """Degrees up to 9 (the 1D problems) are accepted; 10 is refused."""
+    igamg.host_basis(4, 9, 0.3)
+    with pytest.raises(ValueError):
+        igamg.host_basis(4, 10, 0.3)
