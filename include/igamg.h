@@ -422,7 +422,8 @@ igamg_status igamg_get_rhs_1d(igamg_set1d* set, int i, double* b_dev);
  * caller-owned) is the initial guess and receives the result. */
 igamg_status igamg_cycles_1d(igamg_set1d* set, int ncycles, double* const* x_dev);
 /* Algorithm 5 with RRE(q) / MPE(q) (or plain cycles) from the initial guesses
- * x_dev[i] until ||b - A x|| / ||b|| <= tol, tested on t after every restart
+ * x_dev[i] until ||b - A x|| / ||b|| <= tol (||b - A x|| <= tol for b = 0),
+ * tested on t after every restart
  * (after every cycle for NONE), at most max_iters restarts (cycles); x_dev[i]
  * receives the last accepted iterate and stats[i] (may be NULL) its counts.
  * Returns ENOCONV if any problem did not converge, ENONFINITE on NaN/Inf. */

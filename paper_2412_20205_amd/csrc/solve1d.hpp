@@ -295,7 +295,8 @@ __global__ void __launch_bounds__(kBlock) k_solve1d(const Desc1D* __restrict__ d
     Out1D o{0, 0, 0, 0, 0, 0.0, 0.0};
     double bsq = 0.0;
     for (int i = threadIdx.x; i < n; i += kBlock) bsq += D.b[i] * D.b[i];
-    const double bnorm = sqrt(block_sum1d(bsq, red));
+    // ||b|| (1 for a zero right-hand side, whose test is then absolute)
+    const double bn = sqrt(block_sum1d(bsq, red)), bnorm = bn > 0.0 ? bn : 1.0;
     if (mode == 1) {
         for (int k = 0; k < max_iters; ++k) {
             w.cycle();

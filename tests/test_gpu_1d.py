@@ -162,6 +162,13 @@ def test_nonconvergence_and_argument_errors():
         (st,), status = s.solve([x], tol=1e-12, max_iters=3, check=False)
         assert status == igamg.ENOCONV and st.converged == 0 and st.vcycles == 3
         assert np.linalg.norm(host(x)) > 0
+    # a zero right-hand side: the test is absolute and x = 0 is accepted at once
+    with igamg.Set1D([dict(n_el=32, degree=3, levels=3, method=igamg.RRE, q=4)]) as s:
+        s.set_rhs(0, torch.zeros(s.ndof(0), dtype=torch.float64, device=DEV))
+        x = torch.zeros(s.ndof(0), dtype=torch.float64, device=DEV)
+        (st,), status = s.solve([x], tol=1e-12, max_iters=5)
+        assert status == igamg.OK and st.converged == 1 and st.restarts == 1
+        assert st.rel_residual == 0.0 and not torch.any(x != 0)
     for bad in (dict(degree=10), dict(degree=0), dict(n_el=12, levels=4), dict(levels=0),
                 dict(smoother=igamg.SMOOTH_LEXGS), dict(mu=5), dict(method=igamg.RRE, q=9),
                 dict(omega=2.5), dict(n_el=8192, levels=4), dict(n_el=1, degree=1, levels=1)):
