@@ -384,8 +384,8 @@ typedef struct {
     int n_el;       /* elements, a multiple of 2^(levels-1)                     */
     int degree;     /* 1..9                                                     */
     int levels;     /* 1..16                                                    */
-    int smoother;   /* IGAMG_SMOOTH_JACOBI (weighted, omega) or _MCGS (p+1
-                       colours i mod (p+1))                                     */
+    int smoother;   /* IGAMG_SMOOTH_JACOBI (weighted, omega), _MCGS (p+1
+                       colours i mod (p+1)) or _LEXGS (forward, i increasing)   */
     int nu1, nu2;   /* pre- and post-smoothing sweeps (0..64)                   */
     int mu;         /* cycle index: 1 V-cycle, 2 W-cycle (1..4)                 */
     double omega;   /* Jacobi weight in (0, 2)                                  */

@@ -2798,8 +2798,9 @@ void setup_problem1d(igamg_set1d& S, const igamg_problem1d& pr, Desc1D& D) {
     need(ne >= 1 && ne <= (1 << 20), "1D n_el out of range");
     const int ne0 = ne >> (nlev - 1);
     need(ne0 >= 1 && (ne0 << (nlev - 1)) == ne, "n_el must be a multiple of 2^(levels-1)");
-    need(pr.smoother == IGAMG_SMOOTH_JACOBI || pr.smoother == IGAMG_SMOOTH_MCGS,
-         "1D smoother must be weighted Jacobi or multicolour Gauss-Seidel");
+    need(pr.smoother == IGAMG_SMOOTH_JACOBI || pr.smoother == IGAMG_SMOOTH_MCGS ||
+             pr.smoother == IGAMG_SMOOTH_LEXGS,
+         "1D smoother must be weighted Jacobi or multicolour or lexicographic Gauss-Seidel");
     need(pr.nu1 >= 0 && pr.nu2 >= 0 && pr.nu1 <= 64 && pr.nu2 <= 64, "sweep counts must be in 0..64");
     need(pr.mu >= 1 && pr.mu <= kMaxMu, "mu must be in 1..4");
     need(pr.method == IGAMG_EXTRAP_NONE || pr.method == IGAMG_RRE || pr.method == IGAMG_MPE, "bad method");

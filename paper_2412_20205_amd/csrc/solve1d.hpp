@@ -128,15 +128,23 @@ struct Work1D {
     __device__ double* b(int l) const { return lds + D.off[l] + D.n[l]; }
     __device__ double* r(int l) const { return lds + D.off[l] + 2 * D.n[l]; }
 
-    // nsweeps smoothing steps on level l (weighted Jacobi or multicolour
-    // Gauss-Seidel with the p+1 colours i mod (p+1), colours in increasing order;
-    // rows of one colour are more than p apart, so they do not couple).
+    // nsweeps smoothing steps on level l: lexicographic Gauss-Seidel, weighted
+    // Jacobi, or multicolour Gauss-Seidel with the p+1 colours i mod (p+1),
+    // colours in increasing order (rows of one colour are more than p apart, so
+    // they do not couple).
     __device__ void smooth(int l, int nsweeps) const {
         const int n = D.n[l], p = D.p, W = 2 * p + 1;
         const double* K = band(l);
         double *xl = x(l), *bl = b(l), *rl = r(l);
         for (int s = 0; s < nsweeps; ++s) {
-            if (D.smoother == IGAMG_SMOOTH_JACOBI) {
+            if (D.smoother == IGAMG_SMOOTH_LEXGS) {
+                // forward sweep, i increasing: each row needs the new values of
+                // the p rows before it, a strict recurrence run by one thread
+                if (threadIdx.x == 0)
+                    for (int i = 0; i < n; ++i)
+                        xl[i] = xl[i] + (bl[i] - band_row(K, xl, i, n, p)) / K[(size_t)i * W + p];
+                __syncthreads();
+            } else if (D.smoother == IGAMG_SMOOTH_JACOBI) {
                 for (int i = threadIdx.x; i < n; i += kBlock)
                     rl[i] = (bl[i] - band_row(K, xl, i, n, p)) / K[(size_t)i * W + p];
                 __syncthreads();

@@ -2,8 +2,8 @@
 FP64 CPU oracle, through the C ABI (igamg_setup_1d / _cycles_1d / _solve_1d).
 
 Bars: load vectors to 1e-13; mu-cycle iterates (random right-hand side and
-initial guess) to 1e-12 per iterate for weighted Jacobi and multicolour
-Gauss-Seidel, V and W, p = 1..9, grids whose sizes are not multiples of the
+initial guess) to 1e-12 per iterate for weighted Jacobi, multicolour and
+lexicographic Gauss-Seidel, V and W, p = 1..9, grids whose sizes are not multiples of the
 block or the colour count, and one level; at 2048 elements (about the largest
 grid one workgroup's LDS holds) 1e-10: there one ulp on every entry of the
 oracle's own finest band (the same relative change at each offset) moves its
@@ -27,7 +27,8 @@ from test_gpu_parity import DEV, dev, host, rel
 
 pytestmark = pytest.mark.gpu
 
-SMOOTHERS = {igamg.SMOOTH_JACOBI: mg.SMOOTH_JACOBI, igamg.SMOOTH_MCGS: mg.SMOOTH_MCGS}
+SMOOTHERS = {igamg.SMOOTH_JACOBI: mg.SMOOTH_JACOBI, igamg.SMOOTH_MCGS: mg.SMOOTH_MCGS,
+             igamg.SMOOTH_LEXGS: mg.SMOOTH_LEXGS}
 METHODS = {igamg.EXTRAP_NONE: None, igamg.RRE: ex.RRE, igamg.MPE: ex.MPE}
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -58,6 +59,9 @@ CYCLE_CASES = [
     (64, 8, 4, igamg.SMOOTH_JACOBI, 1, 1, 1),
     (32, 9, 3, igamg.SMOOTH_MCGS, 3, 1, 1),
     (8, 2, 1, igamg.SMOOTH_JACOBI, 1, 1, 1),
+    (64, 2, 4, igamg.SMOOTH_LEXGS, 1, 1, 1),
+    (48, 5, 3, igamg.SMOOTH_LEXGS, 2, 2, 1),
+    (32, 9, 3, igamg.SMOOTH_LEXGS, 1, 1, 2),
     (2048, 3, 4, igamg.SMOOTH_MCGS, 1, 1, 1),
     (2048, 6, 6, igamg.SMOOTH_JACOBI, 2, 1, 1),
 ]
@@ -118,6 +122,25 @@ def test_solve_matches_oracle(n_el, p, method):
     assert abs(st.l2_error - e_ref) <= 1e-6 * e_ref + 1e-13
 
 
+@pytest.mark.parametrize("p,method", [(3, igamg.RRE), (5, igamg.EXTRAP_NONE)])
+def test_lexicographic_solve_matches_oracle(p, method):
+    """Lexicographic Gauss-Seidel V(1,1) (the paper's other relaxation for its 1D
+    runs), N = 64, 4 levels, relative residual 1e-12."""
+    print("[1d] lexgs solve p=%d method=%d" % (p, method), flush=True)
+    H = p1.hierarchy(64, p, 4)
+    A = H.fine.A
+    b = p1.load(64, p)
+    G = _oracle_cycle(H, b, igamg.SMOOTH_LEXGS, 1, 1, 1)
+    rn = lambda x: np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    xr, st_r, _ = ex.restarted_solve(G, rn, np.zeros(len(b)), 4, METHODS[method], tol=1e-12, max_restarts=3000)
+    with igamg.Set1D([dict(n_el=64, degree=p, levels=4, smoother=igamg.SMOOTH_LEXGS, method=method, q=4)]) as s:
+        xg = torch.zeros(len(b), dtype=torch.float64, device=DEV)
+        (st,), _ = s.solve([xg], tol=1e-12, max_iters=3000)
+        x = host(xg)
+    assert st.restarts == st_r.restarts and st.vcycles == st_r.vcycles
+    assert rn(x) <= 1.0000001e-12 and rel(x, xr) < 1e-10
+
+
 def test_set_of_mixed_problems_equals_single_solves():
     probs = [dict(n_el=64, degree=2, levels=4, method=igamg.RRE, q=4),
              dict(n_el=128, degree=5, levels=4, method=igamg.MPE, q=8),
@@ -170,7 +193,7 @@ def test_nonconvergence_and_argument_errors():
         assert status == igamg.OK and st.converged == 1 and st.restarts == 1
         assert st.rel_residual == 0.0 and not torch.any(x != 0)
     for bad in (dict(degree=10), dict(degree=0), dict(n_el=12, levels=4), dict(levels=0),
-                dict(smoother=igamg.SMOOTH_LEXGS), dict(mu=5), dict(method=igamg.RRE, q=9),
+                dict(smoother=igamg.SMOOTH_LEARNED), dict(mu=5), dict(method=igamg.RRE, q=9),
                 dict(omega=2.5), dict(n_el=8192, levels=4), dict(n_el=1, degree=1, levels=1)):
         with pytest.raises(igamg.IgamgError):
             igamg.Set1D([bad])
