@@ -179,3 +179,37 @@ def test_fullsize_learned_annulus():
         runs[learned] = st.vcycles
     assert runs[True] < runs[False], runs
     s.close()
+
+
+def test_fullsize_batch():
+    """The benchmark's batch: 96 problems (seeded sizes 32^2..512^2, p = 2..5,
+    square or annulus, right-hand sides 4000 + i), autotuned splits, RRE(5)
+    around FP32 V-cycles in FP64 refinement.  Every member converges; the
+    largest annulus, the largest square, the highest-degree annulus and the
+    smallest member reach 1e-10 by the oracle's own operator."""
+    probs = synth.batch_instances(96, 4)
+    geo = {0: igamg.UNIT_SQUARE, 1: igamg.QUARTER_ANNULUS}
+    print("[fullsize] batch of %d" % len(probs), flush=True)
+    B = igamg.Batch([(geo[g], ne, p) for ne, p, g, _ in probs], tail_items=-1)
+    xs = []
+    for i, (ne, p, g, seed) in enumerate(probs):
+        B.instances[i].set_rhs_field(synth.random_field_modes(seed))
+        xs.append(torch.zeros(B.instances[i].ndof, dtype=torch.float64, device=DEV))
+    stats, status = B.solve(xs, tol=1e-10, max_restarts=200, q=5)
+    assert status == igamg.OK
+    assert all(st.rel_residual <= 1.0000001e-10 for st in stats)
+    size = lambda i: probs[i][0]
+    ann = [i for i in range(len(probs)) if probs[i][2] == 1]
+    sq = [i for i in range(len(probs)) if probs[i][2] == 0]
+    picks = {max(ann, key=size), max(sq, key=size), max(ann, key=lambda i: (probs[i][1], size(i))),
+             min(range(len(probs)), key=size)}
+    for i in sorted(picks):
+        ne, p, g, seed = probs[i]
+        print("[fullsize] batch member %d: n_el=%d p=%d geometry=%d" % (i, ne, p, g), flush=True)
+        modes = synth.random_field_modes(seed)
+        if g == 1:
+            A, b = assemble.mapped_stiffness_2d(ne, p), assemble.load_vector_2d(ne, p, modes)
+        else:
+            A, b = assemble.kron_operator_2d(ne, p), assemble.kron_load_2d(ne, p, modes)
+        assert np.linalg.norm(b - A @ host(xs[i])) / np.linalg.norm(b) <= 1.0000001e-10
+    B.close()
