@@ -91,6 +91,30 @@ def test_cycle_iterates(n_el, p, levels, smoother, mu, nu1, nu2):
         assert rel(host(x2), host(xg)) < 1e-14
 
 
+def test_cycles_on_a_mixed_set():
+    """Cycles on a set of different problems in one launch: every problem's
+    iterates equal the oracle's (1e-12 per iterate)."""
+    probs = [(64, 2, 4, igamg.SMOOTH_JACOBI, 1), (40, 5, 3, igamg.SMOOTH_MCGS, 2),
+             (96, 3, 4, igamg.SMOOTH_LEXGS, 1), (16, 9, 2, igamg.SMOOTH_JACOBI, 3)]
+    print("[1d] cycles on a mixed set of %d" % len(probs), flush=True)
+    with igamg.Set1D([dict(n_el=ne, degree=p, levels=lv, smoother=sm, mu=mu) for ne, p, lv, sm, mu in probs]) as s:
+        refs, xs = [], []
+        for i, (ne, p, lv, sm, mu) in enumerate(probs):
+            H = p1.hierarchy(ne, p, lv)
+            n = H.fine.A.shape[0]
+            b = synth.random_vector(n, 300 + i)
+            x0 = synth.random_vector(n, 400 + i)
+            s.set_rhs(i, dev(b))
+            refs.append((_oracle_cycle(H, b, sm, 1, 1, mu), x0.copy()))
+            xs.append(dev(x0))
+        for it in range(2):
+            s.cycles(xs, 1)
+            for i, (G, xr) in enumerate(refs):
+                xr = G(xr)
+                refs[i] = (G, xr)
+                assert rel(host(xs[i]), xr) < 1e-12, (i, it)
+
+
 SOLVE_CASES = [(64, p, m) for p in (2, 3, 4, 5, 6, 8) for m in (igamg.RRE, igamg.MPE, igamg.EXTRAP_NONE)]
 
 
