@@ -6,9 +6,9 @@
 // Algorithm 5 (restarted RRE/MPE, Algorithms 3 and 4) around mu-cycles of
 // Algorithm 2, with every level's iterate, right-hand side and residual in LDS,
 // the (2p+1)-wide bands too when they fit beside them (staged once per launch),
-// and the transfer tables and coarsest inverse read through the caches.  The iterates s_0 .. s_{q+1} and the orthonormal columns of the
-// QR factorisation live in a per-problem global workspace, touched once per
-// cycle.  A set of problems occupies one workgroup per problem (one per CU).
+// and the transfer tables and coarsest inverse read through the caches.  The
+// iterates s_0 .. s_{q+1} and the orthonormal columns of the QR factorisation
+// live in a per-problem global workspace, touched once per cycle.  A set of problems occupies one workgroup per problem (one per CU).
 #pragma once
 
 namespace igamg {

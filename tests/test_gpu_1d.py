@@ -3,15 +3,17 @@ FP64 CPU oracle, through the C ABI (igamg_setup_1d / _cycles_1d / _solve_1d).
 
 Bars: load vectors to 1e-13; mu-cycle iterates (random right-hand side and
 initial guess) to 1e-12 per iterate for weighted Jacobi, multicolour and
-lexicographic Gauss-Seidel, V and W, p = 1..9, grids whose sizes are not multiples of the
-block or the colour count, and one level; at 2048 elements (about the largest
-grid one workgroup's LDS holds) 1e-10: there one ulp on every entry of the
-oracle's own finest band (the same relative change at each offset) moves its
-own iterates by up to 3.8e-11 (4.7e-13 at 256 elements), through the Galerkin
-products, where a row-sum change grows like a mass term, 4x per 1D coarsening
-against the stiffness, and a coarsest matrix of condition 1e4; RRE/MPE/plain solves to 1e-12 with the oracle's restart and cycle
-counts (x within 1e-10, L2 errors equal); a set of mixed problems in one launch
-equals the problems solved one by one; Table 1's L2 errors from GPU solves.
+lexicographic Gauss-Seidel, V and W, p = 1..9, grids whose sizes are not
+multiples of the block or the colour count, one level, and mixed sets; at 2048
+elements (about the largest grid one workgroup's LDS holds) 1e-10: there one
+ulp on every entry of the oracle's own finest band (the same relative change
+at each offset) moves its own iterates by up to 3.8e-11 (4.7e-13 at 256
+elements), through the Galerkin products, where a row-sum change grows like a
+mass term, 4x per 1D coarsening against the stiffness, and a coarsest matrix
+of condition 1e4.  RRE/MPE/plain solves to 1e-12 with the oracle's restart and
+cycle counts (x within 1e-10, L2 errors equal); a set of mixed problems in one
+launch equals the problems solved one by one; Table 1's L2 errors from GPU
+solves.
 """
 import os
 
