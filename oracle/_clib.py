@@ -34,7 +34,7 @@ def lib():
     if _lib is None:
         _lib = ctypes.CDLL(build())
         _lib.orc_assemble_stiffness_2d.argtypes = [_i, _i, _i, _i, _i, _D, _D, _D, _D, _D]
-        _lib.orc_assemble_load_2d.argtypes = [_i, _i, _i, _i, _D, _D, _D, _D, _i, _D]
+        _lib.orc_assemble_load_2d.argtypes = [_i, _i, _i, _i, _i, _D, _D, _D, _D, _i, _D]
         _lib.orc_gs_lex.argtypes = [_i, _I, _I, _D, _D, _D, _D]
         _lib.orc_gs_lex_backward.argtypes = [_i, _I, _I, _D, _D, _D, _D]
         _lib.orc_gs_colour.argtypes = [_i, _I, _I, _I, _D, _D, _D, _D, _D]

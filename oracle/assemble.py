@@ -83,17 +83,20 @@ def mapped_stiffness_2d(n_el, p, geom=GEOM_ANNULUS, as_stencil=False, interior=T
     return stencil_to_csr(st, n, p)
 
 
-def load_vector_2d(n_el, p, modes, geom=GEOM_ANNULUS):
+def load_vector_2d(n_el, p, modes, geom=GEOM_ANNULUS, interior=True):
     """b_I = int f phi_I with f = sum_m a_m sin(pi (k_m x + l_m y) + phi_m).
 
     f is evaluated in physical coordinates; p+1 Gauss points per direction.
+    interior=False keeps the Dirichlet functions (n = N_el + p), so that by the
+    partition of unity (Section 2.3, Proposition 3) the entries sum to int f.
     """
     nq = p + 1
     xq, wq, V, _ = bspline.local_basis_tables(n_el, p, nq)
-    n = n_el + p - 2
+    first = 1 if interior else 0
+    n = n_el + p - 2 * first
     out = np.zeros(n * n)
     modes = np.ascontiguousarray(np.asarray(modes, dtype=np.float64).reshape(-1, 4))
-    lib().orc_assemble_load_2d(n_el, p, nq, geom, np.ascontiguousarray(xq.ravel()),
+    lib().orc_assemble_load_2d(n_el, p, nq, geom, first, np.ascontiguousarray(xq.ravel()),
                                np.ascontiguousarray(wq.ravel()),
                                np.ascontiguousarray(V.ravel()), modes.ravel().copy(),
                                len(modes), out)

@@ -128,12 +128,14 @@ void orc_assemble_stiffness_2d(int ne, int p, int nq, int geom, int first,
 /*
  * Load vector b_I = int f phi_I dx on the mapped domain, with
  * f(x, y) = sum_m a_m sin(pi (k_m x + l_m y) + phi_m) evaluated at physical
- * points; modes holds (a, k, l, phi) per mode.
+ * points; modes holds (a, k, l, phi) per mode.  first = 1 drops the two
+ * Dirichlet functions per direction (n = ne + p - 2), first = 0 keeps every
+ * function (n = ne + p).
  */
-void orc_assemble_load_2d(int ne, int p, int nq, int geom, const double* xq,
+void orc_assemble_load_2d(int ne, int p, int nq, int geom, int first, const double* xq,
                           const double* wq, const double* V, const double* modes,
                           int n_modes, double* out) {
-    const int n = ne + p - 2;
+    const int n = ne + p - 2 * first;
     const int P1 = p + 1;
     memset(out, 0, sizeof(double) * (size_t)n * n);
     for (int colour = 0; colour < P1; ++colour) {
@@ -152,11 +154,11 @@ void orc_assemble_load_2d(int ne, int p, int nq, int geom, const double* xq,
                         }
                         double w = wq[ex * nq + qx] * wq[ey * nq + qy] * fabs(det) * f;
                         for (int a2 = 0; a2 < P1; ++a2) {
-                            int jr = ey + a2 - 1;
+                            int jr = ey + a2 - first;
                             if (jr < 0 || jr >= n) continue;
                             double vy = V[((size_t)ey * nq + qy) * P1 + a2];
                             for (int a1 = 0; a1 < P1; ++a1) {
-                                int ir = ex + a1 - 1;
+                                int ir = ex + a1 - first;
                                 if (ir < 0 || ir >= n) continue;
                                 double vx = V[((size_t)ex * nq + qx) * P1 + a1];
                                 out[(size_t)ir + (size_t)n * jr] += w * vx * vy;

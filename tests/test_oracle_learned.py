@@ -88,3 +88,31 @@ def test_adam_reduces_loss():
         l, g = ln.loss_and_grads(z, t, Ws, bf16_points=False)
         Ws, st = ln.adam_step(Ws, g, st, lr=3e-3)
     assert l < 0.5 * l0
+
+
+def test_adam_two_steps_closed_form():
+    """Two Adam steps on one scalar weight, derived by hand from the update
+    rule (first and second moment averages with bias correction):
+    after gradients g1, g2 the corrected moments are
+        m^ = (b1 g1 + g2) / (1 + b1),   v^ = (b2 g1^2 + g2^2) / (1 + b2),
+    and after g1 alone they are g1 and g1^2, so the first step moves the
+    weight by lr g1 / (|g1| + eps).  A missing bias correction, square root or
+    (1 - beta) factor changes either step by a large factor."""
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    w0 = np.array([0.25])
+    g1, g2 = np.array([3.0]), np.array([-0.5])
+    st = ([np.zeros(1)], [np.zeros(1)], 0)
+    (w1,), st = ln.adam_step([w0], [g1], st, lr=lr, b1=b1, b2=b2, eps=eps)
+    step1 = lr * g1 / (abs(g1) + eps)
+    np.testing.assert_allclose(w1, w0 - step1, rtol=0, atol=1e-15)
+    (w2,), st = ln.adam_step([w1], [g2], st, lr=lr, b1=b1, b2=b2, eps=eps)
+    mh = (b1 * g1 + g2) / (1 + b1)
+    vh = (b2 * g1 ** 2 + g2 ** 2) / (1 + b2)
+    np.testing.assert_allclose(w2, w1 - lr * mh / (np.sqrt(vh) + eps), rtol=0, atol=1e-15)
+    assert st[2] == 2
+    # constant gradient: every step moves the weight by lr sign(g) for |g| >> eps
+    w = [np.array([1.0])]
+    st = ([np.zeros(1)], [np.zeros(1)], 0)
+    for k in range(5):
+        w, st = ln.adam_step(w, [np.array([7.0])], st, lr=lr)
+    np.testing.assert_allclose(w[0], 1.0 - 5 * lr, rtol=0, atol=1e-10)

@@ -205,3 +205,64 @@ def test_poisson_2d_modes_reproduce_f():
         f = sum(a * np.sin(np.pi * (kx * x + ky * y) + ph) for a, kx, ky, ph in m)
         ref = 2 * (2 * k * np.pi) ** 2 * np.sin(2 * k * np.pi * x) * np.sin(2 * k * np.pi * y)
         np.testing.assert_allclose(f, ref, atol=1e-12)
+
+
+# ---- load vector on the quarter annulus -------------------------------------
+
+def _mode_sum(modes):
+    m = np.asarray(modes, dtype=np.float64).reshape(-1, 4)
+
+    def f(x, y):
+        out = np.zeros_like(np.asarray(x, dtype=np.float64))
+        for a, k, l, ph in m:
+            out = out + a * np.sin(np.pi * (k * x + l * y) + ph)
+        return out
+    return f
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_annulus_load_equals_independent_numpy_assembly(p):
+    """The C element-scatter load vector on the annulus equals the separate
+    numpy assembly of the full elliptic oracle (its own geometry evaluation,
+    Jacobian, physical point and element loop), for the benchmark's random
+    field: b_I = int f(F(xi)) phi_I |det J| (Section 2, eq. (2); Section 4.3)."""
+    from oracle import elliptic
+    n_el = 12
+    modes = synth.random_field_modes(2000 + p)
+    b1 = assemble.load_vector_2d(n_el, p, modes)
+    b2 = elliptic.load(n_el, p, "annulus", _mode_sum(modes))
+    assert np.max(np.abs(b1 - b2)) <= 1e-14 * np.max(np.abs(b2))
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_annulus_load_integrates_area_and_moments(p):
+    """Partition of unity (Section 2.3, Proposition 3): with every function kept,
+    sum_I b_I = int_Omega f.  For f = 1 this is the area of the degree-2 annulus
+    surface, |det J| = (1 + xi)(2 - 2 eta + 2 eta^2), whose integral is exactly
+    3/2 * 5/3 = 5/2; the Gauss rule integrates it exactly.  For a
+    non-constant f evaluated at the physical point, the sum equals an adaptive
+    quadrature of f(F) |det J| over the reference square within the error of
+    the (p+1)-point Gauss rule, O(h^(2p+2)) (f taken at (xi, eta), or |det J|
+    dropped, would change it by O(1))."""
+    import scipy.integrate as si
+    n_el = 16
+    one = [[1.0, 0.0, 0.0, np.pi / 2]]
+    b = assemble.load_vector_2d(n_el, p, one, interior=False)
+    assert b.shape == ((n_el + p) ** 2,)
+    assert abs(b.sum() - 2.5) <= 1e-13
+    assert np.all(b > 0)
+    modes = [[1.0, 1.0, 0.0, 0.3], [-0.7, 0.0, 2.0, 1.1], [0.4, 2.0, 1.0, 0.0]]
+    f = _mode_sum(modes)
+    b = assemble.load_vector_2d(n_el, p, modes, interior=False)
+
+    def integrand(eta, xi):
+        x, y = (1 + xi) * (1 - eta ** 2), (1 + xi) * (2 * eta - eta ** 2)
+        return f(x, y) * (1 + xi) * (2 - 2 * eta + 2 * eta ** 2)
+    ref, err = si.dblquad(integrand, 0.0, 1.0, 0.0, 1.0, epsabs=1e-14, epsrel=1e-14)
+    assert err < 1e-12
+    h = 1.0 / n_el
+    assert abs(b.sum() - ref) <= 20.0 * h ** (2 * p + 2) + 1e-14
+    # the interior load vector is the interior block of the full one
+    bi = assemble.load_vector_2d(n_el, p, modes)
+    n = n_el + p
+    np.testing.assert_array_equal(bi, b.reshape(n, n)[1:-1, 1:-1].reshape(-1))
