@@ -17,17 +17,21 @@ right-hand side already on the device.  Forms timed per degree:
                  measured contraction on seed 5900; other degrees: ir_rre).
 `value` is the chosen form's ms per solve at the headline degree.
 
-Extra legs (reported under config, not timed into `value`): the unit square
-64^2 p = 2 and the unit cube 128^3 p = 3 workloads, the batch of 96 problems,
-and the paper's own 2D setting of Table 11 (64^2 elements, 4 levels, weighted
-Jacobi V(1,1)/W(1,1), plain and RRE/MPE, p = 1..5, relative residual 1e-12),
-and the full elliptic problems of Section 5 (Tables 13 and 15; RRE(8)).
+Extra legs (not timed into `value`): the unit square 64^2 p = 2 and the unit
+cube 128^3 p = 3 workloads, the batch of 96 problems, the paper's own 2D
+setting of Table 11 (64^2 elements, 4 levels, weighted Jacobi V(1,1)/W(1,1),
+plain and RRE/MPE, p = 1..5, relative residual 1e-12), the full elliptic
+problems of Section 4.3 (Tables 13-15; RRE(8)) and the 1D model problem
+(Tables 1 and 4).  Each leg and the per-degree results are written as one JSON
+object per line to stderr and, together, to the detail file (--detail-out);
+stdout carries exactly one compact JSON line, the last one.
 
-The roofline entry is the dominant kernel of the chosen form: one row-class
-launch of the finest-level FP32 multicolour Gauss-Seidel (the p+1 colours of
-the rows j = r mod p+1), timed live with HIP events around a replayed graph of
-sweeps (igamg_profile_smoother).  The CPU baseline is the FP64
-oracle's own restarted RRE(5) solve of the same workload on the host.
+The roofline entry is the finest-level smoother of the chosen form (the
+HBM-bound kernel): one row-class launch of the finest-level FP32 multicolour
+Gauss-Seidel (the p+1 colours of the rows j = r mod p+1), timed live with HIP
+events around a replayed graph of sweeps (igamg_profile_smoother).  The CPU
+baseline is the FP64 oracle's own restarted RRE(5) solve of the same workload
+on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --only-smoother --degree P   (kernel profiling runs)
@@ -87,11 +91,17 @@ def smoother_roofline(s, igamg, precision, nsweeps=8):
     ms, by, n = s.profile_smoother(L, precision, nsweeps)
     gbs = by / (ms * 1e-3) / 1e9
     tname = "double" if precision == igamg.FP64 else "float"
+    p = s.degree
+    if n == nsweeps * (p + 1):
+        kernel = "k_gs_rowclass<Stencil2D<%d,%s>> (finest level; the p+1 colours of a row " \
+                 "class per launch)" % (p, tname)
+        traffic = MEASURED_TRAFFIC.get((p, tname))
+    else:
+        kernel = "k_gs_colour_sliced<Stencil2D<%d,%s>> (finest level; one colour per launch)" \
+                 % (p, tname)
+        traffic = None
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": MEASURED_TRAFFIC.get((s.degree, tname)),
-            "kernel": "k_gs_rowclass<Stencil2D<%d,%s>> (finest level; the p+1 colours of a row "
-                      "class per launch)" % (s.degree, tname),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
             "avg_launch_us": round(ms * 1e3, 3), "bytes_per_launch": int(by), "launches": n}
 
 
@@ -174,7 +184,7 @@ PAPER_TABLE11_ITER = {1: (10, 4, 2, 2), 2: (13, 9, 2, 2), 3: (49, 33, 3, 3), 4: 
 
 
 def paper_setting_measure(igamg, torch, synth, steps):
-    """The paper's own 2D setting (Section 5, Table 11): unit square, 64^2
+    """The paper's own 2D setting (Section 4.2, Table 11): unit square, 64^2
     elements, 4 levels, weighted Jacobi V(1,1)/W(1,1), f of the model problem
     with exact u = sin(2 pi x) sin(2 pi y), relative residual 1e-12, FP64.
     Reports V-cycle counts, restart counts and ms per solve beside the
@@ -265,7 +275,7 @@ PAPER_TABLE14 = {16: (2, 2, 4, 6), 32: (2, 2, 4, 5), 64: (2, 2, 3, 6)}   # p = 1
 
 
 def elliptic_measure(igamg, torch, steps):
-    """The full elliptic problems of Section 5: the unit square with the first
+    """The full elliptic problems of Section 4.3: the unit square with the first
     coefficient set and f = 1 (Table 13), the quarter annulus with exact arcs,
     radii 0.2 and 1, the second coefficient set and the manufactured solution
     (Table 15), and the advection-diffusion problem with f = 1 (Table 14); RRE(8) around FP64 V(2,2) multicolour Gauss-Seidel cycles,
@@ -376,8 +386,23 @@ def c3_oracle_error(xs):
     return {k: float(np.linalg.norm(v.cpu().numpy() - u) / nu) for k, v in xs.items()}
 
 
-def cpu_baseline(p, gpu_restarts):
-    """The FP64 oracle's restarted RRE(5) solve of the same workload (p, 1024^2)."""
+def host_cpu():
+    """Host CPU model and the logical CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(p):
+    """The FP64 oracle's restarted RRE(5) solve of the same workload (p, 1024^2),
+    from x0 = 0 to the same tolerance, with its own restart bound."""
     import numpy as np
 
     import synth
@@ -391,20 +416,23 @@ def cpu_baseline(p, gpu_restarts):
     t0 = time.perf_counter()
     x, st, _ = ex.restarted_solve(lambda v: mg.vcycle(H, b, v),
                                   lambda v: np.linalg.norm(b - A @ v) / nb,
-                                  np.zeros(len(b)), Q, ex.RRE, tol=TOL,
-                                  max_restarts=max(gpu_restarts, 1))
+                                  np.zeros(len(b)), Q, ex.RRE, tol=TOL, max_restarts=50)
     solve_s = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    model, ncpu = host_cpu()
+    # the oracle's Gauss-Seidel colour loops and residuals run on OpenMP threads
+    # (OMP_NUM_THREADS, else every CPU of the affinity mask); its transfers,
+    # sparse products and QR are single-threaded numpy / scipy
+    threads = int(os.environ.get("OMP_NUM_THREADS", ncpu))
     # the same DOF-update count as the GPU forms: unknowns of every smoothed level
     # x 4 sweeps (V(2,2)) x V-cycles
     upd = sum(lev.A.shape[0] for lev in H.levels[1:]) * 4 * st.vcycles
     return x, {"value": round(solve_s * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+               "sample": "one full FP64 restarted RRE(5) solve, quarter annulus p=%d 1024^2, x0=0, "
+                         "tol 1e-10 (oracle setup %.1f s excluded); restarts=%d vcycles=%d; "
+                         "OpenMP in the GS colour loops and residuals only, the rest "
+                         "single-threaded numpy/scipy" % (p, setup_s, st.restarts, st.vcycles),
                "dof_updates_per_s": round(upd / solve_s, 1),
-               "sample": "full FP64 restarted RRE(5) solve, quarter annulus p=%d 1024^2, x0=0, "
-                         "tol 1e-10 (setup %.1f s excluded); restarts=%d vcycles=%d"
-                         % (p, setup_s, st.restarts, st.vcycles),
-               "converged": bool(st.converged),
-               "poisson_1d_n64_p8": cpu_baseline_1d()}
+               "host_cpu": model, "host_ncpu": ncpu, "converged": bool(st.converged)}
 
 
 def cpu_baseline_1d():
@@ -451,6 +479,8 @@ def main():
                          "-1 = autotuned per precision)")
     ap.add_argument("--colour-launches", action="store_true",
                     help="with --only-smoother: one launch per colour instead of per row class")
+    ap.add_argument("--detail-out", default=None,
+                    help="also write the per-degree results and extra legs to this JSON file")
     ap.add_argument("--only-smoother", action="store_true",
                     help="setup + finest-level smoother sweeps only (for kernel profiling)")
     args = ap.parse_args()
@@ -608,24 +638,50 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) p=%d" % args.headline_degree)
-        xo, cpu = cpu_baseline(args.headline_degree, headline["rre_fp64"]["restarts"])
+        xo, cpu = cpu_baseline(args.headline_degree)
         xg = xsol[(args.headline_degree, "rre_fp64")].cpu().numpy()
         xc = xsol[(args.headline_degree, "chosen")].cpu().numpy()
         cpu["gpu_fp64_rre_vs_oracle"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
         cpu["gpu_chosen_vs_oracle"] = float(np.linalg.norm(xc - xo) / np.linalg.norm(xo))
+        if not args.no_1d:
+            cpu["poisson_1d_n64_p8"] = cpu_baseline_1d()
         if c3x is not None:
             log("[bench] cube: oracle exact discrete solution")
             c3["error_vs_oracle_exact"] = c3_oracle_error(c3x)
 
     hp = args.headline_degree
-    line = {
+    detail = {"per_degree": {str(k): v for k, v in results.items()},
+              "batch": batch, "unit_square_64_p2": c1, "unit_cube_128_p3": c3,
+              "paper_setting_square64_jacobi": paper, "full_elliptic": elliptic,
+              "poisson_1d": oned, "cpu_baseline": cpu}
+    for k, v in detail.items():
+        if v is not None:
+            log(json.dumps({"leg": k, "result": v}))
+    if args.detail_out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail_out)), exist_ok=True)
+        with open(args.detail_out, "w") as f:
+            json.dump(detail, f, indent=1)
+    print(json.dumps(headline_line(args, hp, headline, cpu)), flush=True)
+
+
+def headline_line(args, hp, headline, cpu):
+    """The one compact JSON line of the run (the last line on stdout)."""
+    ch, plain = headline["chosen"], headline["plain_fp64"]
+    roof = {k: headline["smoother_fp32"][k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                                         "traffic", "kernel", "avg_launch_us",
+                                                         "bytes_per_launch")}
+    cpu_short = None
+    if cpu is not None:
+        cpu_short = {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample", "host_cpu",
+                                         "gpu_chosen_vs_oracle")}
+    return {
         "metric": METRIC,
-        "value": headline["chosen"]["ms"],
+        "value": ch["ms"],
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": headline["chosen"]["ms"],
+        "ms_per_step": ch["ms"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -634,25 +690,19 @@ def main():
         "config": {"workload": "quarter annulus (radii 1, 2), B-spline p=%d, 1024x1024 elements, "
                                "V(2,2) multicolour GS with the learned first pre-smoothing step, "
                                "9 levels, RRE(5), FP32 V-cycles in FP64 refinement, random-field "
-                               "RHS seed %d" % (hp, 2000 + hp),
-                   "degree": hp, "n_el": N_EL, "ndof": (N_EL + hp - 2) ** 2, "tol": TOL, "q": Q,
-                   "plain_fp64_ms": headline["plain_fp64"]["ms"],
-                   "rre_fp64_ms": headline["rre_fp64"]["ms"],
-                   "ir_rre_ms": headline["ir_rre"]["ms"],
-                   "chosen_uses_learned": headline["chosen"].get("learned", True),
+                               "RHS seed %d, x0=0, tol 1e-10" % (hp, 2000 + hp),
+                   "ndof": (N_EL + hp - 2) ** 2,
+                   "chosen_vcycles": ch["vcycles"], "chosen_uses_learned": ch.get("learned", True),
+                   "plain_fp64_ms": plain["ms"], "plain_fp64_vcycles": plain["vcycles"],
+                   "rre_fp64_ms": headline["rre_fp64"]["ms"], "ir_rre_ms": headline["ir_rre"]["ms"],
+                   "speedup_vs_plain_fp64": round(plain["ms"] / ch["ms"], 2),
+                   "chosen_dof_updates_per_s": ch["dof_updates_per_s"],
                    "smoother_fp64_gbs": headline["smoother_fp64"]["achieved"],
                    "smoother_fp32_gbs": headline["smoother_fp32"]["achieved"],
-                   "per_degree": {str(k): v for k, v in results.items()},
-                   "batch": batch,
-                   "unit_square_64_p2": c1,
-                   "unit_cube_128_p3": c3,
-                   "paper_setting_square64_jacobi": paper,
-                   "full_elliptic": elliptic,
-                   "poisson_1d": oned},
-        "roofline": headline["smoother_fp32"],
-        "cpu_baseline": cpu,
+                   "detail": "per-degree results and extra legs on stderr (one JSON line each)"},
+        "roofline": roof,
+        "cpu_baseline": cpu_short,
     }
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -48,7 +48,7 @@ typedef enum {
     IGAMG_ENONFINITE = -7   /* NaN or Inf met in the data or the iteration      */
 } igamg_status;
 
-/* Geometry of Sections 4 and 5: the unit square and cube use Kronecker
+/* Geometry of Sections 4.2 and 4.3: the unit square and cube use Kronecker
  * operators built from 1D stiffness and mass matrices (for the Poisson
  * operator); the quarter annulus of radii r_in < r_out is the degree-2 B-spline
  * surface F(xi, eta) = (r_in + (r_out - r_in) xi)(1 - eta^2, 2 eta - eta^2)
@@ -69,7 +69,7 @@ typedef struct {
     double r_out;
 } igamg_geometry;
 
-/* Operator (Section 5).  POISSON: -Laplace.  ELLIPTIC_1 and ELLIPTIC_2:
+/* Operator (Section 4.3).  POISSON: -Laplace.  ELLIPTIC_1 and ELLIPTIC_2:
  * -div(A grad u) + B . grad u + c u with
  *   A = [[(2 + cos x)(1 + y), cos(x+y) sin(x+y)], [cos(x+y) sin(x+y), (2 + sin y)(1 + x)]],
  *   ELLIPTIC_1 (the unit-square problem): B = (11 + sin x + y sin x - 2 cos^2(x+y),
@@ -181,7 +181,7 @@ igamg_status igamg_level_ndof(const igamg_ctx* ctx, int level, long long* n);
  * (a, k, l, m, phi) in 3D (host memory).  get_rhs copies b to a device buffer. */
 igamg_status igamg_set_rhs(igamg_ctx* ctx, const double* b, int b_on_device);
 igamg_status igamg_set_rhs_field(igamg_ctx* ctx, const double* modes, int n_modes);
-/* Right-hand side of the context's Section 5 problem, assembled like
+/* Right-hand side of the context's Section 4.3 problem, assembled like
  * set_rhs_field: ELLIPTIC_1 and ADVECTION_DIFFUSION: f = 1; ELLIPTIC_2: f = -div(A grad u) + B.grad u + c u
  * of the manufactured solution u = (x^2 + y^2 - 0.2^2)(x^2 + y^2 - 1) sin x sin y
  * (which vanishes on the boundary of QUARTER_ANNULUS_EXACT with radii 0.2 and
@@ -205,7 +205,8 @@ igamg_status igamg_vcycle(igamg_ctx* ctx, double* x_dev);
  * tree on the device.  q in 1..8.  Optional outputs (NULL to skip):
  * iterates_dev receives s_0 .. s_{q+1} (q+2 blocks of n values, device);
  * gamma receives gamma_0 .. gamma_q (host).  Breakdown (lambda ~ 0) leaves
- * x = s_{q+1} and returns EBREAKDOWN. */
+ * x = s_{q+1} and returns EBREAKDOWN; non-finite iterates leave x = s_0 and
+ * return ENONFINITE. */
 igamg_status igamg_extrapolate(igamg_ctx* ctx, int method, int q, double* x_dev,
                                double* iterates_dev, double* gamma);
 /* Flexible GMRES(m) on A x = b (restarted every m <= 30 steps), right-
@@ -233,9 +234,44 @@ igamg_status igamg_generalized_residual(const igamg_ctx* ctx, double* gres);
  * ||b - A x||_2 / ||b||_2 <= tol (tested on t only); method EXTRAP_NONE runs
  * plain V-cycles tested after each one.  max_restarts bounds the cycles
  * (V-cycles for the plain method).  stats may be NULL.  Returns ENOCONV with
- * stats filled when the bound is reached, ENONFINITE on NaN/Inf. */
+ * stats filled when the bound is reached, ENONFINITE on NaN/Inf.  On every
+ * return past the argument checks x_dev holds the accepted iterate: the last
+ * t (or V-cycle result) whose residual was finite, else the initial guess;
+ * stats count the accepted cycles and give that iterate's residual. */
 igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int method, int q,
                          double* x_dev, igamg_stats* stats);
+
+/* Checkpoint of a solve.  Algorithm 5 carries nothing from one restart cycle
+ * to the next but s_0 = t (Section 3.2), so the accepted iterate, the counts
+ * and the adaptive settings below are the whole state of a solve. */
+typedef struct {
+    int method;             /* igamg_extrap of the solve                          */
+    int q;                  /* its restart number (0 for EXTRAP_NONE)            */
+    int restarts, vcycles, breakdowns, learned_fallbacks, residual_checks;
+                            /* counts of the accepted cycles, as in igamg_stats  */
+    int learned_off;        /* 1: the fallback switched the learned step off     */
+    double rel_residual;    /* ||b - A x|| / ||b|| of the accepted iterate (the
+                               monitor's estimate when it skipped the evaluation) */
+    double gen_scale;       /* ||s_1 - s_0|| of the solve's first cycle (0: none) */
+    double monitor_ratio;   /* monitor calibration rel / g (-1: none yet)        */
+} igamg_state;
+
+/* After igamg_solve has returned (with any status past its argument checks),
+ * copies that solve's accepted iterate -- the x_dev it returned -- into x_dev
+ * (device, ndof values; NULL to skip) and its state into *state.  EINVAL if
+ * no solve has run on the context since setup, or a flexible-GMRES solve ran
+ * after it (its preconditioner reuses the checkpoint buffer). */
+igamg_status igamg_get_state(igamg_ctx* ctx, double* x_dev, igamg_state* state);
+/* Loads a state for the NEXT igamg_solve call on this context (that call
+ * only): it must use the state's method and q, starts from its own x_dev
+ * (pass the checkpointed iterate), continues the counts (max_restarts bounds
+ * the total, so max_restarts <= state.restarts runs no cycle) and takes over
+ * the learned-step fallback and the monitor calibration.  A solve resumed
+ * this way returns bit for bit the iterate and counts of the uninterrupted
+ * solve (with the monitor, the interrupted solve's last cycle evaluates the
+ * true residual, which recalibrates it).  The state may come from another
+ * context set up with the same problem and options.  EINVAL on a bad field. */
+igamg_status igamg_set_state(igamg_ctx* ctx, const igamg_state* state);
 
 /* rel = ||b - A x||_2 / ||b||_2 in FP64 on the finest level. */
 igamg_status igamg_residual(igamg_ctx* ctx, const double* x_dev, double* rel);

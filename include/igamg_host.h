@@ -35,6 +35,15 @@ int igamg_host_prolongation_1d(int ne_coarse, int p, double* out);
  * below the finest level).  Returns 0, or -1 for bad arguments. */
 int igamg_host_bands(int ne, int ne_coarsest, int level, int p, double* K, double* M);
 
+/* Dense inverse inv[n x n] (row-major) of the coarsest-level operator A[n x n]
+ * for Algorithm 2's direct coarsest solve, exactly as the setup phase forms
+ * it: from the Cholesky factor A = L L^T when symmetric != 0 (the Poisson
+ * operators, Section 2: A is SPD), else by Gauss-Jordan elimination with
+ * partial pivoting (the nonsymmetric operators of Section 4.3).  Returns 0;
+ * -4 (IGAMG_ENOTSPD) when a Cholesky pivot is not positive or an LU pivot
+ * is below 1e-14 max|A| (inv untouched); -1 for bad arguments. */
+int igamg_host_coarse_inverse(int n, const double* A, int symmetric, double* inv);
+
 #ifdef __cplusplus
 }
 #endif

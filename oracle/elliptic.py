@@ -1,6 +1,6 @@
 """Full elliptic operator -div(A grad u) + B . grad u + c u (FP64, test oracle).
 
-Paper: Section 5, the full elliptic problem with homogeneous Dirichlet
+Paper: Section 4.3, the full elliptic problem with homogeneous Dirichlet
 conditions: on the unit square with the first coefficient set (right-hand side
 f = 1, Table 13) and on a quarter annulus with radii 0.2 and 1 with the second
 coefficient set and a manufactured solution (Table 15); the discretisation is
@@ -31,13 +31,13 @@ import scipy.sparse as sp
 from . import bspline
 
 CSET_LAPLACE = "laplace"
-CSET_SQUARE = "square"     # Section 5, unit square: A, B of Table 13's problem, c = 1
-CSET_ANNULUS = "annulus"   # Section 5, quarter annulus: same A, B = (-5y, 5x), c = xy
-CSET_ADVDIFF = "advdiff"   # Section 5, advection-diffusion (Table 14): A = 0.1 I, B = (1, 1), c = 0
+CSET_SQUARE = "square"     # Section 4.3, unit square: A, B of Table 13's problem, c = 1
+CSET_ANNULUS = "annulus"   # Section 4.3, quarter annulus: same A, B = (-5y, 5x), c = xy
+CSET_ADVDIFF = "advdiff"   # Section 4.3, advection-diffusion (Table 14): A = 0.1 I, B = (1, 1), c = 0
 
 
 def _A(x, y):
-    """Diffusion tensor of both Section 5 problems (symmetric positive definite)."""
+    """Diffusion tensor of both Section 4.3 problems (symmetric positive definite)."""
     a11 = (2.0 + np.cos(x)) * (1.0 + y)
     a12 = np.cos(x + y) * np.sin(x + y)
     a22 = (2.0 + np.sin(y)) * (1.0 + x)

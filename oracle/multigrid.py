@@ -106,7 +106,7 @@ class Hierarchy:
 
 
 def build_elliptic_hierarchy(kind, n_el, p, cset, r_in=1.0, r_out=2.0, n_el_coarsest=4):
-    """Hierarchy of the full elliptic operator of Section 5 (oracle.elliptic)."""
+    """Hierarchy of the full elliptic operator of Section 4.3 (oracle.elliptic)."""
     from . import elliptic
     A = elliptic.assemble(n_el, p, kind, cset, r_in, r_out)
     return Hierarchy(A, n_el, p, 2, n_el_coarsest)

@@ -373,6 +373,18 @@ bool inverse_lu(const std::vector<double>& A, int n, std::vector<double>& inv) {
     return true;
 }
 
+int coarse_inverse(std::vector<double> A, int n, bool symmetric, std::vector<double>& inv) {
+    if (!symmetric) {
+        std::vector<double> r;
+        if (!inverse_lu(A, n, r)) return -4;
+        inv.swap(r);
+        return 0;
+    }
+    if (!cholesky_inplace(A, n)) return -4;
+    inv = inverse_from_cholesky(A, n);
+    return 0;
+}
+
 }  // namespace igamg
 
 // ---------------------------------------------------------------------------
@@ -435,6 +447,15 @@ int igamg_host_bands(int ne, int ne_coarsest, int level, int p, double* K, doubl
         K[k] = Kb.v[k];
         M[k] = Mb.v[k];
     }
+    return 0;
+}
+
+int igamg_host_coarse_inverse(int n, const double* A, int symmetric, double* inv) {
+    if (n < 1 || !A || !inv) return -1;
+    std::vector<double> M(A, A + (size_t)n * n), r;
+    int st = igamg::coarse_inverse(std::move(M), n, symmetric != 0, r);
+    if (st != 0) return st;
+    std::copy(r.begin(), r.end(), inv);
     return 0;
 }
 

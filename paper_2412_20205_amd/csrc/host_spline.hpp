@@ -77,5 +77,10 @@ std::vector<double> inverse_from_cholesky(const std::vector<double>& L, int n);
 // Inverse of a dense row-major n x n matrix by Gauss-Jordan elimination with
 // partial pivoting (nonsymmetric coarsest operators); false if singular.
 bool inverse_lu(const std::vector<double>& A, int n, std::vector<double>& inv);
+// Dense inverse of the coarsest operator (Algorithm 2's direct solve): from
+// the Cholesky factor when `symmetric`, else by LU.  Returns 0, or -4 (the
+// library's ENOTSPD) when a Cholesky pivot is not positive or the LU pivot
+// vanishes; inv is then unchanged.
+int coarse_inverse(std::vector<double> A, int n, bool symmetric, std::vector<double>& inv);
 
 }  // namespace igamg

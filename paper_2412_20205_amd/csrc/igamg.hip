@@ -127,6 +127,14 @@ struct igamg_ctx {
     double* kry_h = nullptr;
     double* kry_partial = nullptr;
     double* bsave = nullptr;
+    // checkpoint of the last restarted solve: the accepted iterate (also the
+    // iterate a restart cycle started from, while it runs) and its counters;
+    // a state loaded by igamg_set_state for the next solve
+    double* ckpt = nullptr;
+    bool have_state = false;
+    igamg_state state{};
+    bool resume = false;
+    igamg_state resume_state{};
     ExtrapCoeffs last_coeffs{};          // of the last extrapolation read back
     bool have_coeffs = false;
     int tail_top = 0;  // levels 0..tail_top run in the single-workgroup kernel
@@ -668,6 +676,7 @@ struct igamg_ctx {
 
     void ensure_iterates(int q) {
         while ((int)S.size() < q + 2) S.push_back(alloc<double>(lv[L].N));
+        if (!ckpt) ckpt = alloc<double>(lv[L].N);
         int ncols = q + 1;
         long long leaves = (lv[L].N + kQrRows - 1) / kQrRows;
         size_t need = (size_t)leaves * ncols * ncols;
@@ -713,7 +722,8 @@ struct igamg_ctx {
     }
 
     // One restart cycle (Algorithm 5 body) on the iterate buffers: S[0] holds
-    // s_0 on entry and t on exit; the residual norm of t goes to scal[0]
+    // s_0 on entry and t on exit (s_0 again if the coefficients are not
+    // finite), ckpt receives s_0; the residual norm of S[0] goes to scal[0]
     // (unless with_resnorm is false).
     void restart_cycle(int method, int q, bool with_resnorm = true) {
         long long N = lv[L].N;
@@ -724,13 +734,15 @@ struct igamg_ctx {
         IterPtrs it = iter_ptrs(q);
         extrap_coeffs_async(it, q, method);
         hipLaunchKernelGGL(k_extrap_combine, dim3(grid_for(N)), dim3(kBlock), 0, stream, it, q, N,
-                           (const ExtrapCoeffs*)coeffs, S[0]);
+                           (const ExtrapCoeffs*)coeffs, S[0], ckpt);
         check_launch();
         if (with_resnorm) resnorm_async(S[0]);
     }
 
-    // Plain multigrid step on S[0]: one application of G and the residual norm.
+    // Plain multigrid step on S[0]: one application of G and the residual norm;
+    // ckpt receives the iterate it starts from.
     void plain_cycle() {
+        copy(S[0], ckpt, lv[L].N);
         G(S[0]);
         resnorm_async(S[0]);
     }
@@ -1042,14 +1054,12 @@ void igamg_ctx::setup_annulus() {
             A[(size_t)I * n0 + i2 + c.n * j2] = st[(size_t)I * Sn + o];
         }
     }
-    if (opt.pde != IGAMG_PDE_POISSON) {  // nonsymmetric: LU with partial pivoting
-        std::vector<double> inv;
-        if (!inverse_lu(A, n0, inv)) throw Error(IGAMG_ENOTSPD, "coarsest operator is singular");
-        Ainv0 = upload(inv);
-        return;
-    }
-    if (!cholesky_inplace(A, n0)) throw Error(IGAMG_ENOTSPD, "coarsest operator is not SPD");
-    Ainv0 = upload(inverse_from_cholesky(A, n0));
+    // nonsymmetric operators: LU with partial pivoting; Poisson: Cholesky
+    const bool sym = opt.pde == IGAMG_PDE_POISSON;
+    std::vector<double> inv;
+    if (coarse_inverse(std::move(A), n0, sym, inv) != 0)
+        throw Error(IGAMG_ENOTSPD, sym ? "coarsest operator is not SPD" : "coarsest operator is singular");
+    Ainv0 = upload(inv);
 }
 
 void igamg_ctx::setup_coarse() {
@@ -1074,8 +1084,10 @@ void igamg_ctx::setup_coarse() {
             A[(size_t)I * n0 + J] = v;
         }
     }
-    if (!cholesky_inplace(A, n0)) throw Error(IGAMG_ENOTSPD, "coarsest operator is not SPD");
-    Ainv0 = upload(inverse_from_cholesky(A, n0));
+    std::vector<double> inv;
+    if (coarse_inverse(std::move(A), n0, true, inv) != 0)
+        throw Error(IGAMG_ENOTSPD, "coarsest operator is not SPD");
+    Ainv0 = upload(inv);
 }
 
 // Per-point FP32 coefficient records of the levels whose colours fit the
@@ -1196,7 +1208,7 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
     setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// n_modes < 0: the built-in right-hand side of the context's Section 5 problem.
+// n_modes < 0: the built-in right-hand side of the context's Section 4.3 problem.
 void igamg_ctx::set_rhs_field(const double* modes, int n_modes) {
     Level& f = lv[L];
     std::vector<double> md;
@@ -1280,6 +1292,7 @@ void igamg_ctx::precond_apply(int precond, int q, const double* v, double* z) {
 // ||b - A x|| <= tol ||b|| at a restart (the Arnoldi estimate ends a cycle early).
 void igamg_ctx::fgmres(double tol, int max_iters, int m, int precond, int q, double* x, igamg_stats& st) {
     const long long N = lv[L].N;
+    have_state = false;  // the preconditioner's restart cycles reuse the checkpoint buffer
     while ((int)kry_V.size() < m + 1) kry_V.push_back(alloc<double>(N));
     while ((int)kry_Z.size() < m) kry_Z.push_back(alloc<double>(N));
     const unsigned nbk = (unsigned)std::min<long long>(grid_for(N), 512);
@@ -2015,7 +2028,7 @@ struct igamg_batch {
             c->extrap_coeffs_async(it, q, IGAMG_RRE);
             long long N = c->lv[c->L].N;
             BLAUNCH(k_extrap_combine, dim3(grid_for(N)), dim3(kBlock), 0, stream, it, q, N,
-                               (const ExtrapCoeffs*)c->coeffs, c->S[0]);
+                               (const ExtrapCoeffs*)c->coeffs, c->S[0], (double*)nullptr);
             c->resnorm_async(c->S[0]);
         }
         BLAUNCH(k_b_gather, dim3(((int)inst.size() + 127) / 128), dim3(128), 0, stream, scal_ptrs,
@@ -2235,7 +2248,7 @@ igamg_status igamg_extrapolate(igamg_ctx* ctx, int method, int q, double* x_dev,
         IterPtrs it = ctx->iter_ptrs(q);
         ctx->extrap_coeffs_async(it, q, method);
         hipLaunchKernelGGL(k_extrap_combine, dim3(grid_for(N)), dim3(kBlock), 0, ctx->stream, it, q, N,
-                           (const ExtrapCoeffs*)ctx->coeffs, x_dev);
+                           (const ExtrapCoeffs*)ctx->coeffs, x_dev, (double*)nullptr);
         ctx->check_launch();
         ExtrapCoeffs c = ctx->read_coeffs();
         if (gamma)
@@ -2258,45 +2271,101 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
     igamg_stats st{};
     auto t0 = std::chrono::steady_clock::now();
     bool converged = false;
+    igamg_state rs{};
+    bool resumed = false;
     igamg_status s = guarded([&] {
         need(ctx && x_dev, "null argument");
+        resumed = ctx->resume;
+        rs = ctx->resume_state;
+        ctx->resume = false;  // a loaded state applies to this call only
         need(tol > 0 && max_restarts > 0, "bad tolerance or max_restarts");
         need(method == IGAMG_EXTRAP_NONE || method == IGAMG_RRE || method == IGAMG_MPE, "bad method");
+        if (method != IGAMG_EXTRAP_NONE) need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
+        if (resumed)
+            need(rs.method == method && (method == IGAMG_EXTRAP_NONE || rs.q == q),
+                 "the loaded state belongs to another method or q");
         st.setup_ms = ctx->setup_ms;
         long long N = ctx->lv[ctx->L].N;
+        // counters and adaptive settings carried over from a checkpoint
+        double prev = 1.0;             // relative residual of the accepted iterate (x_0 = 0: 1)
+        double d0_first = 0.0, ratio = -1.0;
+        bool learned_off = false;
+        if (resumed) {
+            st.restarts = rs.restarts;
+            st.vcycles = rs.vcycles;
+            st.breakdowns = rs.breakdowns;
+            st.learned_fallbacks = rs.learned_fallbacks;
+            st.residual_checks = rs.residual_checks;
+            st.rel_residual = rs.rel_residual;
+            prev = rs.rel_residual;
+            d0_first = rs.gen_scale;
+            ratio = rs.monitor_ratio;
+            learned_off = rs.learned_off != 0;
+        }
+        ctx->have_state = false;
+        ctx->ensure_iterates(method == IGAMG_EXTRAP_NONE ? 0 : q);
+        ctx->copy(x_dev, ctx->S[0], N);
+        ctx->copy(x_dev, ctx->ckpt, N);
+        const bool learned_at_start = ctx->learned_on;
+        if (learned_off && ctx->learned_on) {
+            ctx->learned_on = false;
+            ctx->graph_method = -1;
+        }
+        // on every exit: x_dev (and the checkpoint) hold the accepted iterate,
+        // the learned step is back as it was, the state is recorded
+        auto finish = [&](bool finite) {
+            if (finite) ctx->copy(ctx->S[0], ctx->ckpt, N);
+            else ctx->copy(ctx->ckpt, ctx->S[0], N);
+            ctx->copy(ctx->ckpt, x_dev, N);
+            ctx->sync();
+            igamg_state& o = ctx->state;
+            o.method = method;
+            o.q = method == IGAMG_EXTRAP_NONE ? 0 : q;
+            o.restarts = st.restarts;
+            o.vcycles = st.vcycles;
+            o.breakdowns = st.breakdowns;
+            o.learned_fallbacks = st.learned_fallbacks;
+            o.residual_checks = st.residual_checks;
+            o.learned_off = (learned_at_start && !ctx->learned_on) ? 1 : 0;
+            o.rel_residual = st.rel_residual;
+            o.gen_scale = d0_first;
+            o.monitor_ratio = ratio;
+            ctx->have_state = true;
+            if (learned_at_start && !ctx->learned_on) {
+                ctx->learned_on = true;  // the fallback lasts for this solve only
+                ctx->graph_method = -1;
+            }
+        };
+        // a non-finite cycle: the iterate it started from is the accepted one
+        auto fail_nonfinite = [&](const char* what) {
+            ctx->copy(ctx->ckpt, ctx->S[0], N);
+            ctx->resnorm_async(ctx->S[0]);
+            st.rel_residual = ctx->read_scal();
+            finish(false);
+            throw Error(IGAMG_ENONFINITE, what);
+        };
         if (method == IGAMG_EXTRAP_NONE) {
-            ctx->ensure_iterates(0);
-            ctx->copy(x_dev, ctx->S[0], N);
-            for (int k = 0; k < max_restarts; ++k) {
+            while (st.restarts < max_restarts) {
                 ctx->run_restart_cycle(IGAMG_EXTRAP_NONE, 0);
                 double rel = ctx->read_scal();
+                if (!std::isfinite(rel)) fail_nonfinite("non-finite residual");
                 st.vcycles++;
                 st.restarts++;
                 st.residual_checks++;
                 st.rel_residual = rel;
-                if (!std::isfinite(rel)) {
-                    ctx->copy(ctx->S[0], x_dev, N);
-                    ctx->sync();
-                    throw Error(IGAMG_ENONFINITE, "non-finite residual");
-                }
+                prev = rel;
                 if (rel <= tol) {
                     converged = true;
                     break;
                 }
             }
-            ctx->copy(ctx->S[0], x_dev, N);
-            ctx->sync();
+            finish(true);
         } else {
-            need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
-            ctx->ensure_iterates(q);
-            ctx->copy(x_dev, ctx->S[0], N);
-            double prev = 1.0;
-            bool learned_at_start = ctx->learned_on;
             // generalised-residual monitor: ||b - A t|| is evaluated when
             // ratio * g <= 4 tol, ratio = rel/g at the last evaluation
             const bool monitor = ctx->opt.monitor != 0;
-            double d0_first = 0.0, ratio = -1.0;
-            for (int k = 0; k < max_restarts; ++k) {
+            while (st.restarts < max_restarts) {
+                const bool first = st.restarts == 0;
                 ExtrapCoeffs c;
                 double rel;
                 if (!monitor) {
@@ -2306,9 +2375,10 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
                 } else {
                     ctx->run_restart_cycle(method, q, false);
                     c = ctx->read_coeffs();
-                    if (k == 0) d0_first = c.d0 > 0.0 ? c.d0 : 1.0;
+                    if (first) d0_first = c.d0 > 0.0 ? c.d0 : 1.0;
                     const double g = c.gres / d0_first;
-                    if (ratio < 0.0 || !std::isfinite(g) || ratio * g <= 4.0 * tol || k + 1 == max_restarts) {
+                    if (ratio < 0.0 || !std::isfinite(g) || ratio * g <= 4.0 * tol ||
+                        st.restarts + 1 == max_restarts) {
                         ctx->resnorm_async(ctx->S[0]);
                         rel = ctx->read_scal();
                         st.residual_checks++;
@@ -2317,11 +2387,12 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
                         rel = ratio * g;  // estimate (above 4 tol): not converged
                     }
                 }
+                if (c.info == -2 || !std::isfinite(rel)) fail_nonfinite("non-finite iterate");
                 if (std::isfinite(c.gres) && d0_first == 0.0 && c.d0 > 0.0) d0_first = c.d0;
                 st.gen_residual = d0_first > 0.0 ? c.gres / d0_first : c.gres;
                 // learned-smoother fallback: a cycle contracting worse than plain
                 // V-cycles would (measured at training) switches back to Gauss-Seidel
-                if (ctx->learned_on && ctx->rho_plain_ref > 0.0 && std::isfinite(rel) && k > 0 &&
+                if (ctx->learned_on && ctx->rho_plain_ref > 0.0 && !first &&
                     rel / prev > std::pow(ctx->rho_plain_ref, q + 1) && rel > tol) {
                     ctx->learned_on = false;
                     ctx->graph_method = -1;
@@ -2332,26 +2403,45 @@ igamg_status igamg_solve(igamg_ctx* ctx, double tol, int max_restarts, int metho
                 st.restarts++;
                 if (c.info == -1) st.breakdowns++;
                 st.rel_residual = rel;
-                if (c.info == -2 || !std::isfinite(rel)) {
-                    throw Error(IGAMG_ENONFINITE, "non-finite iterate");
-                }
                 if (rel <= tol) {
                     converged = true;
                     break;
                 }
             }
-            ctx->copy(ctx->S[0], x_dev, N);
-            ctx->sync();
-            if (learned_at_start && !ctx->learned_on) {
-                ctx->learned_on = true;  // the fallback lasts for this solve only
-                ctx->graph_method = -1;
-            }
+            finish(true);
         }
         if (!converged) throw Error(IGAMG_ENOCONV, "tolerance not reached within max_restarts");
     });
     st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
     return s;
+}
+
+igamg_status igamg_get_state(igamg_ctx* ctx, double* x_dev, igamg_state* state) {
+    return guarded([&] {
+        need(ctx && state, "null argument");
+        need(ctx->have_state, "no restarted solve to checkpoint");
+        if (x_dev) {
+            ctx->copy(ctx->ckpt, x_dev, ctx->lv[ctx->L].N);
+            ctx->sync();
+        }
+        *state = ctx->state;
+    });
+}
+
+igamg_status igamg_set_state(igamg_ctx* ctx, const igamg_state* state) {
+    return guarded([&] {
+        need(ctx && state, "null argument");
+        const igamg_state& r = *state;
+        need(r.method == IGAMG_EXTRAP_NONE || r.method == IGAMG_RRE || r.method == IGAMG_MPE, "bad method");
+        need(r.method == IGAMG_EXTRAP_NONE || (r.q >= 1 && r.q <= kMaxQ), "bad q");
+        need(r.restarts >= 0 && r.vcycles >= 0 && r.breakdowns >= 0 && r.learned_fallbacks >= 0 &&
+                 r.residual_checks >= 0, "negative counter");
+        need(std::isfinite(r.rel_residual) && r.rel_residual >= 0.0, "bad rel_residual");
+        need(std::isfinite(r.gen_scale) && std::isfinite(r.monitor_ratio), "bad monitor state");
+        ctx->resume_state = r;
+        ctx->resume = true;
+    });
 }
 
 igamg_status igamg_solve_fgmres(igamg_ctx* ctx, double tol, int max_iters, int m, int precond, int q,
@@ -2857,8 +2947,10 @@ void setup_problem1d(igamg_set1d& S, const igamg_problem1d& pr, Desc1D& D) {
     for (int i = 0; i < n0; ++i)
         for (int d = -p; d <= p; ++d)
             if (i + d >= 0 && i + d < n0) A[(size_t)i * n0 + i + d] = K[0].v[(size_t)i * W + d + p];
-    if (!cholesky_inplace(A, n0)) throw Error(IGAMG_ENOTSPD, "coarsest 1D operator is not SPD");
-    D.Ainv0 = S.upload(inverse_from_cholesky(A, n0));
+    std::vector<double> inv;
+    if (coarse_inverse(std::move(A), n0, true, inv) != 0)
+        throw Error(IGAMG_ENOTSPD, "coarsest 1D operator is not SPD");
+    D.Ainv0 = S.upload(inv);
     ElementTables E = element_tables(ne, p, p + 1);
     D.V = S.upload(E.V);
     D.wq = S.upload(E.wts);

@@ -1096,17 +1096,23 @@ __global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int me
 
 // t = s_0 + sum_{j<q} alpha_j (s_{j+1} - s_j); on breakdown t = s_{q+1}.
 // `out` may alias s_0.
+// t = s_0 + sum_{j<q} alpha_j (s_{j+1} - s_j) into out.  keep (optional)
+// receives s_0, the iterate accepted before this cycle.  info -1 (no
+// extrapolation): out = s_{q+1}; info -2 (non-finite coefficients): out is not
+// written, so an in-place call leaves s_0 there.
 __global__ void __launch_bounds__(kBlock) k_extrap_combine(IterPtrs S, int q, long long N,
                                                            const ExtrapCoeffs* __restrict__ cf,
-                                                           double* out) {
+                                                           double* out, double* keep) {
     long long I = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (I >= N) return;
     int info = cf->info;
+    double prev = S.s[0][I];
+    if (keep) keep[I] = prev;
+    if (info == -2) return;
     if (info < 0) {
         out[I] = S.s[q + 1][I];
         return;
     }
-    double prev = S.s[0][I];
     double t = prev;
     for (int j = 0; j < q; ++j) {
         double nxt = S.s[j + 1][I];
@@ -1839,9 +1845,9 @@ __global__ void k_to_records(const float* __restrict__ coef, int ncp, int ncol, 
 // rho_a * {(1,0), (1,1), (0,1)}_b, rho = (r_in, (r_in + r_out)/2, r_out);
 // 2: the same net with weights (1, 1/sqrt 2, 1) in eta (rational quadratic,
 // exact circular arcs).  pde 0: -Laplace; 1, 2: -div(A grad u) + B.grad u + c u
-// with the two coefficient sets of Section 5 (unit square: B of its first
+// with the two coefficient sets of Section 4.3 (unit square: B of its first
 // problem, c = 1; quarter annulus: B = (-5y, 5x), c = xy; the same A); 3: the
-// advection-diffusion problem of Section 5, A = 0.1 I, B = (1, 1), c = 0.
+// advection-diffusion problem of Section 4.3, A = 0.1 I, B = (1, 1), c = 0.
 struct GeomParams {
     int kind;
     int pde;
@@ -1863,7 +1869,7 @@ struct GeomQP {
     double* Cw;
 };
 
-// Coefficients of the Section 5 problems at a physical point (pde 1, 2 or 3).
+// Coefficients of the Section 4.3 problems at a physical point (pde 1, 2 or 3).
 __device__ inline void pde_coefficients(int pde, double x, double y, double& a11, double& a12, double& a22,
                                         double& b1, double& b2, double& c) {
     if (pde == 3) {  // advection-diffusion: -0.1 Laplace + (1, 1) . grad
@@ -2034,7 +2040,7 @@ __global__ void k_assemble_stencil(int ne, int nq, const double* __restrict__ V,
     out[t] = acc;
 }
 
-// Built-in right-hand sides of the Section 5 problems at the quadrature points,
+// Built-in right-hand sides of the Section 4.3 problems at the quadrature points,
 // premultiplied by w |det J|: pde 1 and 3: f = 1; pde 2: f of the manufactured solution
 // u = (x^2 + y^2 - 0.2^2)(x^2 + y^2 - 1) sin x sin y, i.e.
 // f = -div(A grad u) + B.grad u + c u written out with u = g s,

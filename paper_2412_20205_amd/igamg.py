@@ -53,6 +53,17 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class State(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("q", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("vcycles", ctypes.c_int), ("breakdowns", ctypes.c_int),
+                ("learned_fallbacks", ctypes.c_int), ("residual_checks", ctypes.c_int),
+                ("learned_off", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("gen_scale", ctypes.c_double), ("monitor_ratio", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class TrainOptions(ctypes.Structure):
     _fields_ = [("n_rhs", ctypes.c_int), ("modes", ctypes.c_void_p), ("n_modes", ctypes.c_int),
                 ("vcycles_per_rhs", ctypes.c_int), ("epochs", ctypes.c_int), ("batch", ctypes.c_int),
@@ -119,6 +130,8 @@ _SIGNATURES = {
     "igamg_solve_fgmres": (_i, [_P, _d, _i, _i, _i, _i, _P, ctypes.POINTER(Stats)]),
     "igamg_solve": (_i, [_P, _d, _i, _i, _i, _P, ctypes.POINTER(Stats)]),
     "igamg_residual": (_i, [_P, _P, ctypes.POINTER(_d)]),
+    "igamg_get_state": (_i, [_P, _P, ctypes.POINTER(State)]),
+    "igamg_set_state": (_i, [_P, ctypes.POINTER(State)]),
     "igamg_get_operator_rows": (_i, [_P, _i, _P, _i, _P]),
     "igamg_apply": (_i, [_P, _i, _P, _P]),
     "igamg_smooth": (_i, [_P, _i, _P, _P, _i]),
@@ -153,6 +166,7 @@ _SIGNATURES = {
     "igamg_host_basis": (_i, [_i, _i, _d, _P, _P, ctypes.POINTER(_i)]),
     "igamg_host_prolongation_1d": (_i, [_i, _i, _P]),
     "igamg_host_bands": (_i, [_i, _i, _i, _i, _P, _P]),
+    "igamg_host_coarse_inverse": (_i, [_i, _P, _i, _P]),
 }
 
 
@@ -177,27 +191,59 @@ def _check(status, func):
         raise IgamgError(status, func, lib().igamg_last_error().decode())
 
 
-def _ptr(t):
-    """Device pointer of a contiguous float64 CUDA tensor (or None).
+def _check_len(t, n, what):
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d entries, the call reads/writes %d" % (what, t.numel(), n))
 
-    Work already queued by torch on its current stream is completed first, so
-    the library's stream sees the tensor's final contents."""
+
+def _ptr(t, n=None, what="vector"):
+    """Device pointer of a contiguous float64 CUDA tensor of n entries (or None).
+
+    The length is checked first (the library reads and writes exactly n
+    values).  Work already queued by torch on its current stream is completed
+    first, so the library's stream sees the tensor's final contents."""
     if t is None:
         return None
+    _check_len(t, n, what)
     import torch
-    torch.cuda.current_stream().synchronize()
-    if not t.is_cuda or t.dtype.__repr__() != "torch.float64" or not t.is_contiguous():
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
         raise ValueError("expected a contiguous float64 device tensor")
+    torch.cuda.current_stream().synchronize()
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _ptr32(t):
-    """Device pointer of a contiguous float32 CUDA tensor."""
+def _ptr32(t, n=None, what="vector"):
+    """Device pointer of a contiguous float32 CUDA tensor of n entries."""
+    _check_len(t, n, what)
     import torch
-    torch.cuda.current_stream().synchronize()
     if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
         raise ValueError("expected a contiguous float32 device tensor")
+    torch.cuda.current_stream().synchronize()
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptrs(*specs):
+    """Pointers of several (tensor, length, name) vectors: every length is
+    checked before any tensor is inspected further."""
+    for t, n, what in specs:
+        if t is not None:
+            _check_len(t, n, what)
+    return [_ptr(t, n, what) for t, n, what in specs]
+
+
+def _ptrs32(*specs):
+    for t, n, what in specs:
+        _check_len(t, n, what)
+    return [_ptr32(t, n, what) for t, n, what in specs]
+
+
+def _ptr_list(xs, lengths, what):
+    """ctypes array of the device pointers of xs (one per problem)."""
+    if len(xs) != len(lengths):
+        raise ValueError("%d %s given for %d problems" % (len(xs), what, len(lengths)))
+    for x, n in zip(xs, lengths):
+        _check_len(x, n, what)
+    return (ctypes.c_void_p * len(xs))(*[_ptr(x, n, what).value for x, n in zip(xs, lengths)])
 
 
 def _np_ptr(a):
@@ -275,12 +321,14 @@ class Solver:
                 raise ValueError("wrong length")
             _check(lib().igamg_set_rhs(self._h, _np_ptr(b), 0), "igamg_set_rhs")
         else:
-            if b.numel() != self.ndof:
-                raise ValueError("wrong length")
-            _check(lib().igamg_set_rhs(self._h, _ptr(b), 1), "igamg_set_rhs")
+            _check(lib().igamg_set_rhs(self._h, _ptr(b, self.ndof, "b"), 1), "igamg_set_rhs")
 
     def set_rhs_field(self, modes):
+        """modes: one row (a, k, l, phi) per sine mode in 2D, (a, k, l, m, phi) in 3D."""
         modes = np.ascontiguousarray(modes, dtype=np.float64)
+        width = 5 if self.geometry == UNIT_CUBE else 4
+        if modes.ndim != 2 or modes.shape[1] != width or modes.shape[0] < 1:
+            raise ValueError("mode table must have shape (n_modes, %d)" % width)
         _check(lib().igamg_set_rhs_field(self._h, _np_ptr(modes), modes.shape[0]),
                "igamg_set_rhs_field")
 
@@ -288,19 +336,21 @@ class Solver:
         _check(lib().igamg_set_rhs_builtin(self._h), "igamg_set_rhs_builtin")
 
     def get_rhs(self, out):
-        _check(lib().igamg_get_rhs(self._h, _ptr(out)), "igamg_get_rhs")
+        _check(lib().igamg_get_rhs(self._h, _ptr(out, self.ndof, "out")), "igamg_get_rhs")
         return out
 
     def set_precision(self, precision):
         _check(lib().igamg_set_precision(self._h, precision), "igamg_set_precision")
 
     def vcycle(self, x):
-        _check(lib().igamg_vcycle(self._h, _ptr(x)), "igamg_vcycle")
+        _check(lib().igamg_vcycle(self._h, _ptr(x, self.ndof, "x")), "igamg_vcycle")
         return x
 
     def extrapolate(self, method, q, x, iterates=None):
         gamma = np.zeros(q + 1)
-        st = lib().igamg_extrapolate(self._h, method, q, _ptr(x), _ptr(iterates), _np_ptr(gamma))
+        n = self.ndof
+        px, pit = _ptrs((x, n, "x"), (iterates, (q + 2) * n, "iterates"))
+        st = lib().igamg_extrapolate(self._h, method, q, px, pit, _np_ptr(gamma))
         _check(st, "igamg_extrapolate")
         return gamma
 
@@ -308,7 +358,8 @@ class Solver:
         """Flexible GMRES(m) preconditioned by the multigrid cycle; x is the
         initial guess and the result.  Returns (stats, status)."""
         st = Stats()
-        status = lib().igamg_solve_fgmres(self._h, tol, max_iters, m, precond, q, _ptr(x), ctypes.byref(st))
+        status = lib().igamg_solve_fgmres(self._h, tol, max_iters, m, precond, q, _ptr(x, self.ndof, "x"),
+                                          ctypes.byref(st))
         if check:
             _check(status, "igamg_solve_fgmres")
         return st, status
@@ -321,15 +372,27 @@ class Solver:
 
     def solve(self, x, tol=1e-10, max_restarts=100, method=RRE, q=5, check=True):
         st = Stats()
-        status = lib().igamg_solve(self._h, tol, max_restarts, method, q, _ptr(x),
+        status = lib().igamg_solve(self._h, tol, max_restarts, method, q, _ptr(x, self.ndof, "x"),
                                    ctypes.byref(st))
         if check:
             _check(status, "igamg_solve")
         return st, status
 
+    def get_state(self, x=None):
+        """Checkpoint of the last solve: its accepted iterate goes to x (if
+        given) and its counts and adaptive settings are returned."""
+        state = State()
+        _check(lib().igamg_get_state(self._h, _ptr(x, self.ndof, "x"), ctypes.byref(state)),
+               "igamg_get_state")
+        return state
+
+    def set_state(self, state):
+        """Loads a checkpoint for the next solve (which starts from its x)."""
+        _check(lib().igamg_set_state(self._h, ctypes.byref(state)), "igamg_set_state")
+
     def residual(self, x):
         r = _d()
-        _check(lib().igamg_residual(self._h, _ptr(x), ctypes.byref(r)), "igamg_residual")
+        _check(lib().igamg_residual(self._h, _ptr(x, self.ndof, "x"), ctypes.byref(r)), "igamg_residual")
         return r.value
 
     def operator_rows(self, level, rows):
@@ -342,23 +405,30 @@ class Solver:
         return out
 
     def apply(self, level, x, y):
-        _check(lib().igamg_apply(self._h, level, _ptr(x), _ptr(y)), "igamg_apply")
+        n = self.level_ndof(level)
+        _check(lib().igamg_apply(self._h, level, *_ptrs((x, n, "x"), (y, n, "y"))), "igamg_apply")
         return y
 
     def smooth(self, level, b, x, nsweeps=1):
-        _check(lib().igamg_smooth(self._h, level, _ptr(b), _ptr(x), nsweeps), "igamg_smooth")
+        n = self.level_ndof(level)
+        _check(lib().igamg_smooth(self._h, level, *_ptrs((b, n, "b"), (x, n, "x")), nsweeps), "igamg_smooth")
         return x
 
     def restrict(self, level, r, rc):
-        _check(lib().igamg_restrict(self._h, level, _ptr(r), _ptr(rc)), "igamg_restrict")
+        _check(lib().igamg_restrict(self._h, level, *_ptrs((r, self.level_ndof(level), "r"),
+                                                           (rc, self.level_ndof(level - 1), "rc"))),
+               "igamg_restrict")
         return rc
 
     def prolong_add(self, level, e, x):
-        _check(lib().igamg_prolong_add(self._h, level, _ptr(e), _ptr(x)), "igamg_prolong_add")
+        _check(lib().igamg_prolong_add(self._h, level, *_ptrs((e, self.level_ndof(level - 1), "e"),
+                                                              (x, self.level_ndof(level), "x"))),
+               "igamg_prolong_add")
         return x
 
     def coarse_solve(self, b, x):
-        _check(lib().igamg_coarse_solve(self._h, _ptr(b), _ptr(x)), "igamg_coarse_solve")
+        n = self.level_ndof(0)
+        _check(lib().igamg_coarse_solve(self._h, *_ptrs((b, n, "b"), (x, n, "x"))), "igamg_coarse_solve")
         return x
 
     def profile_smoother(self, level, precision, nsweeps=4):
@@ -411,14 +481,16 @@ class Solver:
                "igamg_set_smoother_weights")
 
     def smoother_forward(self, level, z, y):
-        _check(lib().igamg_smoother_forward(self._h, level, _ptr32(z), _ptr32(y)),
+        n = self.level_ndof(level)
+        _check(lib().igamg_smoother_forward(self._h, level, *_ptrs32((z, n, "z"), (y, n, "y"))),
                "igamg_smoother_forward")
         return y
 
     def smoother_loss_grad(self, level, z, t):
         g = np.zeros(2592, dtype=np.float32)
         loss = _d()
-        _check(lib().igamg_smoother_loss_grad(self._h, level, _ptr32(z), _ptr32(t),
+        n = self.level_ndof(level)
+        _check(lib().igamg_smoother_loss_grad(self._h, level, *_ptrs32((z, n, "z"), (t, n, "t")),
                                               ctypes.byref(loss), _np_ptr(g)),
                "igamg_smoother_loss_grad")
         return loss.value, g
@@ -426,7 +498,8 @@ class Solver:
     def extrap_coeffs(self, method, q, iterates):
         gamma = np.zeros(q + 1)
         info = _i()
-        _check(lib().igamg_extrap_coeffs(self._h, method, q, _ptr(iterates), _np_ptr(gamma),
+        _check(lib().igamg_extrap_coeffs(self._h, method, q, _ptr(iterates, (q + 2) * self.ndof, "iterates"),
+                                         _np_ptr(gamma),
                                          ctypes.byref(info)), "igamg_extrap_coeffs")
         return gamma, info.value
 
@@ -484,7 +557,7 @@ class Batch:
 
     def solve(self, xs, tol=1e-10, max_restarts=100, q=5, check=True):
         n = len(xs)
-        ptrs = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+        ptrs = _ptr_list(xs, [inst.ndof for inst in self.instances], "initial guesses")
         stats = (Stats * n)()
         st = lib().igamg_solve_batch(self._h, tol, max_restarts, q, ctypes.cast(ptrs, _P),
                                      ctypes.cast(stats, _P))
@@ -538,20 +611,20 @@ class Set1D:
         return int(lib().igamg_ndof_1d(self._h, i))
 
     def set_rhs(self, i, b):
-        _check(lib().igamg_set_rhs_1d(self._h, i, _ptr(b)), "igamg_set_rhs_1d")
+        _check(lib().igamg_set_rhs_1d(self._h, i, _ptr(b, self.ndof(i), "b")), "igamg_set_rhs_1d")
 
     def get_rhs(self, i, out):
-        _check(lib().igamg_get_rhs_1d(self._h, i, _ptr(out)), "igamg_get_rhs_1d")
+        _check(lib().igamg_get_rhs_1d(self._h, i, _ptr(out, self.ndof(i), "out")), "igamg_get_rhs_1d")
         return out
 
     def cycles(self, xs, ncycles=1):
-        ptrs = (ctypes.c_void_p * len(xs))(*[_ptr(x).value for x in xs])
+        ptrs = _ptr_list(xs, [self.ndof(i) for i in range(len(self.problems))], "initial guesses")
         _check(lib().igamg_cycles_1d(self._h, ncycles, ctypes.cast(ptrs, _P)), "igamg_cycles_1d")
         return xs
 
     def solve(self, xs, tol=1e-12, max_iters=1000, check=True):
         n = len(xs)
-        ptrs = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+        ptrs = _ptr_list(xs, [self.ndof(i) for i in range(len(self.problems))], "initial guesses")
         stats = (Stats1D * n)()
         st = lib().igamg_solve_1d(self._h, tol, max_iters, ctypes.cast(ptrs, _P), stats)
         if check:
@@ -589,3 +662,14 @@ def host_bands(ne, ne_coarsest, level, p):
     if lib().igamg_host_bands(ne, ne_coarsest, level, p, _np_ptr(K), _np_ptr(M)) != 0:
         raise ValueError("bad arguments")
     return K, M
+
+
+def host_coarse_inverse(A, symmetric=True):
+    """(status, inverse) of a dense coarsest operator, as the setup forms it."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("square matrix expected")
+    inv = np.zeros((n, n))
+    st = lib().igamg_host_coarse_inverse(n, _np_ptr(A), int(symmetric), _np_ptr(inv))
+    return st, inv

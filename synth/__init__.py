@@ -43,7 +43,7 @@ def manufactured_sine_modes_2d():
 
 def poisson_2d_sine_modes(k=1):
     """Mode table of f = 2 (2 k pi)^2 sin(2 k pi x) sin(2 k pi y), exact
-    u = sin(2 k pi x) sin(2 k pi y): the 2D Poisson model problem of Section 5."""
+    u = sin(2 k pi x) sin(2 k pi y): the 2D Poisson model problem of Section 4.2."""
     c = (2.0 * k * math.pi) ** 2
     h = 0.5 * math.pi
     return np.array([[c, 2.0 * k, -2.0 * k, h], [-c, 2.0 * k, 2.0 * k, h]], dtype=np.float64)

@@ -1,6 +1,6 @@
 """Parity of mu-cycles (Algorithm 2 with mu = 2, the W-cycle) and of the
 paper's own smoother setting (weighted Jacobi, V(1,1), omega = 2/3, RRE(8),
-tolerance 1e-12; Section 5) with the FP64 CPU oracle.
+tolerance 1e-12; Section 4.2) with the FP64 CPU oracle.
 
 Bars as for the V-cycle: FP64 iterates to 1e-12 relative per iterate; solves
 reach their tolerance with the oracle's V-cycle and restart counts; FP32
@@ -124,7 +124,7 @@ def test_mu_argument_errors():
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_table11_setting_counts(p):
-    """The Section 5 setting of Table 11 (64 x 64 elements, 4 levels, weighted
+    """The Section 4.2 setting of Table 11 (64 x 64 elements, 4 levels, weighted
     Jacobi V(1,1) and W(1,1), RRE(q)/MPE(q) with q = 4 for p <= 2 and 8 above,
     relative residual 1e-12): the library's V-cycle and restart counts equal
     the oracle's and the solutions agree."""

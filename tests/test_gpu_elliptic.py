@@ -1,4 +1,4 @@
-"""Parity of the full elliptic operators of Section 5 (nonsymmetric stored
+"""Parity of the full elliptic operators of Section 4.3 (nonsymmetric stored
 stencils) with the FP64 CPU oracle, through the C ABI.
 
 Problems: ELLIPTIC_1 on the unit square (f = 1) and ELLIPTIC_2 on the quarter

@@ -9,7 +9,7 @@ import re
 import numpy as np
 import pytest
 
-from oracle import bspline
+from oracle import assemble, bspline
 from paper_2412_20205_amd import igamg
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -94,3 +94,37 @@ def test_host_degree_limit():
     igamg.host_basis(4, 9, 0.3)
     with pytest.raises(ValueError):
         igamg.host_basis(4, 10, 0.3)
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_coarse_inverse_of_the_coarsest_operator(p):
+    """The setup's coarsest inverse (Cholesky of the SPD operator, Section 2)
+    of the oracle's 4 x 4-element annulus operator equals the dense inverse."""
+    A = assemble.mapped_stiffness_2d(4, p).toarray()
+    st, inv = igamg.host_coarse_inverse(A, symmetric=True)
+    assert st == 0
+    ref = np.linalg.inv(A)
+    assert np.abs(inv - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the nonsymmetric path (LU) agrees on the same matrix
+    st2, inv2 = igamg.host_coarse_inverse(A, symmetric=False)
+    assert st2 == 0
+    assert np.abs(inv2 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_coarse_inverse_refuses_indefinite_and_singular():
+    """A symmetric matrix that is not positive definite gives ENOTSPD (-4),
+    as does a singular one on the LU path; the output is left untouched."""
+    A = assemble.mapped_stiffness_2d(4, 3).toarray()
+    lam = np.linalg.eigvalsh(A)
+    B = A - 0.5 * (lam[0] + lam[1]) * np.eye(len(A))   # one negative eigenvalue
+    st, inv = igamg.host_coarse_inverse(B, symmetric=True)
+    assert st == igamg.ENOTSPD
+    assert not inv.any()
+    C = A.copy()
+    C[:, 3] = C[:, 1]                                    # rank deficient
+    C[3, :] = C[1, :]
+    st, inv = igamg.host_coarse_inverse(C, symmetric=False)
+    assert st == igamg.ENOTSPD
+    assert not inv.any()
+    st, _ = igamg.host_coarse_inverse(-A, symmetric=True)
+    assert st == igamg.ENOTSPD

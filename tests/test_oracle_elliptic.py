@@ -1,7 +1,7 @@
-"""Pins of the oracle's full elliptic operator (Section 5) and its geometry.
+"""Pins of the oracle's full elliptic operator (Section 4.3) and its geometry.
 
 The bilinear form a(u, v) = int A grad u . grad v + (B . grad u) v + c u v with
-the two coefficient sets of Section 5; the quarter annulus with exact
+the two coefficient sets of Section 4.3; the quarter annulus with exact
 (rational) arcs for the manufactured solution of the second problem.
 """
 import math
@@ -119,7 +119,7 @@ def test_manufactured_rhs_matches_finite_differences():
 
 @pytest.mark.parametrize("p", [2, 3])
 def test_manufactured_solution_converges_at_order_p_plus_1(p):
-    """Galerkin solutions of the second Section 5 problem on the exact annulus
+    """Galerkin solutions of the second Section 4.3 problem on the exact annulus
     (radii 0.2, 1): the relative L2 error decays like h^(p+1)."""
     errs = []
     for ne in (8, 16, 32):

@@ -42,7 +42,7 @@ def test_restart_keeps_reducing_the_residual():
 @pytest.mark.parametrize("method", [None, ex.RRE])
 def test_extrapolated_cycle_preconditions_the_nonsymmetric_problem(method):
     """FGMRES with one V-cycle or one RRE(3) restart cycle as preconditioner
-    reaches 1e-10 on the first Section 5 problem in fewer iterations than the
+    reaches 1e-10 on the first Section 4.3 problem in fewer iterations than the
     identity preconditioner reaches in 200."""
     H = mg.build_elliptic_hierarchy("square", 16, 2, el.CSET_SQUARE)
     b = el.load(16, 2, "square", lambda x, y: np.ones_like(x))

@@ -2,7 +2,7 @@
 
 Paper: Section 2 (A SPD, eq. (2); Galerkin operator eq. (4)); Section 4.2
 (2D Poisson, eq. (12)); Section 4.3 (quarter annulus as a B-spline surface);
-Section 5 (Table 11: 2D discretisation errors).
+Section 4.2 (Table 11: 2D discretisation errors).
 """
 import math
 import os
@@ -176,7 +176,7 @@ def _l2_error_2d(n_el, p, modes, exact):
 
 
 def test_table11_l2_errors_reproduced():
-    """Table 11's L2-err column for the Section 5 model problem on 64 x 64
+    """Table 11's L2-err column for the Section 4.2 model problem on 64 x 64
     elements: reproduced to 3 % for p = 3, 4, 5.  For p = 1, 2 the printed
     values are 15-20 % below the exact 2D discrete solution's error (for p = 2..5
     they equal the 1D values of Table 1 at 64 elements, which the 2D error of
@@ -196,7 +196,7 @@ def test_table11_l2_errors_reproduced():
 
 
 def test_poisson_2d_modes_reproduce_f():
-    """The mode table of the Section 5 model problem evaluates to
+    """The mode table of the Section 4.2 model problem evaluates to
     f = 2 (2 k pi)^2 sin(2 k pi x) sin(2 k pi y)."""
     rng = np.random.default_rng(3)
     x, y = rng.uniform(0, 1, 100), rng.uniform(0, 1, 100)
