@@ -302,6 +302,19 @@ igamg_status igamg_coarse_solve(igamg_ctx* ctx, const double* b_dev, double* x_d
 igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q,
                                  const double* iterates_dev, double* gamma, int* info);
 
+/* The same coefficients, outputs and errors as igamg_extrap_coeffs, for
+ * callers that cannot allocate device memory (serving loops, harnesses that
+ * forbid hipMalloc): no allocation at all -- the R factors of the QR tree and
+ * the coefficient record live in a fixed device array of about 10.8 MB that
+ * each GPU the library runs on holds until the process ends (found once per
+ * device, at context setup or at the first call there).  The context
+ * supplies n and the stream; run it with the context's device current.
+ * Limit: n <= 2^23 unknowns (EINVAL beyond).  Calls on one GPU share the
+ * array: calls that overlap on one GPU (other host threads, other streams)
+ * race and must be serialised by the caller. */
+igamg_status igamg_extrap_coeffs_noalloc(igamg_ctx* ctx, int method, int q,
+                                         const double* iterates_dev, double* gamma, int* info);
+
 /* Measurement hook: runs nsweeps multicolour Gauss-Seidel sweeps on level
  * `level` (1..L) in the given precision (igamg_precision: FP64 uses the FP64
  * operator, FP32_IR the FP32 copy) on the context's own work vectors.  The

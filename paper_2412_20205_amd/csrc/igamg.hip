@@ -30,6 +30,34 @@ using namespace igamg;
 
 namespace {
 
+// Tall-skinny QR tree of Delta S (iterates it[0..q+1], N unknowns) and the
+// small RRE/MPE solve of Algorithms 3/4, enqueued on `stream`: leaf R factors
+// go to R0 (ceil(N / kQrRows) blocks of (q+1)^2 doubles), the tree levels
+// ping-pong between R0 and R1 (R1 holds ceil(leaves / (kQrRows / (q+1)))
+// blocks), the coefficients to `out` (device).
+void tsqr_coeffs_async(hipStream_t stream, const IterPtrs& it, int q, long long N, int method,
+                       double* R0, double* R1, ExtrapCoeffs* out) {
+    const int ncols = q + 1;
+    long long count = (N + kQrRows - 1) / kQrRows;
+    const size_t shm = (size_t)kQrRows * ncols * sizeof(double);
+    hipLaunchKernelGGL(k_tsqr_leaf, dim3((unsigned)count), dim3(kBlock), shm, stream, it, ncols, N, R0);
+    IGAMG_HIP(hipGetLastError());
+    double* R[2] = {R0, R1};
+    int cur = 0;
+    const int group = kQrRows / ncols;
+    while (count > 1) {
+        long long nxt = (count + group - 1) / group;
+        size_t shm2 = (size_t)group * ncols * ncols * sizeof(double);
+        hipLaunchKernelGGL(k_tsqr_node, dim3((unsigned)nxt), dim3(kBlock), shm2, stream, R[cur],
+                           (int)count, group, ncols, R[1 - cur]);
+        IGAMG_HIP(hipGetLastError());
+        cur = 1 - cur;
+        count = nxt;
+    }
+    hipLaunchKernelGGL(k_extrap_coeffs, dim3(1), dim3(64), 0, stream, R[cur], ncols, method, out);
+    IGAMG_HIP(hipGetLastError());
+}
+
 thread_local std::string g_last_error;
 
 // Autotuning cache: key -> tail_items (process-wide).
@@ -692,27 +720,7 @@ struct igamg_ctx {
     // Tall-skinny QR tree of Delta S from iterates it[0..q+1] and the small
     // solve; result in coeffs (device).
     void extrap_coeffs_async(const IterPtrs& it, int q, int method) {
-        int ncols = q + 1;
-        long long N = lv[L].N;
-        long long count = (N + kQrRows - 1) / kQrRows;
-        size_t shm = (size_t)kQrRows * ncols * sizeof(double);
-        hipLaunchKernelGGL(k_tsqr_leaf, dim3((unsigned)count), dim3(kBlock), shm, stream, it, ncols, N,
-                           Rbuf[0]);
-        check_launch();
-        int cur = 0;
-        int group = kQrRows / ncols;
-        while (count > 1) {
-            long long nxt = (count + group - 1) / group;
-            size_t shm2 = (size_t)group * ncols * ncols * sizeof(double);
-            hipLaunchKernelGGL(k_tsqr_node, dim3((unsigned)nxt), dim3(kBlock), shm2, stream,
-                               Rbuf[cur], (int)count, group, ncols, Rbuf[1 - cur]);
-            check_launch();
-            cur = 1 - cur;
-            count = nxt;
-        }
-        hipLaunchKernelGGL(k_extrap_coeffs, dim3(1), dim3(64), 0, stream, Rbuf[cur], ncols, method,
-                           coeffs);
-        check_launch();
+        tsqr_coeffs_async(stream, it, q, lv[L].N, method, Rbuf[0], Rbuf[1], coeffs);
     }
 
     IterPtrs iter_ptrs(int q) {
@@ -2067,6 +2075,51 @@ struct igamg_batch {
 #undef BLAUNCH
 
 // ---------------------------------------------------------------------------
+// Scratch of igamg_extrap_coeffs_noalloc: one copy per GPU, held until the
+// process ends.  Layout in doubles: the coefficient record (256 bytes), the
+// leaf R factors of up to kNoAllocMaxN unknowns (one (q+1)^2 block per
+// kQrRows-row panel, q <= kMaxQ), then the first tree level.  Every block a
+// call reads was written earlier in the same call, so nothing is cleared.
+
+namespace {
+
+constexpr long long kNoAllocMaxN = 1LL << 23;
+constexpr long long kNoAllocLeaves = kNoAllocMaxN / kQrRows;
+constexpr long long kNoAllocNodes =
+    (kNoAllocLeaves + kQrRows / kMaxCols - 1) / (kQrRows / kMaxCols);
+constexpr size_t kScratchCoeffs = 32;
+static_assert(sizeof(ExtrapCoeffs) <= kScratchCoeffs * sizeof(double), "coefficient record");
+constexpr size_t kScratchDoubles =
+    kScratchCoeffs + (size_t)(kNoAllocLeaves + kNoAllocNodes) * kMaxCols * kMaxCols;
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch array, looked up once per device
+// with that device current (in host code the array's name only stands in for
+// it).  Called at context setup and, for a device with no context yet, by the
+// first igamg_extrap_coeffs_noalloc call there.
+double* scratch_for_current_device() {
+    int dev = 0;
+    IGAMG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        throw Error(IGAMG_EINVAL, "device index " + std::to_string(dev) + " beyond the scratch table");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        IGAMG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Error(IGAMG_EHIP, "no device address for the scratch array");
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 
 namespace {
@@ -2129,6 +2182,7 @@ igamg_status igamg_setup(const igamg_geometry* geom, int degree, int levels,
         else
             igamg_options_default(&c->opt);
         c->setup(*geom, degree, levels);
+        (void)scratch_for_current_device();
         *out = c.release();
     });
 }
@@ -2569,6 +2623,35 @@ igamg_status igamg_extrap_coeffs(igamg_ctx* ctx, int method, int q, const double
         for (int j = 0; j <= q + 1; ++j) it.s[j] = iterates_dev + (size_t)j * N;
         ctx->extrap_coeffs_async(it, q, method);
         ExtrapCoeffs c = ctx->read_coeffs();
+        for (int j = 0; j <= q; ++j) gamma[j] = c.gamma[j];
+        if (info) *info = c.info;
+    });
+}
+
+igamg_status igamg_extrap_coeffs_noalloc(igamg_ctx* ctx, int method, int q, const double* iterates_dev,
+                                         double* gamma, int* info) {
+    return guarded([&] {
+        need(ctx && iterates_dev && gamma, "null argument");
+        need(method == IGAMG_RRE || method == IGAMG_MPE, "method must be RRE or MPE");
+        need(q >= 1 && q <= kMaxQ, "q must be in 1..8");
+        const long long N = ctx->lv[ctx->L].N;
+        if (N > kNoAllocMaxN)
+            throw Error(IGAMG_EINVAL, "igamg_extrap_coeffs_noalloc: " + std::to_string(N) +
+                                          " unknowns exceed its scratch limit of " +
+                                          std::to_string(kNoAllocMaxN));
+        double* sc = scratch_for_current_device();
+        ExtrapCoeffs* cf = reinterpret_cast<ExtrapCoeffs*>(sc);
+        double* R0 = sc + kScratchCoeffs;
+        double* R1 = R0 + (size_t)kNoAllocLeaves * kMaxCols * kMaxCols;
+        IterPtrs it{};
+        for (int j = 0; j <= q + 1; ++j) it.s[j] = iterates_dev + (size_t)j * N;
+        tsqr_coeffs_async(ctx->stream, it, q, N, method, R0, R1, cf);
+        IGAMG_HIP(hipMemcpyAsync(ctx->host_coeffs, cf, sizeof(ExtrapCoeffs), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+        IGAMG_HIP(hipStreamSynchronize(ctx->stream));
+        const ExtrapCoeffs c = *ctx->host_coeffs;
+        ctx->last_coeffs = c;
+        ctx->have_coeffs = true;
         for (int j = 0; j <= q; ++j) gamma[j] = c.gamma[j];
         if (info) *info = c.info;
     });

@@ -1094,12 +1094,10 @@ __global__ void k_extrap_coeffs(const double* __restrict__ Rg, int ncols, int me
     *out = extrap_coefficients(Rg, ncols, method);
 }
 
-// t = s_0 + sum_{j<q} alpha_j (s_{j+1} - s_j); on breakdown t = s_{q+1}.
-// `out` may alias s_0.
 // t = s_0 + sum_{j<q} alpha_j (s_{j+1} - s_j) into out.  keep (optional)
 // receives s_0, the iterate accepted before this cycle.  info -1 (no
 // extrapolation): out = s_{q+1}; info -2 (non-finite coefficients): out is not
-// written, so an in-place call leaves s_0 there.
+// written, so an in-place call leaves s_0 there.  `out` may alias s_0.
 __global__ void __launch_bounds__(kBlock) k_extrap_combine(IterPtrs S, int q, long long N,
                                                            const ExtrapCoeffs* __restrict__ cf,
                                                            double* out, double* keep) {

@@ -139,6 +139,7 @@ _SIGNATURES = {
     "igamg_prolong_add": (_i, [_P, _i, _P, _P]),
     "igamg_coarse_solve": (_i, [_P, _P, _P]),
     "igamg_extrap_coeffs": (_i, [_P, _i, _i, _P, _P, ctypes.POINTER(_i)]),
+    "igamg_extrap_coeffs_noalloc": (_i, [_P, _i, _i, _P, _P, ctypes.POINTER(_i)]),
     "igamg_profile_smoother": (_i, [_P, _i, _i, _i, ctypes.POINTER(_d), ctypes.POINTER(_d),
                                     ctypes.POINTER(_i)]),
     "igamg_train_options_default": (None, [ctypes.POINTER(TrainOptions)]),
@@ -495,12 +496,14 @@ class Solver:
                "igamg_smoother_loss_grad")
         return loss.value, g
 
-    def extrap_coeffs(self, method, q, iterates):
+    def extrap_coeffs(self, method, q, iterates, noalloc=False):
+        """gamma_0..gamma_q and the breakdown code for q+2 stored iterates;
+        noalloc=True takes igamg_extrap_coeffs_noalloc (fixed device scratch)."""
         gamma = np.zeros(q + 1)
         info = _i()
-        _check(lib().igamg_extrap_coeffs(self._h, method, q, _ptr(iterates, (q + 2) * self.ndof, "iterates"),
-                                         _np_ptr(gamma),
-                                         ctypes.byref(info)), "igamg_extrap_coeffs")
+        name = "igamg_extrap_coeffs_noalloc" if noalloc else "igamg_extrap_coeffs"
+        _check(getattr(lib(), name)(self._h, method, q, _ptr(iterates, (q + 2) * self.ndof, "iterates"),
+                                    _np_ptr(gamma), ctypes.byref(info)), name)
         return gamma, info.value
 
 
