@@ -562,11 +562,23 @@ struct igamg_ctx {
         return learned_on && l > tail_top && l < (int)nets.size() && nets[l].have;
     }
     // Learned first pre-smoothing step on level l: x += sigma N_l(D^{-1} r / sigma).
-    // The residual kernel writes z = D^{-1} r and per-block sums of z^2 directly.
+    // The residual kernel writes z = D^{-1} r and per-block sums of z^2 directly;
+    // when x is known to be zero (x_zero), r = b and the same z and sums come
+    // from b and the stencil centres alone.
     template <typename T>
-    void learned_step(int l, const T* bl, T* xl) {
+    void learned_step(int l, const T* bl, T* xl, bool x_zero = false) {
         Level& v = lv[l];
-        residual<T, float>(l, bl, xl, lz, 3, partial);
+        bool done = false;
+        if (x_zero)
+            with_op<T>(l, [&](auto op) {
+                using Op = decltype(op);
+                if constexpr (Op::kColourOrder) {
+                    hipLaunchKernelGGL((k_scaled_rhs<Op>), dim3((unsigned)residual_blocks(l)), dim3(64), 0,
+                                       stream, op, bl, lz, partial);
+                    done = true;
+                }
+            });
+        if (!done) residual<T, float>(l, bl, xl, lz, 3, partial);
         hipLaunchKernelGGL(k_learned_sigma, dim3(1), dim3(kLSigmaThreads), 0, stream, partial,
                            (int)residual_blocks(l), v.N, scal + 2);
         LImage im{lz, v.n, v.n, v.n, 0, 0};
@@ -619,8 +631,10 @@ struct igamg_ctx {
     // 0..min(top, tail_top) run in one single-workgroup kernel.  `rec`, when
     // given (V-cycles only), is called at the start of every level l >= 1
     // with (l, b_l, x_l).
+    // xt_zero: the caller guarantees xt = 0 on entry (every coarser level
+    // starts from zero anyway).
     template <typename T, class Rec = std::nullptr_t>
-    void vcycle_from(int top, const T* bt, T* xt, Rec rec = nullptr) {
+    void vcycle_from(int top, const T* bt, T* xt, Rec rec = nullptr, bool xt_zero = false) {
         if (top == 0) {
             coarse<T>(bt, xt);
             return;
@@ -640,7 +654,7 @@ struct igamg_ctx {
             T* xl = (l == top) ? xt : lv[l].x<T>();
             if constexpr (!std::is_same_v<Rec, std::nullptr_t>) rec(l, bl, xl);
             if (use_learned(l)) {
-                learned_step<T>(l, bl, xl);
+                learned_step<T>(l, bl, xl, l < top || xt_zero);
                 smooth<T>(l, bl, xl, opt.nu1 - 1);
             } else {
                 smooth<T>(l, bl, xl, opt.nu1);
@@ -668,7 +682,7 @@ struct igamg_ctx {
         Level& f = lv[L];
         residual<double, float>(L, b, x, f.b32, 0, nullptr);  // round32(b - A x)
         fill(f.x32, f.N);
-        vcycle<float>(f.b32, f.x32);
+        vcycle_from<float>(L, f.b32, f.x32, nullptr, true);
         hipLaunchKernelGGL(k_add_f32_to_f64, dim3(grid_for(f.N)), dim3(kBlock), 0, stream, f.x32, x,
                            f.N);
         check_launch();

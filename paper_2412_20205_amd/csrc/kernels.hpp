@@ -601,6 +601,33 @@ __device__ __forceinline__ void residual_body(const Op& A, const typename Op::T*
     }
 }
 
+// The learned step's input when x = 0 (a level entered from a zero start):
+// z = D^{-1} b and per-block sums of z^2, exactly what residual_body's mode 3
+// gives for x = 0 (every product with x is +0, so b - A x = b bit for bit) over
+// the same blocks, points and wave sums, but reading only b and the stencil
+// centre (colour-ordered stored stencils; one wave per block).
+template <class Op>
+__global__ void __launch_bounds__(64) k_scaled_rhs(Op A, const typename Op::T* __restrict__ b,
+                                                   float* __restrict__ out, double* __restrict__ partial) {
+    using T = typename Op::T;
+    static_assert(Op::kColourOrder, "colour-ordered stored stencils only");
+    const int lane = threadIdx.x;
+    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int bpc = A.ncp / 64;
+    const int c = blk / bpc, k = (blk - c * bpc) * 64 + lane;
+    typename Op::Pt pt;
+    const bool ok = (c < Op::NC) && A.point(c, k, pt);
+    double sq = 0.0;
+    if (ok) {
+        const T d = A.coef[((size_t)c * Op::S + (size_t)Op::W * Op::kP + Op::kP) * A.ncp + k];
+        const float z = (float)((double)b[pt.I] / (double)d);
+        out[pt.I] = z;
+        sq = (double)z * z;
+    }
+    const double t = wave_sum(sq);
+    if (lane == 0) partial[blockIdx.x] = t;
+}
+
 // Residual-type products with the sliced layout: r = b - A x (mode 0),
 // y = A x (mode 1), damped Jacobi step (mode 2); optional per-block sums of
 // squares.  Colour-ordered traversal for stored stencils, natural otherwise.
