@@ -537,12 +537,14 @@ def main():
         s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p, tail_items=args.tail_items)
         res = {}
         if args.tail_items < 0:
-            # split between multi-block levels and the single-workgroup kernel,
-            # tuned per precision (the FP32 form trains above its own split)
-            t64 = s.autotune()
+            # launch shapes (sweep launches and learned kernel per level, the
+            # split between multi-block levels and the single-workgroup
+            # kernel), tuned per precision (the FP32 form trains above its own split)
+            s.autotune()
+            tun64 = s.tuning()
             s.set_precision(igamg.FP32_IR)
-            t32 = s.autotune()
-            res["tail_split"] = {"fp64": t64[0], "fp32": t32[0]}
+            s.autotune()
+            res["tuning"] = {"fp64": tun64, "fp32": s.tuning()}
         trained = False
         if p == args.headline_degree and not args.no_learned:
             log("[bench] training the learned smoother p=%d" % p)
@@ -699,6 +701,9 @@ def headline_line(args, hp, headline, cpu):
                    "chosen_dof_updates_per_s": ch["dof_updates_per_s"],
                    "smoother_fp64_gbs": headline["smoother_fp64"]["achieved"],
                    "smoother_fp32_gbs": headline["smoother_fp32"]["achieved"],
+                   "tuning_fp32": {k: headline["tuning"]["fp32"][k] for k in
+                                   ("tail_items", "row_class", "learned_kernel")}
+                   if "tuning" in headline else None,
                    "detail": "per-degree results and extra legs on stderr (one JSON line each)"},
         "roofline": roof,
         "cpu_baseline": cpu_short,

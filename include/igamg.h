@@ -329,13 +329,39 @@ igamg_status igamg_extrap_coeffs_noalloc(igamg_ctx* ctx, int method, int q,
 igamg_status igamg_profile_smoother(igamg_ctx* ctx, int level, int precision, int nsweeps,
                                     double* avg_ms, double* bytes, int* launches);
 
-/* Autotuner: times V-cycles (current precision and smoother) for every
- * distinct split between multi-block levels and the single-workgroup kernel
- * (the tail_items option), keeps the fastest, and caches the choice for this
- * process keyed by (GPU architecture, geometry kind, degree, n_el, precision);
- * a later igamg_setup with tail_items < 0 takes the cached choice (or 32).
- * Outputs (may be NULL): the chosen tail_items and its V-cycle time in ms. */
+/* Autotuner of the launch shapes, by timing on the device in the current
+ * precision: (1) per level, row-class sweep launches (the p+1 colours of a row
+ * class per launch, where the kernel applies: stored stencils, p <= 4) or one
+ * launch per colour; (2) per level, the learned smoother's inference kernel
+ * (the 16 x 16-tile VALU/MFMA kernel, or the all-MFMA kernel with 12 x 12 or
+ * 28 x 28 tiles; timed with zero weights, whose values do not change the
+ * time); (3) the split between multi-block levels and the single-workgroup
+ * kernel (the tail_items option), by whole V-cycles with (1) and (2) in
+ * place.  The choice is cached for this process keyed by (GPU architecture,
+ * geometry kind, operator, degree, n_el, precision); a later igamg_setup with
+ * tail_items < 0 (and igamg_set_precision on such a context) takes the cached
+ * choice, else the defaults.  Outputs (may be NULL): the chosen tail_items and
+ * its V-cycle time in ms.  The launch shapes change times, not iterates:
+ * every choice gives the same results. */
 igamg_status igamg_autotune(igamg_ctx* ctx, int* tail_items, double* vcycle_ms);
+
+/* The launch shapes a context uses (tuned or default). */
+typedef struct {
+    int tail_items;          /* the split threshold in use                      */
+    int tail_top;            /* finest level of the single-workgroup kernel (0: none) */
+    int num_levels;          /* levels of the hierarchy (<= 16)                 */
+    int row_class[16];       /* per level: 1 row-class sweep launches, 0 one per colour */
+    int learned_kernel[16];  /* per level: 0 16x16-tile VALU/MFMA kernel; 12, 28 all-MFMA
+                                kernel with that tile (28: 512 threads); 29 tile 28
+                                with 256 threads                               */
+    double vcycle_ms;        /* V-cycle time of the last autotune (0: none)     */
+} igamg_tuning;
+igamg_status igamg_get_tuning(const igamg_ctx* ctx, igamg_tuning* out);
+/* Sets the launch shapes (for instance a tuning saved by another process):
+ * tail_items >= 0, row_class 0 or 1 (1 takes effect where row-class sweeps
+ * apply), learned_kernel one of 0, 12, 28, 29; num_levels must match;
+ * tail_top and vcycle_ms are ignored.  EINVAL on a bad field. */
+igamg_status igamg_set_tuning(igamg_ctx* ctx, const igamg_tuning* in);
 
 /* ---- Learned smoother (2D only) ------------------------------------------
  * Per level l >= 1 a network N_l (3x3 convolutions 1 -> 16 -> 16 -> 1, ReLU,

@@ -60,9 +60,18 @@ void tsqr_coeffs_async(hipStream_t stream, const IterPtrs& it, int q, long long 
 
 thread_local std::string g_last_error;
 
-// Autotuning cache: key -> tail_items (process-wide).
+// Autotuned launch shapes of one problem (key: architecture, geometry,
+// operator, degree, grid, precision), process-wide: the split between
+// multi-block levels and the single-workgroup kernel, and per level the sweep
+// launch shape and the learned inference kernel.
+struct TuneChoice {
+    int tail_items = 32;
+    std::vector<int> row;      // 1: row-class sweeps where available; 0: one launch per colour
+    std::vector<int> learned;  // learned inference kernel (igamg_ctx::learned_apply)
+    double vcycle_ms = 0.0;
+};
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune_cache;
+std::map<std::string, TuneChoice> g_tune_cache;
 
 enum OpKind { OP_STENCIL2D = 0, OP_KRON2D = 1, OP_KRON3D = 2 };
 
@@ -171,6 +180,8 @@ struct igamg_ctx {
     struct Net {
         bool have = false;
         uint16_t *wc = nullptr, *w2f = nullptr, *w2b = nullptr;
+        float* mf32 = nullptr;       // per-lane MFMA records of the inference kernel
+        uint16_t* mfbf = nullptr;
         float *master = nullptr, *m = nullptr, *v = nullptr;
     };
     std::vector<Net> nets;
@@ -178,6 +189,11 @@ struct igamg_ctx {
     std::vector<float*> diag32;
     float* lz = nullptr;       // z = D^{-1} r of the current level (FP32)
     bool learned_on = false;
+    // per level: learned inference kernel (learned_apply) and sweep launch
+    // shape (row_sweeps); defaults, or the tuned choice
+    std::vector<int> learned_kern;
+    std::vector<int> row_pref;
+    double tuned_ms = 0.0;
     double rho_plain_ref = 0.0;  // measured plain contraction (fallback threshold)
 
     ~igamg_ctx() {
@@ -326,14 +342,15 @@ struct igamg_ctx {
         }
     }
 
-    // Stored-stencil levels narrow enough for the LDS row store sweep the p+1
-    // colours of a row class in one launch.
     // Stored-stencil levels narrow enough for the LDS row store (and with at
     // most kRowThreads points per colour and row) sweep the p+1 colours of a
     // row class in one launch.
     // (the kernel addresses a level's coefficients with 32-bit byte offsets)
     bool row_sweeps(int l) const {
-        return opt.row_sweeps && kind == OP_STENCIL2D && row_fits(p, lv[l].n) &&
+        return row_sweeps_available(l) && (l >= (int)row_pref.size() || row_pref[l] != 0);
+    }
+    bool row_sweeps_available(int l) const {
+        return opt.row_sweeps && kind == OP_STENCIL2D && p <= 4 && row_fits(p, lv[l].n) &&
                coef_bytes(l, sizeof(double)) < (1LL << 32);
     }
     // One multicolour Gauss-Seidel sweep of level l (multi-block launches).
@@ -426,14 +443,37 @@ struct igamg_ctx {
         return arch + "/" + std::to_string(geom) + "/" + std::to_string(opt.pde) + "/" + std::to_string(p) + "/" +
                std::to_string(lv[L].n_el) + "/" + std::to_string(opt.precision);
     }
+    // Launch-shape defaults: row-class sweeps wherever they apply; the learned
+    // step with 28 x 28 tiles (512 threads) on levels of 384 unknowns per
+    // direction and more, 12 x 12 tiles below (the faster of the two measured
+    // on the 1024^2 annulus hierarchy, p = 3).
+    void default_shapes() {
+        row_pref.assign(L + 1, 1);
+        learned_kern.assign(L + 1, 12);
+        for (int l = 0; l <= L; ++l)
+            if (lv[l].n >= 384) learned_kern[l] = 28;
+    }
+    void apply_choice(const TuneChoice& c) {
+        opt.tail_items = c.tail_items;
+        if ((int)c.row.size() == L + 1) row_pref = c.row;
+        if ((int)c.learned.size() == L + 1) learned_kern = c.learned;
+        tuned_ms = c.vcycle_ms;
+        graph_method = -1;
+    }
+    // Takes the cached choice of this problem and precision, if there is one.
+    bool apply_cached_choice() {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(tune_key());
+        if (it == g_tune_cache.end()) return false;
+        apply_choice(it->second);
+        return true;
+    }
     void choose_tail() {
         tail_top = 0;
         if (opt.smoother != IGAMG_SMOOTH_MCGS) return;  // the single-workgroup kernel sweeps colours
         if (opt.tail_items < 0) {
             tail_auto = true;
-            std::lock_guard<std::mutex> g(g_tune_mu);
-            auto it = g_tune_cache.find(tune_key());
-            opt.tail_items = (it != g_tune_cache.end()) ? it->second : 32;
+            if (!apply_cached_choice()) opt.tail_items = 32;
         }
         if (opt.tail_items <= 0) return;
         const int limit = (opt.precision == IGAMG_FP64) ? tail_limit<double>() : tail_limit<float>();
@@ -582,10 +622,36 @@ struct igamg_ctx {
         hipLaunchKernelGGL(k_learned_sigma, dim3(1), dim3(kLSigmaThreads), 0, stream, partial,
                            (int)residual_blocks(l), v.N, scal + 2);
         LImage im{lz, v.n, v.n, v.n, 0, 0};
-        LearnedW W{nets[l].wc, nets[l].w2f, nets[l].w2b};
-        int tiles = (v.n + kLTile - 1) / kLTile;
-        hipLaunchKernelGGL(k_learned_apply<T>, dim3(tiles * tiles), dim3(kLThreads), 0, stream, im, W,
-                           (const double*)(scal + 2), xl, (float*)nullptr);
+        learned_apply<T>(l, im, (const double*)(scal + 2), xl, nullptr);
+    }
+
+    // Inference launch of the network on one level image: x += sigma N(z / sigma)
+    // (yout null) or yout = N(z).  The level's learned_kern selects the kernel: 0 the
+    // 16 x 16 VALU / MFMA tile kernel, 12 / 28 the all-MFMA kernel with that
+    // output tile (28: 512 threads, 29: tile 28 with 256 threads).
+    template <typename T>
+    void learned_apply(int l, const LImage& im, const double* sigma, T* xl, float* yout) {
+        learned_apply_k<T>(learned_kern[l], nets[l], im, sigma, xl, yout);
+    }
+    template <typename T>
+    void learned_apply_k(int kern_id, const Net& net, const LImage& im, const double* sigma, T* xl,
+                         float* yout) {
+        auto go = [&](auto kern, int tl, int nt) {
+            const int tiles = (im.width + tl - 1) / tl;
+            hipLaunchKernelGGL(kern, dim3(tiles * tiles), dim3(nt), 0, stream, im, (const float*)net.mf32,
+                               (const uint16_t*)net.mfbf, sigma, xl, yout);
+        };
+        switch (kern_id) {
+            case 12: go(k_learned_apply_mf<12, 256, T>, 12, 256); break;
+            case 28: go(k_learned_apply_mf<28, 512, T>, 28, 512); break;
+            case 29: go(k_learned_apply_mf<28, 256, T>, 28, 256); break;
+            default: {
+                const int tiles = (im.width + kLTile - 1) / kLTile;
+                LearnedW W{net.wc, net.w2f, net.w2b};
+                hipLaunchKernelGGL(k_learned_apply<T>, dim3(tiles * tiles), dim3(kLThreads), 0, stream, im, W,
+                                   sigma, xl, yout);
+            }
+        }
         check_launch();
     }
 
@@ -892,7 +958,7 @@ struct igamg_ctx {
     void train(const igamg_train_options& o, igamg_train_report& rep);
     double measure_rho(int vcycles, bool learned);
 
-    void autotune(int* best_items, double* best_ms);
+    void autotune(int* best_items, double* best_ms, bool tune_learned = true);
     void precond_apply(int precond, int q, const double* v, double* z);
     void fgmres(double tol, int max_iters, int m, int precond, int q, double* x, igamg_stats& st);
 
@@ -1216,6 +1282,7 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
         fill(v.b64, v.N);
         fill(v.b32, v.N);
     }
+    default_shapes();
     choose_tail();
     b = alloc<double>(lv[L].N);
     fill(b, lv[L].N);
@@ -1413,12 +1480,113 @@ void igamg_ctx::fgmres(double tol, int max_iters, int m, int precond, int q, dou
     if (!converged) throw Error(IGAMG_ENOCONV, "tolerance not reached within max_iters");
 }
 
-void igamg_ctx::autotune(int* best_items, double* best_ms) {
+// Autotuner: picks, by timing on the device, (1) per level the sweep launch
+// shape (row-class launches or one launch per colour) in the current
+// precision, (2) per level the learned inference kernel (the timing does not
+// depend on the weights, so zero weights stand in), (3) the split between
+// multi-block levels and the single-workgroup kernel (whole V-cycles with the
+// choices of (1) and (2)); the result is cached for the process.
+void igamg_ctx::autotune(int* best_items, double* best_ms, bool tune_learned) {
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    IGAMG_HIP(hipEventCreate(&ev.a));
+    IGAMG_HIP(hipEventCreate(&ev.b));
+    // ms of one replay of the launches `body` enqueues, captured as a graph
+    // and replayed once to warm up, then once between two events
+    auto timed = [&](auto&& body) -> double {
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ge = nullptr;
+        IGAMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            hipGraph_t g2 = nullptr;
+            (void)hipStreamEndCapture(stream, &g2);
+            if (g2) (void)hipGraphDestroy(g2);
+            throw;
+        }
+        IGAMG_HIP(hipStreamEndCapture(stream, &gr));
+        float ms = 0.f;
+        hipError_t err = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        if (err == hipSuccess) err = hipGraphLaunch(ge, stream);
+        if (err == hipSuccess) err = hipEventRecord(ev.a, stream);
+        if (err == hipSuccess) err = hipGraphLaunch(ge, stream);
+        if (err == hipSuccess) err = hipEventRecord(ev.b, stream);
+        if (err == hipSuccess) err = hipEventSynchronize(ev.b);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev.a, ev.b);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        (void)hipGraphDestroy(gr);
+        if (err != hipSuccess) throw Error(IGAMG_EHIP, std::string("autotune: ") + hipGetErrorString(err));
+        return ms;
+    };
+    // (1) sweep launch shape per level
+    auto sweep_shapes = [&](auto tag) {
+        using T = decltype(tag);
+        for (int l = 1; l <= L; ++l) {
+            if (!row_sweeps_available(l)) continue;
+            Level& v = lv[l];
+            fill(v.x<T>(), v.N);
+            hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(v.N)), dim3(kBlock), 0, stream, v.b<T>(), (T)1, v.N);
+            check_launch();
+            double t[2];
+            for (int pref = 0; pref < 2; ++pref) {
+                row_pref[l] = pref;
+                t[pref] = timed([&] {
+                    for (int k = 0; k < 2; ++k) mc_sweep<T>(l, v.b<T>(), v.x<T>());
+                });
+            }
+            row_pref[l] = t[1] <= t[0] ? 1 : 0;
+        }
+    };
+    if (opt.precision == IGAMG_FP64)
+        sweep_shapes(double{});
+    else
+        sweep_shapes(float{});
+    // (2) learned inference kernel per level
+    if (dim == 2 && tune_learned) {
+        const long long nmax = lv[L].N;
+        float* zt = alloc<float>(nmax);
+        float* yt = alloc<float>(nmax);
+        fill(zt, nmax);
+        Net tmp;
+        tmp.wc = alloc<uint16_t>(kLWeights);
+        tmp.w2f = alloc<uint16_t>(kLW2);
+        tmp.w2b = alloc<uint16_t>(kLW2);
+        tmp.mf32 = alloc<float>(kLMf32);
+        tmp.mfbf = alloc<uint16_t>(kLMfBf);
+        fill(tmp.wc, kLWeights);
+        fill(tmp.w2f, kLW2);
+        fill(tmp.w2b, kLW2);
+        fill(tmp.mf32, kLMf32);
+        fill(tmp.mfbf, kLMfBf);
+        const int cand[] = {0, 12, 28, 29};
+        for (int l = 1; l <= L; ++l) {
+            const LImage im{zt, lv[l].n, lv[l].n, lv[l].n, 0, 0};
+            double bt = 1e300;
+            int bk = learned_kern[l];
+            for (int k : cand) {
+                const double t = timed([&] {
+                    for (int r = 0; r < 3; ++r) learned_apply_k<float>(k, tmp, im, nullptr, (float*)nullptr, yt);
+                });
+                if (t < bt) {
+                    bt = t;
+                    bk = k;
+                }
+            }
+            learned_kern[l] = bk;
+        }
+        for (void* q : {(void*)zt, (void*)yt, (void*)tmp.wc, (void*)tmp.w2f, (void*)tmp.w2b, (void*)tmp.mf32,
+                        (void*)tmp.mfbf})
+            release(q);
+    }
+    // (3) the multi-block / single-workgroup split
     const int cand[] = {0, 8, 16, 32, 64, 128, 256, 512};
     double* x = alloc<double>(lv[L].N);
-    hipEvent_t e0, e1;
-    IGAMG_HIP(hipEventCreate(&e0));
-    IGAMG_HIP(hipEventCreate(&e1));
     int save_items = opt.tail_items;
     int best = save_items;
     double bms = 1e300;
@@ -1430,26 +1598,30 @@ void igamg_ctx::autotune(int* best_items, double* best_ms) {
         last_top = tail_top;
         fill(x, lv[L].N);
         G(x);  // warm-up
-        IGAMG_HIP(hipEventRecord(e0, stream));
+        IGAMG_HIP(hipEventRecord(ev.a, stream));
         for (int k = 0; k < 3; ++k) G(x);
-        IGAMG_HIP(hipEventRecord(e1, stream));
-        IGAMG_HIP(hipEventSynchronize(e1));
+        IGAMG_HIP(hipEventRecord(ev.b, stream));
+        IGAMG_HIP(hipEventSynchronize(ev.b));
         float ms = 0.f;
-        IGAMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        IGAMG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
         if (ms / 3.0 < bms) {
             bms = ms / 3.0;
             best = items;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     release(x);
     opt.tail_items = best;
     choose_tail();
     graph_method = -1;
+    tuned_ms = bms;
     {
+        TuneChoice c;
+        c.tail_items = best;
+        c.row = row_pref;
+        c.learned = learned_kern;
+        c.vcycle_ms = bms;
         std::lock_guard<std::mutex> g(g_tune_mu);
-        g_tune_cache[tune_key()] = best;
+        g_tune_cache[tune_key()] = c;
     }
     if (best_items) *best_items = best;
     if (best_ms) *best_ms = bms;
@@ -1501,6 +1673,10 @@ void igamg_ctx::ensure_net(int l) {
     t.wc = alloc<uint16_t>(kLWeights);
     t.w2f = alloc<uint16_t>(kLW2);
     t.w2b = alloc<uint16_t>(kLW2);
+    t.mf32 = alloc<float>(kLMf32);
+    t.mfbf = alloc<uint16_t>(kLMfBf);
+    fill(t.mf32, kLMf32);  // record entries of no weight stay zero
+    fill(t.mfbf, kLMfBf);
     t.master = alloc<float>(kLWeights);
     t.m = alloc<float>(kLWeights);
     t.v = alloc<float>(kLWeights);
@@ -1701,7 +1877,7 @@ void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
         fill(g, kLWeights);
         hipLaunchKernelGGL(k_learned_adam, dim3((kLWeights + 255) / 256), dim3(256), 0, stream, net.master,
                            net.m, net.v, (const float*)g, 0.f, 0.9f, 0.999f, 1e-8f, 1.f, 1.f, net.wc, net.w2f,
-                           net.w2b);
+                           net.w2b, net.mf32, net.mfbf);
         net.have = true;
         int tiles = ((ls + kLTile - 1) / kLTile) * ((ls + kLTile - 1) / kLTile);
         int B = std::min(o.batch, np);
@@ -1744,7 +1920,7 @@ void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
                 float bc1 = 1.f - std::pow(0.9f, (float)step), bc2 = 1.f - std::pow(0.999f, (float)step);
                 hipLaunchKernelGGL(k_learned_adam, dim3((kLWeights + 255) / 256), dim3(256), 0, stream,
                                    net.master, net.m, net.v, (const float*)g, (float)o.lr, 0.9f, 0.999f,
-                                   1e-8f, bc1, bc2, net.wc, net.w2f, net.w2b);
+                                   1e-8f, bc1, bc2, net.wc, net.w2f, net.w2b, net.mf32, net.mfbf);
                 check_launch();
                 if (ep == 0 || ep == o.epochs - 1) {
                     IGAMG_HIP(hipMemcpyAsync(host_scal + 4, lsum, 8, hipMemcpyDeviceToHost, stream));
@@ -2271,11 +2447,7 @@ igamg_status igamg_set_precision(igamg_ctx* ctx, int precision) {
         need(precision == IGAMG_FP64 || precision == IGAMG_FP32_IR, "bad precision");
         if (precision != ctx->opt.precision) {
             ctx->opt.precision = precision;
-            if (ctx->tail_auto) {  // the tuned split of this precision, if any
-                std::lock_guard<std::mutex> g(g_tune_mu);
-                auto it = g_tune_cache.find(ctx->tune_key());
-                if (it != g_tune_cache.end()) ctx->opt.tail_items = it->second;
-            }
+            if (ctx->tail_auto) ctx->apply_cached_choice();  // the tuned shapes of this precision, if any
             ctx->choose_tail();      // the LDS store holds more FP32 levels
             ctx->graph_method = -1;  // recapture the restart cycle
         }
@@ -2720,7 +2892,7 @@ igamg_status igamg_setup_batch(int count, const igamg_geometry* geoms, const int
                     std::lock_guard<std::mutex> g(g_tune_mu);
                     cached = g_tune_cache.count(c->tune_key()) > 0;
                 }
-                if (!cached) c->autotune(nullptr, nullptr);
+                if (!cached) c->autotune(nullptr, nullptr, false);  // batches have no learned step
             }
             B->inst.push_back(c.release());
         }
@@ -2812,6 +2984,43 @@ igamg_status igamg_autotune(igamg_ctx* ctx, int* tail_items, double* vcycle_ms) 
     });
 }
 
+igamg_status igamg_get_tuning(const igamg_ctx* ctx, igamg_tuning* out) {
+    return guarded([&] {
+        need(ctx && out, "null argument");
+        need(ctx->L + 1 <= 16, "more levels than the report holds");
+        *out = igamg_tuning{};
+        out->tail_items = ctx->opt.tail_items;
+        out->tail_top = ctx->tail_top;
+        out->num_levels = ctx->L + 1;
+        for (int l = 0; l <= ctx->L; ++l) {
+            out->row_class[l] = ctx->row_sweeps(l) ? 1 : 0;
+            out->learned_kernel[l] = ctx->learned_kern[l];
+        }
+        out->vcycle_ms = ctx->tuned_ms;
+    });
+}
+
+igamg_status igamg_set_tuning(igamg_ctx* ctx, const igamg_tuning* in) {
+    return guarded([&] {
+        need(ctx && in, "null argument");
+        need(in->num_levels == ctx->L + 1, "num_levels does not match the hierarchy");
+        need(in->tail_items >= 0, "tail_items must be >= 0");
+        for (int l = 0; l <= ctx->L; ++l) {
+            need(in->row_class[l] == 0 || in->row_class[l] == 1, "row_class must be 0 or 1");
+            const int k = in->learned_kernel[l];
+            need(k == 0 || k == 12 || k == 28 || k == 29, "learned_kernel must be 0, 12, 28 or 29");
+        }
+        for (int l = 0; l <= ctx->L; ++l) {
+            ctx->row_pref[l] = in->row_class[l];
+            ctx->learned_kern[l] = in->learned_kernel[l];
+        }
+        ctx->opt.tail_items = in->tail_items;
+        ctx->tail_auto = false;
+        ctx->choose_tail();
+        ctx->graph_method = -1;
+    });
+}
+
 void igamg_train_options_default(igamg_train_options* o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
@@ -2871,8 +3080,8 @@ igamg_status igamg_set_smoother_weights(igamg_ctx* ctx, int level, const uint16_
             std::memcpy(&mw[k], &u, 4);
         }
         IGAMG_HIP(hipMemcpyAsync(net.master, mw.data(), kLWeights * 4, hipMemcpyHostToDevice, ctx->stream));
-        hipLaunchKernelGGL(k_learned_layouts, dim3((kLW2 + 255) / 256), dim3(256), 0, ctx->stream,
-                           (const uint16_t*)net.wc, net.w2f, net.w2b);
+        hipLaunchKernelGGL(k_learned_layouts, dim3((kLWeights + 255) / 256), dim3(256), 0, ctx->stream,
+                           (const uint16_t*)net.wc, net.w2f, net.w2b, net.mf32, net.mfbf);
         ctx->check_launch();
         ctx->sync();
         net.have = true;
@@ -2888,11 +3097,8 @@ igamg_status igamg_smoother_forward(igamg_ctx* ctx, int level, const float* z, f
         auto& v = ctx->lv[level];
         auto& net = ctx->nets[level];
         LImage im{z, v.n, v.n, v.n, 0, 0};
-        LearnedW W{net.wc, net.w2f, net.w2b};
-        int tiles = (v.n + kLTile - 1) / kLTile;
-        hipLaunchKernelGGL(k_learned_apply<float>, dim3(tiles * tiles), dim3(kLThreads), 0, ctx->stream, im,
-                           W, (const double*)nullptr, (float*)nullptr, y);
-        ctx->check_launch();
+        (void)net;
+        ctx->learned_apply<float>(level, im, nullptr, (float*)nullptr, y);
         ctx->sync();
     });
 }

@@ -193,6 +193,222 @@ __global__ void __launch_bounds__(kLThreads, 3) k_learned_apply(LImage im, Learn
     }
 }
 
+// ---- inference with every layer on the matrix cores -------------------------
+// One workgroup per TL x TL output tile, all three layers as MFMA products in
+// the transposed form D[channel or tap][pixel] = W x patch^T, 16 pixels per
+// product:
+//   layer 1: h1[ch][px] = sum_tap W1[ch][tap] z[px + tap]; FP32 MFMA 16x16x4
+//            (K = taps, 3 products, taps 9..11 zero), ReLU, zero outside the
+//            domain, rounded to BF16 into LDS ([pixel][channel]);
+//   layer 2: h2[co][px] = sum_{tap,ci} W2[co][ci][tap] h1[px + tap][ci];
+//            BF16 MFMA 16x16x32 (K = 16 tap + ci, 5 products, tap 9 zero),
+//            FP32 accumulation, ReLU and the domain mask in registers;
+//   layer 3: u[tap][px] = sum_ci W3[ci][tap] h2[ci][px] straight from those
+//            registers (FP32 MFMA 16x16x4, 4 products over the channel groups),
+//            then y[px] = sum_tap u[tap][px + tap] from LDS.
+// Layer 1 and 3 arithmetic stays FP32 and layer 2's operands BF16, as in the
+// VALU/MFMA kernel above (results agree up to FP32 summation order).
+// MFMA operand layouts (lane l, g = l / 16): 16x16x4 f32: A[l%16][g],
+// B[g][l%16]; 16x16x32 bf16: A[l%16][8g + e], B[8g + e][l%16], e = 0..7;
+// D[4g + j][l%16], j = 0..3, for both.
+//
+// The weights reach the kernel as per-lane MFMA A-operand records, written
+// whenever the canonical weights change: FP32 mf32[l][8] = (a1[0..2], a3[0..3],
+// 0) and BF16 mfbf[l][5][8] = a2[m][e], zero where a tap is >= 9 or a row is
+// no tap.  Inside a tile every load is unconditional (clamped addresses), so
+// no memory wait sits on a branch, and each wave interleaves two 16-pixel
+// groups so that two independent MFMA chains are in flight.
+typedef __bf16 lbf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kLMf32 = 64 * 8;      // floats of the FP32 records
+constexpr int kLMfBf = 64 * 5 * 8;  // BF16 values of the layer-2 records
+
+// Record positions of canonical weight k (-1: none), for the writers below.
+__device__ __forceinline__ void l_mf_slot(int k, int& f32_slot, int& bf_slot) {
+    f32_slot = -1;
+    bf_slot = -1;
+    if (k < kLW1) {
+        const int ch = k / 9, tap = k % 9;
+        f32_slot = (ch + 16 * (tap % 4)) * 8 + tap / 4;
+    } else if (k < kLW1 + kLW2) {
+        const int e2 = k - kLW1, co = e2 / (kLC * 9), ci = (e2 / 9) % kLC, tap = e2 % 9;
+        const int g = 2 * (tap % 2) + ci / 8;
+        bf_slot = ((co + 16 * g) * 5 + tap / 2) * 8 + ci % 8;
+    } else if (k < kLWeights) {
+        const int e3 = k - kLW1 - kLW2, ci = e3 / 9, tap = e3 % 9;
+        f32_slot = (tap + 16 * (ci / 4)) * 8 + 3 + ci % 4;
+    }
+}
+
+__device__ __forceinline__ bool l_row_in(const LImage& im, int pj) {
+    const int gj = pj + im.off_j;
+    return pj >= 0 && pj < im.height && gj >= 0 && gj < im.n;
+}
+__device__ __forceinline__ bool l_col_in(const LImage& im, int pi) {
+    const int gi = pi + im.off_i;
+    return pi >= 0 && pi < im.width && gi >= 0 && gi < im.n;
+}
+// Two FP32 values to BF16 (round to nearest even), packed low | high << 16.
+__device__ __forceinline__ uint32_t l_pack_bf16(float lo, float hi) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)lo) |
+           ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)hi) << 16);
+}
+
+// Tile of TL x TL outputs: layer 1 on an HW x HW grid with HW = TL + 4 a
+// multiple of 16, so that a 16-pixel group is one run of a grid row; layer 2
+// and 3 on UW = TL + 2 rows of the same HW-wide runs (columns UW.. unused);
+// z on ZW = TL + 6.  u is stored [tap][row][HW].
+template <int TL>
+struct LMShared {
+    static constexpr int ZW = TL + 6, HW = TL + 4, UW = TL + 2, RG = HW / 16;
+    static_assert(HW % 16 == 0, "layer-1 rows must be whole 16-pixel runs");
+    float z[ZW * ZW];
+    alignas(16) uint16_t h1[HW * HW * kLC];
+    float u[9 * UW * HW];
+};
+
+template <int TL, int NT, typename T>
+__global__ void __launch_bounds__(NT) k_learned_apply_mf(LImage im, const float* __restrict__ mf32,
+                                                         const uint16_t* __restrict__ mfbf,
+                                                         const double* __restrict__ sigma_dev,
+                                                         T* __restrict__ x, float* __restrict__ yout) {
+    using SH = LMShared<TL>;
+    constexpr int ZW = SH::ZW, HW = SH::HW, UW = SH::UW, RG = SH::RG, NWV = NT / 64;
+    constexpr int NG1 = HW * RG, NG2 = UW * RG;
+    constexpr int KZ = (ZW * ZW + NT - 1) / NT, KO = (TL * TL + NT - 1) / NT;
+    __shared__ SH S;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c16 = lane & 15;
+    const int tiles = (im.width + TL - 1) / TL;
+    const int tj0 = (blockIdx.x / tiles) * TL, ti0 = (blockIdx.x % tiles) * TL;
+    // every global load of the tile (sigma, weights, the z patch and the x
+    // values to update) is issued before the first wait
+    const double sg = sigma_dev ? *sigma_dev : 1.0;
+    T xo[KO];
+    if (!yout) {
+#pragma unroll
+        for (int k = 0; k < KO; ++k) {
+            const int o = min(tid + k * NT, TL * TL - 1);
+            const int pj = min(tj0 + o / TL, im.height - 1), pi = min(ti0 + o % TL, im.width - 1);
+            xo[k] = x[(size_t)pj * im.width + pi];
+        }
+    }
+    const floatx4 r0 = *reinterpret_cast<const floatx4*>(mf32 + lane * 8);
+    const floatx4 r1 = *reinterpret_cast<const floatx4*>(mf32 + lane * 8 + 4);
+    lbf16x8 a2[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) a2[m] = *reinterpret_cast<const lbf16x8*>(mfbf + (lane * 5 + m) * 8);
+    float zv[KZ];
+    bool zin[KZ];
+#pragma unroll
+    for (int k = 0; k < KZ; ++k) {
+        const int t = min(tid + k * NT, ZW * ZW - 1);
+        const int pj = tj0 - 3 + t / ZW, pi = ti0 - 3 + t % ZW;
+        zin[k] = l_inside(im, pj, pi);
+        zv[k] = im.z[(size_t)clampi(pj, 0, im.height - 1) * im.width + clampi(pi, 0, im.width - 1)];
+    }
+    const float a1[3] = {r0[0], r0[1], r0[2]};
+    const float a3[4] = {r0[3], r1[0], r1[1], r1[2]};
+    // per-lane tap offsets (taps 9.. meet zero weights: clamped to tap 8)
+    int zo[3], ho[5];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int tap = min(4 * m + g, 8);
+        zo[m] = (tap / 3) * ZW + tap % 3;
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        const int tap = min(2 * m + (g >> 1), 8);
+        ho[m] = ((tap / 3) * HW + tap % 3) * kLC + 8 * (g & 1);
+    }
+    // per-lane column masks of the RG runs of a row (layer 1; layers 2-3)
+    bool c1[RG], c2[RG];
+    int hb2[RG];
+#pragma unroll
+    for (int h = 0; h < RG; ++h) {
+        const int px = 16 * h + c16;
+        c1[h] = l_col_in(im, ti0 - 2 + px);
+        c2[h] = px < UW && l_col_in(im, ti0 - 1 + px);
+        hb2[h] = (px < UW ? px : 0) * kLC;
+    }
+    if (!(sg > 0.0)) return;  // uniform: the whole workgroup leaves
+    const float zscale = (float)(1.0 / sg);
+#pragma unroll
+    for (int k = 0; k < KZ; ++k) {
+        const int t = tid + k * NT;
+        if (t < ZW * ZW) S.z[t] = zin[k] ? zv[k] * zscale : 0.f;
+    }
+    __syncthreads();
+    // layer 1: group gr = run h of row r; two groups per wave in flight
+    auto layer1 = [&](int gr) {
+        const int r = gr / RG, h = gr % RG;
+        const float* zb = S.z + r * ZW + 16 * h + c16;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[m], zb[zo[m]], acc, 0, 0, 0);
+        return acc;
+    };
+    auto store1 = [&](int gr, const floatx4& acc) {
+        const int r = gr / RG, h = gr % RG;
+        const bool in = c1[h] && l_row_in(im, tj0 - 2 + r);
+        const uint2 v{l_pack_bf16(in ? fmaxf(acc[0], 0.f) : 0.f, in ? fmaxf(acc[1], 0.f) : 0.f),
+                      l_pack_bf16(in ? fmaxf(acc[2], 0.f) : 0.f, in ? fmaxf(acc[3], 0.f) : 0.f)};
+        *reinterpret_cast<uint2*>(&S.h1[(r * HW + 16 * h + c16) * kLC + 4 * g]) = v;
+    };
+    for (int gr = wave; gr < NG1; gr += 2 * NWV) {
+        const int gb = gr + NWV;
+        const floatx4 ha = layer1(gr);
+        const floatx4 hb = layer1(gb < NG1 ? gb : gr);
+        store1(gr, ha);
+        if (gb < NG1) store1(gb, hb);
+    }
+    __syncthreads();
+    auto layer23 = [&](int gr) {
+        const int r = gr / RG, h = gr % RG;
+        const uint16_t* hb = S.h1 + r * HW * kLC + hb2[h];
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 0; m < 5; ++m)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[m], *reinterpret_cast<const lbf16x8*>(hb + ho[m]), acc,
+                                                          0, 0, 0);
+        const bool in = c2[h] && l_row_in(im, tj0 - 1 + r);
+        floatx4 u = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            u = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[j], in ? fmaxf(acc[j], 0.f) : 0.f, u, 0, 0, 0);
+        return u;
+    };
+    auto store23 = [&](int gr, const floatx4& u) {
+        const int r = gr / RG, h = gr % RG;
+        float* ub = S.u + r * HW + 16 * h + c16;  // columns >= UW: unused padding
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (4 * g + j < 9) ub[(4 * g + j) * UW * HW] = u[j];
+    };
+    for (int gr = wave; gr < NG2; gr += 2 * NWV) {
+        const int gb = gr + NWV;
+        const floatx4 ua = layer23(gr);
+        const floatx4 ub = layer23(gb < NG2 ? gb : gr);
+        store23(gr, ua);
+        if (gb < NG2) store23(gb, ub);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+        const int o = tid + k * NT;
+        const int oy = o / TL, ox = o % TL;
+        const int pj = tj0 + oy, pi = ti0 + ox;
+        if (o < TL * TL && pj < im.height && pi < im.width && l_inside(im, pj, pi)) {
+            float y = 0.f;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) y += S.u[(tap * UW + oy + tap / 3) * HW + ox + tap % 3];
+            const size_t I = (size_t)pj * im.width + pi;
+            if (yout)
+                yout[I] = y;
+            else
+                x[I] = xo[k] + (T)(sg * (double)y);
+        }
+    }
+}
+
 // sigma = sqrt(sum partial / N), one block of kLSigmaThreads.
 constexpr int kLSigmaThreads = 1024;
 __global__ void __launch_bounds__(kLSigmaThreads) k_learned_sigma(const double* __restrict__ partial, int np,
@@ -370,7 +586,8 @@ __global__ void k_learned_reduce(const float* __restrict__ gpart, int nblocks,
 __global__ void k_learned_adam(float* __restrict__ master, float* __restrict__ m, float* __restrict__ v,
                                const float* __restrict__ grad, float lr, float b1, float b2, float eps,
                                float bc1, float bc2, uint16_t* __restrict__ wc, uint16_t* __restrict__ w2f,
-                               uint16_t* __restrict__ w2b) {
+                               uint16_t* __restrict__ w2b, float* __restrict__ mf32,
+                               uint16_t* __restrict__ mfbf) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= kLWeights) return;
     float g = grad[k];
@@ -387,17 +604,29 @@ __global__ void k_learned_adam(float* __restrict__ master, float* __restrict__ m
         w2f[((size_t)tap * kLC + co) * kLC + ci] = h;
         w2b[((size_t)tap * kLC + ci) * kLC + co] = h;
     }
+    int fs, bs;
+    l_mf_slot(k, fs, bs);
+    if (fs >= 0) mf32[fs] = bf16_to_f32(h);
+    if (bs >= 0) mfbf[bs] = h;
 }
 
-// Canonical BF16 weights -> the two W2 layouts (after an external load).
+// Canonical BF16 weights -> the two W2 layouts and the MFMA records (after an
+// external load; one thread per canonical weight).
 __global__ void k_learned_layouts(const uint16_t* __restrict__ wc, uint16_t* __restrict__ w2f,
-                                  uint16_t* __restrict__ w2b) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= kLW2) return;
-    int co = e / (kLC * 9), ci = (e / 9) % kLC, tap = e % 9;
-    uint16_t h = wc[kLW1 + e];
-    w2f[((size_t)tap * kLC + co) * kLC + ci] = h;
-    w2b[((size_t)tap * kLC + ci) * kLC + co] = h;
+                                  uint16_t* __restrict__ w2b, float* __restrict__ mf32,
+                                  uint16_t* __restrict__ mfbf) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kLWeights) return;
+    const uint16_t h = wc[k];
+    if (k >= kLW1 && k < kLW1 + kLW2) {
+        int e = k - kLW1, co = e / (kLC * 9), ci = (e / 9) % kLC, tap = e % 9;
+        w2f[((size_t)tap * kLC + co) * kLC + ci] = h;
+        w2b[((size_t)tap * kLC + ci) * kLC + co] = h;
+    }
+    int fs, bs;
+    l_mf_slot(k, fs, bs);
+    if (fs >= 0) mf32[fs] = bf16_to_f32(h);
+    if (bs >= 0) mfbf[bs] = h;
 }
 
 // e_hf = u - x - P e_c target pieces are formed with the ordinary kernels;

@@ -64,6 +64,18 @@ class State(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tail_items", ctypes.c_int), ("tail_top", ctypes.c_int), ("num_levels", ctypes.c_int),
+                ("row_class", ctypes.c_int * 16), ("learned_kernel", ctypes.c_int * 16),
+                ("vcycle_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        n = self.num_levels
+        return {"tail_items": self.tail_items, "tail_top": self.tail_top, "num_levels": n,
+                "row_class": list(self.row_class)[:n], "learned_kernel": list(self.learned_kernel)[:n],
+                "vcycle_ms": self.vcycle_ms}
+
+
 class TrainOptions(ctypes.Structure):
     _fields_ = [("n_rhs", ctypes.c_int), ("modes", ctypes.c_void_p), ("n_modes", ctypes.c_int),
                 ("vcycles_per_rhs", ctypes.c_int), ("epochs", ctypes.c_int), ("batch", ctypes.c_int),
@@ -154,6 +166,8 @@ _SIGNATURES = {
     "igamg_batch_instance": (_i, [_P, _i, ctypes.POINTER(_P)]),
     "igamg_solve_batch": (_i, [_P, _d, _i, _i, _P, _P]),
     "igamg_autotune": (_i, [_P, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+    "igamg_get_tuning": (_i, [_P, ctypes.POINTER(Tuning)]),
+    "igamg_set_tuning": (_i, [_P, ctypes.POINTER(Tuning)]),
     "igamg_problem1d_default": (None, [ctypes.POINTER(Problem1D)]),
     "igamg_setup_1d": (_i, [_i, ctypes.POINTER(Problem1D), _P, ctypes.POINTER(_P)]),
     "igamg_destroy_1d": (None, [_P]),
@@ -441,10 +455,28 @@ class Solver:
         return ms.value, by.value, n.value
 
     def autotune(self):
-        """(chosen tail_items, V-cycle ms)."""
+        """(chosen tail_items, V-cycle ms); the per-level choices via tuning()."""
         t, ms = _i(), _d()
         _check(lib().igamg_autotune(self._h, ctypes.byref(t), ctypes.byref(ms)), "igamg_autotune")
         return t.value, ms.value
+
+    def tuning(self):
+        """The launch shapes in use (dict: split, per-level sweep and learned kernels)."""
+        t = Tuning()
+        _check(lib().igamg_get_tuning(self._h, ctypes.byref(t)), "igamg_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, d):
+        """Sets the launch shapes from a dict as tuning() returns."""
+        n = int(d["num_levels"])
+        if len(d["row_class"]) != n or len(d["learned_kernel"]) != n or n > 16:
+            raise ValueError("per-level lists must have num_levels <= 16 entries")
+        t = Tuning()
+        t.tail_items, t.num_levels = int(d["tail_items"]), n
+        for l in range(n):
+            t.row_class[l] = int(d["row_class"][l])
+            t.learned_kernel[l] = int(d["learned_kernel"][l])
+        _check(lib().igamg_set_tuning(self._h, ctypes.byref(t)), "igamg_set_tuning")
 
     # ---- learned smoother
     def train_smoother(self, modes_list, val_modes=None, **kw):

@@ -63,10 +63,14 @@ def test_batch_equals_standalone_and_converges():
 def test_autotune_choice_is_cached_and_used():
     s = igamg.Solver(igamg.QUARTER_ANNULUS, 128, 4)
     items, ms = s.autotune()
-    print("[autotune] annulus 128 p=4 -> tail_items=%d (%.3f ms per V-cycle)" % (items, ms))
+    tu = s.tuning()
+    print("[autotune] annulus 128 p=4 -> tail_items=%d (%.3f ms per V-cycle) %s" % (items, ms, tu))
     assert items in (0, 8, 16, 32, 64, 128, 256, 512) and ms > 0
+    assert tu["tail_items"] == items and tu["vcycle_ms"] == ms and tu["num_levels"] == s.num_levels
+    assert set(tu["row_class"]) <= {0, 1} and set(tu["learned_kernel"]) <= {0, 12, 28, 29}
     t = igamg.Solver(igamg.QUARTER_ANNULUS, 128, 4, tail_items=-1)
     assert t.options.tail_items == -1  # resolved inside the library
+    assert t.tuning() == tu  # every tuned shape comes from the cache
     modes = synth.random_field_modes(77)
     for solver in (s, t):
         solver.set_rhs_field(modes)
@@ -76,3 +80,11 @@ def test_autotune_choice_is_cached_and_used():
     sb, _ = t.solve(xb, tol=1e-10, method=igamg.RRE, q=5)
     assert sa.vcycles == sb.vcycles
     assert torch.equal(xa, xb)
+    # the sweep launch shape changes times, not iterates: flipping every
+    # level's row-class choice gives the same solve bit for bit
+    u = dict(tu, row_class=[1 - r for r in tu["row_class"]])
+    t.set_tuning(u)
+    xc = torch.zeros(t.ndof, dtype=torch.float64, device=DEV)
+    sc, _ = t.solve(xc, tol=1e-10, method=igamg.RRE, q=5)
+    assert sc.vcycles == sa.vcycles
+    assert torch.equal(xc, xa)

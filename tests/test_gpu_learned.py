@@ -54,6 +54,44 @@ def test_forward_matches_oracle(solver, level, seed):
     assert err < 1e-4
 
 
+@pytest.mark.parametrize("kernel", [0, 12, 28, 29])
+@pytest.mark.parametrize("level,seed", [(5, 11), (3, 12)])
+def test_every_inference_kernel_matches_oracle(solver, kernel, level, seed):
+    """Each inference kernel the autotuner can pick (16x16-tile VALU/MFMA;
+    all-MFMA with 12x12 or 28x28 tiles, 512 or 256 threads) against the
+    oracle's forward pass on the same BF16 points; level 3 (11^2) is smaller
+    than one tile and level 5 (131^2) leaves a ragged edge tile for each."""
+    rng = np.random.default_rng(seed)
+    Ws = ln.init_weights(rng)
+    solver.set_smoother_weights(level, to_bf16_bits(canonical(Ws)))
+    Wq = from_canonical(ln.bf16_round(canonical(Ws)))
+    t = solver.tuning()
+    t["learned_kernel"][level] = kernel
+    solver.set_tuning(t)
+    assert solver.tuning()["learned_kernel"][level] == kernel
+    n = int(round(solver.level_ndof(level) ** 0.5))
+    z = rng.standard_normal((n, n)).astype(np.float32)
+    y = torch.zeros(n * n, dtype=torch.float32, device=DEV)
+    solver.smoother_forward(level, torch.tensor(z.ravel(), device=DEV), y)
+    yr, _ = ln.forward(z.astype(np.float64), Wq, bf16_points=True)
+    err = np.linalg.norm(y.cpu().numpy().reshape(n, n) - yr) / np.linalg.norm(yr)
+    print("[learned fwd] kernel %d level %d n=%d rel err %.2e" % (kernel, level, n, err))
+    assert err < 1e-4
+
+
+def test_tuning_is_validated(solver):
+    t = solver.tuning()
+    for field, bad in (("learned_kernel", 16), ("row_class", 2)):
+        u = dict(t, **{field: list(t[field])})
+        u[field][1] = bad
+        with pytest.raises(igamg.IgamgError):
+            solver.set_tuning(u)
+    with pytest.raises(ValueError):
+        solver.set_tuning(dict(t, num_levels=t["num_levels"] + 1))
+    solver.set_tuning(t)
+    assert solver.tuning()["learned_kernel"] == t["learned_kernel"]
+
+
 @pytest.mark.parametrize("level,seed", [(5, 4), (3, 5)])
 def test_gradients_match_oracle(solver, level, seed):
     rng = np.random.default_rng(seed)
