@@ -546,6 +546,11 @@ struct igamg_ctx {
             a.b[l] = (l == tail_top) ? (T*)bt : lv[l].b<T>();
             a.r[l] = lv[l].r<T>();
             if constexpr (std::is_same_v<T, float>) a.rec[l] = lv[l].rec32;
+            {
+                int mx = 0;
+                for (int c = 0; c < lv[l].ncol; ++c) mx = std::max(mx, colour_size_host(lv[l].n, p, dim, c));
+                a.act[l] = std::max(1, (mx + 63) / 64);
+            }
             if (!tail_level_ok<T>(l)) throw Error(IGAMG_EINVAL, "tail level without coefficient records");
             if (l >= 1) {
                 a.rs[l] = lv[l].r_start;

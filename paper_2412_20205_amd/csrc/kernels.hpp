@@ -1221,6 +1221,7 @@ struct TailArgs {
     T* b[kTailMaxLevels];
     T* r[kTailMaxLevels];
     const T* rec[kTailMaxLevels];   // per-point coefficient records (prefetching variant)
+    int act[kTailMaxLevels];        // prefetching variant: waves holding points of the level's largest colour
     const int* rs[kTailMaxLevels];  // transfer tables between l-1 and l
     const T* rw[kTailMaxLevels];
     const int* ps[kTailMaxLevels];
@@ -1649,7 +1650,20 @@ constexpr int pf_group() {
     return u;
 }
 
-template <int P, int U = 0>
+// Ordering point between two colour steps.  Several waves: a workgroup
+// barrier.  One wave (kSolo: every point of every colour in wave 0): its LDS
+// operations run in issue order, so waiting for its own outstanding LDS
+// operations, with the compiler kept from moving memory accesses across the
+// point, orders the updates without a workgroup barrier.
+template <bool kSolo>
+__device__ __forceinline__ void pf_sync() {
+    if constexpr (kSolo)
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    else
+        __syncthreads();
+}
+
+template <int P, bool kSolo, int U = 0>
 __device__ __forceinline__ void pf_group_colours(const Stencil2D<P, float>& A, const float* __restrict__ rec,
                                                  const float* __restrict__ b, float* xl,
                                                  float* __restrict__ r, bool gs, int c0,
@@ -1658,37 +1672,62 @@ __device__ __forceinline__ void pf_group_colours(const Stencil2D<P, float>& A, c
     const int c = c0 + U;
     pf_fetch<P>(A, rec, b, (c + R - 1) % NC, ring[(U + R - 1) % R]);
     pf_colour<P, U>(A, xl, r, gs, ring[U % R]);
-    if (gs || c == NC - 1) __syncthreads();
-    if constexpr (U + 1 < pf_group<P>()) pf_group_colours<P, U + 1>(A, rec, b, xl, r, gs, c0, ring);
+    if (gs || c == NC - 1) pf_sync<kSolo>();
+    if constexpr (U + 1 < pf_group<P>()) pf_group_colours<P, kSolo, U + 1>(A, rec, b, xl, r, gs, c0, ring);
 }
 
 // One sweep: groups of pf_group colours, the groups in a (not unrolled) loop.
-template <int P>
+template <int P, bool kSolo>
 __device__ __forceinline__ void pf_sweep(const Stencil2D<P, float>& A, const float* __restrict__ rec,
                                          const float* __restrict__ b, float* xl, float* __restrict__ r,
                                          bool gs, PfRegs<P> (&ring)[pf_ring<P>()]) {
     constexpr int NC = (P + 1) * (P + 1), R = pf_ring<P>(), U = pf_group<P>();
     static_assert(NC % R == 0 && NC % U == 0 && U % (P + 1) == 0, "colour grouping");
 #pragma unroll 1
-    for (int c0 = 0; c0 < NC; c0 += U) pf_group_colours<P>(A, rec, b, xl, r, gs, c0, ring);
+    for (int c0 = 0; c0 < NC; c0 += U) pf_group_colours<P, kSolo>(A, rec, b, xl, r, gs, c0, ring);
 }
 
-// nsw Gauss-Seidel sweeps (a barrier after every colour), then, if resid,
-// r = b - A x over all colours (one barrier at the end).  The records of the
-// next R - 1 colours are in flight while a colour is updated, across the
-// LDS-only barriers (after the last colour they fetch colours of a sweep
-// that does not come; the loads are valid and unused).
-template <int P>
-__device__ void pf_sequence(const Stencil2D<P, float>& A, const float* __restrict__ rec,
-                            const float* __restrict__ b, float* xl, float* __restrict__ r, int nsw,
-                            bool resid) {
+// nsw Gauss-Seidel sweeps (an ordering point after every colour), then, if
+// resid, r = b - A x over all colours (one at the end), run by the waves that
+// hold points.  The records of the next R - 1 colours are in flight while a
+// colour is updated, across the LDS-only ordering points (after the last
+// colour they fetch colours of a sweep that does not come; the loads are valid
+// and unused).
+template <int P, bool kSolo>
+__device__ void pf_run(const Stencil2D<P, float>& A, const float* __restrict__ rec,
+                       const float* __restrict__ b, float* xl, float* __restrict__ r, int nsw, bool resid) {
     constexpr int R = pf_ring<P>();
     const int nsweeps = nsw + (resid ? 1 : 0);
-    if (nsweeps == 0) return;
     PfRegs<P> ring[R];
 #pragma unroll
     for (int c = 0; c + 1 < R; ++c) pf_fetch<P>(A, rec, b, c, ring[c]);
-    for (int sw = 0; sw < nsweeps; ++sw) pf_sweep<P>(A, rec, b, xl, r, sw < nsw, ring);
+    for (int sw = 0; sw < nsweeps; ++sw) pf_sweep<P, kSolo>(A, rec, b, xl, r, sw < nsw, ring);
+}
+
+// The sequence on a level whose largest colour spans `act` waves: only those
+// waves load records and update (one point per thread; inside an active wave
+// the lanes past a colour's points load a valid record they do not use, so
+// each wait counts exactly the loads issued before it).  The other waves meet
+// the same workgroup barriers and nothing else; with act == 1 wave 0 runs
+// alone and the workgroup meets once at the end.
+template <int P>
+__device__ void pf_sequence(const Stencil2D<P, float>& A, const float* __restrict__ rec,
+                            const float* __restrict__ b, float* xl, float* __restrict__ r, int nsw,
+                            bool resid, int act) {
+    constexpr int NC = (P + 1) * (P + 1);
+    if (nsw + (resid ? 1 : 0) == 0) return;
+    const int wave = threadIdx.x >> 6;
+    if (act <= 1) {
+        if (wave == 0) pf_run<P, true>(A, rec, b, xl, r, nsw, resid);
+        __syncthreads();
+        return;
+    }
+    if (wave < act) {
+        pf_run<P, false>(A, rec, b, xl, r, nsw, resid);
+    } else {
+        const int nbar = nsw * NC + (resid ? 1 : 0);
+        for (int k = 0; k < nbar; ++k) __syncthreads();
+    }
 }
 
 template <int P, typename T>
@@ -1712,7 +1751,7 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
         const Op& A = a.op[l];
         T* xl = xs + a.xoff[l];
         if constexpr (tail_prefetch<Op>()) {
-            pf_sequence<P>(A, a.rec[l], a.b[l], xl, a.r[l], a.nu1, true);
+            pf_sequence<P>(A, a.rec[l], a.b[l], xl, a.r[l], a.nu1, true, a.act[l]);
         } else {
             for (int s = 0; s < a.nu1; ++s) ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 0);
             ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1);
@@ -1740,7 +1779,7 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
         ft_prolong<P, T>(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l]);
         __syncthreads();
         if constexpr (tail_prefetch<Op>())
-            pf_sequence<P>(A, a.rec[l], a.b[l], xl, a.r[l], a.nu2, false);
+            pf_sequence<P>(A, a.rec[l], a.b[l], xl, a.r[l], a.nu2, false, a.act[l]);
         else
             for (int s = 0; s < a.nu2; ++s) ft_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 0);
     };
