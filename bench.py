@@ -471,6 +471,8 @@ def main():
     ap.add_argument("--no-elliptic", action="store_true")
     ap.add_argument("--no-1d", action="store_true")
     ap.add_argument("--only-batch", action="store_true")
+    ap.add_argument("--only-chosen", action="store_true",
+                    help="setup, tuning and training, then only the chosen-form solves (kernel profiles)")
     ap.add_argument("--only-1d", action="store_true",
                     help="only the 1D model problem leg (Tables 1 and 4), printed as its own JSON line")
     ap.add_argument("--epochs", type=int, default=10)
@@ -517,6 +519,23 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only_smoother": True, "degree": p, "copy_bytes": 2 * a.numel() * 8,
                           **out}), flush=True)
+        return
+
+    if args.only_chosen:
+        # setup, tuning and training as in the full run, then only the timed
+        # chosen-form solves (a short run for kernel profiles)
+        p = args.headline_degree
+        s = igamg.Solver(igamg.QUARTER_ANNULUS, N_EL, p, tail_items=-1)
+        s.set_precision(igamg.FP32_IR)
+        s.autotune()
+        rep = s.train_smoother([synth.random_field_modes(5000 + k) for k in range(16)],
+                               val_modes=synth.random_field_modes(5900), epochs=args.epochs)
+        s.set_rhs_field(synth.random_field_modes(2000 + p))
+        ms, st, _ = time_form(s, igamg, torch, igamg.RRE, igamg.FP32_IR, args.steps, args.warmup, True,
+                              bool(rep["accepted"]))
+        print(json.dumps({"only_chosen": True, "degree": p, "ms": round(ms, 3), "vcycles": st.vcycles,
+                          "restarts": st.restarts, "learned": bool(rep["accepted"]),
+                          "tuning": s.tuning()}), flush=True)
         return
 
     if args.only_batch:

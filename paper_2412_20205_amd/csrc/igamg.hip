@@ -91,6 +91,7 @@ struct Level {
     double *r_w64 = nullptr, *p_w64 = nullptr;
     float *r_w32 = nullptr, *p_w32 = nullptr;
     int RW = 0, PW = 0;
+    bool sym = false;        // stored stencils made exactly symmetric at setup
     double *x64 = nullptr, *b64 = nullptr, *r64 = nullptr;
     float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
 
@@ -1100,6 +1101,22 @@ void igamg_ctx::setup_annulus() {
     check_launch();
     for (double* a : {G.D11, G.D12, G.D22, G.wdet, G.X, G.Y, G.Bx, G.By, G.Cw})
         if (a) release(a);
+    // the Poisson operator is symmetric (Section 2, eq. (2)): make every level
+    // exactly so (its assembly and the Galerkin products give it up to
+    // rounding); the coarsest Cholesky factor then sees a symmetric matrix
+    const bool sym = opt.pde == IGAMG_PDE_POISSON;
+    auto symmetrize = [&](int l) {
+        if (!sym) return;
+        const long long cnt = lv[l].N * (long long)(p * W + p);
+        with_p([&](auto PC) {
+            constexpr int P = decltype(PC)::value;
+            hipLaunchKernelGGL(k_symmetrize_stencil<P>, dim3(grid_for(cnt)), dim3(kBlock), 0, stream, stage[l],
+                               lv[l].n);
+        });
+        check_launch();
+        lv[l].sym = true;
+    };
+    symmetrize(L);
     // Galerkin coarse operators, separable: x pass then y pass
     for (int l = L; l >= 1; --l) {
         Level& fl = lv[l];
@@ -1115,6 +1132,7 @@ void igamg_ctx::setup_annulus() {
         });
         check_launch();
         release(Tm);
+        symmetrize(l - 1);
     }
     for (int l = 0; l <= L; ++l) {
         Level& v = lv[l];
@@ -1148,7 +1166,6 @@ void igamg_ctx::setup_annulus() {
         }
     }
     // nonsymmetric operators: LU with partial pivoting; Poisson: Cholesky
-    const bool sym = opt.pde == IGAMG_PDE_POISSON;
     std::vector<double> inv;
     if (coarse_inverse(std::move(A), n0, sym, inv) != 0)
         throw Error(IGAMG_ENOTSPD, sym ? "coarsest operator is not SPD" : "coarsest operator is singular");

@@ -2273,6 +2273,24 @@ __global__ void k_rap_y(const double* __restrict__ Tin, int nf, int nc, const in
 }
 
 // Natural row-major stencil rows -> colour-blocked FP64 and FP32 copies.
+// Exact symmetry of an assembled stencil operator (natural layout, n^2 rows
+// of S offsets): every lower-half entry A[I, I+o] (offsets before the centre,
+// o < p W + p) takes the value of its mirror A[J, J-o], J = I + o, an
+// upper-half entry, so that A equals A^T bit for bit (assembly and Galerkin
+// products give it up to rounding).
+template <int P>
+__global__ void k_symmetrize_stencil(double* __restrict__ st, int n) {
+    constexpr int W = 2 * P + 1, S = W * W, H0 = P * W + P;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long long)n * n * H0) return;
+    const long long I = t / H0;
+    const int o = (int)(t - I * H0);
+    const int j = (int)(I / n), i = (int)(I - (long long)j * n);
+    const int i2 = i + o % W - P, j2 = j + o / W - P;
+    if (i2 < 0 || i2 >= n || j2 < 0 || j2 >= n) return;
+    st[I * S + o] = st[((long long)j2 * n + i2) * S + (S - 1 - o)];
+}
+
 template <int P>
 __global__ void k_to_colour_blocked(const double* __restrict__ st, int n, int ncp,
                                     double* __restrict__ c64, float* __restrict__ c32) {
