@@ -49,7 +49,7 @@ HBM_PEAK_GBS = 8000.0
 # Counter-derived HBM traffic per launch of the finest-level row-class sweep (FETCH_SIZE x 2.0
 # + WRITE_SIZE, calibrated on a 1 GiB copy), from the committed counter profile of that
 # kernel.  Valid only for the kernel as profiled; entries are removed when the kernel changes.
-MEASURED_TRAFFIC = {(3, "double"): 119.67e6, (3, "float"): 58.65e6}
+MEASURED_TRAFFIC = {(3, "double"): 119.70e6, (3, "float"): 58.67e6}
 TOL = 1e-10
 Q = 5
 N_EL = 1024
