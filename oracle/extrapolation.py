@@ -40,16 +40,25 @@ def differences(S):
 
 
 def _gamma_from_R(R, method):
-    """Coefficients gamma (summing to 1) from the R factor of Delta S_{q+1}.
+    """Weights gamma (summing to 1) from the triangular factor R of the
+    difference matrix U = Delta S = Q R (so U^T U = R^T R).
 
-    Algorithm 3 (RRE): R^T R d = (1,...,1)^T.  Algorithm 4 (MPE): R_q d = -r_q
-    with d_q = 1.  Returns (gamma, info) with info in {"ok", "lucky"}.
+    RRE: gamma minimises ||U gamma|| over sum(gamma) = 1.  Stationarity of
+    ||U gamma||^2 - 2 lam (sum(gamma) - 1) gives U^T U gamma = lam 1, so gamma
+    is d = (R^T R)^{-1} 1 scaled to sum 1.
+    MPE: the combination U c with c_q = 1 is orthogonal to the first q
+    differences, U_q^T U c = 0, i.e. (R_q^T R_q) c_{<q} = -R_q^T r_q with R_q the
+    leading q x q block and r_q the first q entries of the last column; with
+    R_q invertible that is R_q c_{<q} = -r_q; gamma = c scaled to sum 1.
+    Returns (gamma, info) with info in {"ok", "lucky"}.
     """
     q1 = R.shape[1]
     colnorm = np.sqrt(np.sum(R * R, axis=0))
     for j in range(q1):
         if abs(R[j, j]) <= LUCKY_TOL * colnorm[j]:
-            # lucky breakdown: the first j+1 differences are dependent
+            # lucky breakdown: the first j+1 differences are dependent, and the
+            # combination of them that vanishes gives the fixed point of a
+            # linear map exactly
             if j == 0:
                 g = np.zeros(q1)
                 g[0] = 1.0
@@ -62,9 +71,9 @@ def _gamma_from_R(R, method):
                 raise Breakdown("lambda ~ 0")
             return d / lam, "lucky"
     if method == RRE:
-        e = np.ones(q1)
-        y = np.linalg.solve(R.T, e)          # R^T y = e
-        d = np.linalg.solve(np.triu(R), y)   # R d = y
+        # (R^T R) d = 1 through the two triangular factors (not the normal
+        # matrix, whose condition is the square of R's)
+        d = np.linalg.solve(np.triu(R), np.linalg.solve(np.triu(R).T, np.ones(q1)))
     elif method == MPE:
         q = q1 - 1
         d = np.zeros(q1)
@@ -79,31 +88,44 @@ def _gamma_from_R(R, method):
     return d / lam, "ok"
 
 
-def extrapolate(S, method):
-    """t_{0,q} from s_0 .. s_{q+1} by Algorithm 3 (RRE) or 4 (MPE).
-
-    QR by Householder reflections (LAPACK through numpy).  Returns
-    (t, gamma, info).  t = s_0 + Q_q (R_q alpha), where
-    alpha_0 = 1 - gamma_0 and alpha_j = alpha_{j-1} - gamma_j.
-    """
+def _factor(S):
+    """Q, R of the difference matrix (Householder QR through numpy), padded to
+    q+1 columns when there are fewer unknowns than differences (the missing
+    rows of R are zero: the trailing differences are dependent)."""
     U = differences(S)
     q1 = U.shape[1]
-    q = q1 - 1
     Q, R = np.linalg.qr(U, mode="reduced")
     if R.shape[0] < q1:
-        # fewer unknowns than differences: R is trapezoidal; the missing rows are
-        # zero, so the trailing columns are dependent (lucky breakdown)
         R = np.vstack([R, np.zeros((q1 - R.shape[0], q1))])
         Q = np.hstack([Q, np.zeros((Q.shape[0], q1 - Q.shape[1]))])
     if not np.all(np.isfinite(R)):
         raise FloatingPointError("non-finite R")
+    return Q, R
+
+
+def extrapolate(S, method):
+    """The extrapolated vector of s_0 .. s_{q+1} (Section 3, Algorithms 3 and 4):
+    t = sum_{j=0}^{q} gamma_j s_j with the RRE or MPE weights of the q+1 first
+    differences (see _gamma_from_R).  Returns (t, gamma, info)."""
+    _, R = _factor(S)
     gamma, info = _gamma_from_R(R, method)
-    alpha = np.zeros(q)
-    acc = 1.0
-    for j in range(q):
-        acc -= gamma[j]
-        alpha[j] = acc
-    t = np.asarray(S[0], dtype=np.float64) + Q[:, :q] @ (R[:q, :q] @ alpha)
+    t = np.zeros_like(np.asarray(S[0], dtype=np.float64))
+    for j in range(len(gamma)):
+        t = t + gamma[j] * np.asarray(S[j], dtype=np.float64)
+    return t, gamma, info
+
+
+def extrapolate_qr_form(S, method):
+    """The same t computed through the QR factor, as the algorithms do and as
+    the library does without forming Q: t = s_0 + sum_{j<q} a_j (s_{j+1} - s_j)
+    with a_j = 1 - (gamma_0 + ... + gamma_j), here evaluated as s_0 + Q_q (R_q a)
+    (Q_q R_q = U_q, the first q differences).  Equal to extrapolate() up to
+    rounding (summation by parts); a cross-check of that identity."""
+    Q, R = _factor(S)
+    gamma, info = _gamma_from_R(R, method)
+    q = len(gamma) - 1
+    a = 1.0 - np.cumsum(gamma[:q])
+    t = np.asarray(S[0], dtype=np.float64) + Q[:, :q] @ (R[:q, :q] @ a)
     return t, gamma, info
 
 
@@ -160,7 +182,11 @@ class SolveStats:
 
 def restarted_solve(G, residual_norm, s0, q, method, tol=1e-10, max_restarts=100,
                     keep_iterates=False):
-    """Algorithm 5: restarted RRE(q) / MPE(q) around the fixed-point map G.
+    """Restarted extrapolation (Section 3.2, Algorithm 5): from the current
+    vector, apply the fixed-point map G q+1 times, extrapolate, test the
+    extrapolated vector's relative residual and, if it is not small enough,
+    start the next cycle from it.  A cycle whose weights are undefined
+    (Breakdown) continues from its last iterate.
 
     G(x) returns the next iterate; residual_norm(x) returns ||b - A x|| / ||b||.
     method None gives the plain iteration, tested after every application of G.

@@ -38,6 +38,27 @@ def _krylov(A, r0, m):
 
 
 @pytest.mark.parametrize("q", [1, 3, 5, 8])
+@pytest.mark.parametrize("method", [ex.RRE, ex.MPE])
+def test_weighted_sum_equals_qr_form(q, method):
+    """t = sum_j gamma_j s_j (the definition) equals the algorithms' QR form
+    s_0 + Q_q R_q a, a_j = 1 - sum_{i<=j} gamma_i (summation by parts), on a
+    linear sequence and on FP64 V-cycle iterates of the annulus."""
+    _, _, S = _linear_sequence(q=q, seed=10 + q)
+    t, g, _ = ex.extrapolate(S, method)
+    t2, g2, _ = ex.extrapolate_qr_form(S, method)
+    assert np.array_equal(g, g2)
+    np.testing.assert_allclose(t, t2, rtol=1e-12, atol=1e-13 * np.abs(t).max())
+    H = mg.build_hierarchy("annulus", 16, 3)
+    b = assemble.load_vector_2d(16, 3, synth.random_field_modes(2003))
+    V = [np.zeros(len(b))]
+    for _ in range(q + 1):
+        V.append(mg.vcycle(H, b, V[-1]))
+    t, _, _ = ex.extrapolate(V, method)
+    t2, _, _ = ex.extrapolate_qr_form(V, method)
+    assert np.linalg.norm(t - t2) <= 1e-13 * np.linalg.norm(t)
+
+
+@pytest.mark.parametrize("q", [1, 3, 5, 8])
 def test_algorithms_match_closed_forms(q):
     _, _, S = _linear_sequence(q=q, seed=q)
     t_rre, g, _ = ex.extrapolate(S, ex.RRE)
