@@ -1,7 +1,9 @@
 """Flexible GMRES preconditioned by one V-cycle or by one RRE/MPE restart cycle
 (the extrapolated cycle as a preconditioner), against the oracle's FGMRES with
-the same preconditioners: iterates after a fixed number of steps to 1e-9
-relative, and solves to 1e-10 with the oracle's iteration counts (+-1)."""
+the same preconditioners: iterates after a fixed number of steps to 1e-12
+relative (the FP64 per-iterate bar; measured 1.3e-15 to 4.6e-15, while a
+one-ulp change of b moves the oracle's own iterates by up to 1.4e-15), and
+solves to 1e-10 with exactly the oracle's iteration counts and x within 1e-12."""
 import numpy as np
 import pytest
 import torch
@@ -34,7 +36,7 @@ def test_fixed_iterations_match_oracle(kind, n_el, p, precond):
         st, status = s.solve_fgmres(xg, tol=1e-300, max_iters=k, m=20, precond=precond, q=3, check=False)
         assert status == igamg.ENOCONV and st.restarts == k
         xr, it = krylov.fgmres(A, b, M, m=20, fixed_iters=k)
-        assert rel(host(xg), xr) < 1e-9, k
+        assert rel(host(xg), xr) < 1e-12, k
 
 
 @pytest.mark.parametrize("kind,n_el,p", [("annulus", 64, 3), ("square1", 64, 3), ("exact2", 64, 4)])
@@ -47,7 +49,8 @@ def test_solve_matches_oracle_counts(kind, n_el, p, precond):
     st, _ = s.solve_fgmres(xg, tol=1e-10, max_iters=200, m=20, precond=precond, q=3)
     x = host(xg)
     assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1.0000001e-10
-    assert abs(st.restarts - it) <= 1
+    assert st.restarts == it
+    assert rel(x, xr) < 1e-12
     assert st.vcycles == st.restarts * (1 if precond == igamg.PRECOND_VCYCLE else 4)
 
 
