@@ -167,6 +167,9 @@ def c1_measure(igamg, torch, synth, steps):
     for sm_name, sm in (("mcgs", igamg.SMOOTH_MCGS), ("lexgs", igamg.SMOOTH_LEXGS)):
         s = igamg.Solver(igamg.UNIT_SQUARE, 64, 2, smoother=sm)
         s.set_rhs_field(synth.manufactured_sine_modes_2d())
+        if sm == igamg.SMOOTH_MCGS:
+            s.autotune()  # sweep launch shapes and the single-workgroup split
+            out["mcgs_tuning"] = s.tuning()
         for m_name, m in (("plain", igamg.EXTRAP_NONE), ("rre5", igamg.RRE), ("mpe5", igamg.MPE)):
             ms, st, _ = time_form(s, igamg, torch, m, igamg.FP64, steps, 1)
             out["%s_%s" % (sm_name, m_name)] = {"ms": round(ms, 3), "vcycles": st.vcycles,
@@ -347,17 +350,25 @@ def elliptic_measure(igamg, torch, steps):
     return out
 
 
-def c3_measure(igamg, torch, synth, steps):
+def c3_measure(igamg, torch, synth, steps, forms=None):
     """Unit cube, p = 3, 128^3 elements, f = 3 pi^2 prod sin(pi x_d), V(2,2)
-    multicolour GS (64 colours): plain FP64 V-cycles, FP64 MPE(4), and MPE(4)
-    around FP32 V-cycles in FP64 refinement."""
+    multicolour GS (64 colours in 16 row classes): plain FP64 V-cycles, FP64
+    MPE(4), and MPE(4) around FP32 V-cycles in FP64 refinement; launch shapes
+    and the single-workgroup split autotuned per precision."""
     s = igamg.Solver(igamg.UNIT_CUBE, 128, 3)
     s.set_rhs_field(synth.manufactured_sine_modes_3d())
-    out = {"ndof": s.ndof}
+    out = {"ndof": s.ndof, "tuning": {}}
     xs = {}
+    tuned = set()
     for name, m, prec in (("plain_fp64", igamg.EXTRAP_NONE, igamg.FP64), ("mpe4_fp64", igamg.MPE, igamg.FP64),
                           ("mpe4_ir", igamg.MPE, igamg.FP32_IR)):
+        if forms is not None and name not in forms:
+            continue
         s.set_precision(prec)
+        if prec not in tuned:
+            s.autotune()
+            tuned.add(prec)
+            out["tuning"]["fp64" if prec == igamg.FP64 else "fp32"] = s.tuning()
         x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
         s.solve(x, tol=TOL, max_restarts=2000, method=m, q=4)
         torch.cuda.synchronize()
@@ -367,7 +378,8 @@ def c3_measure(igamg, torch, synth, steps):
             st, _ = s.solve(x, tol=TOL, max_restarts=2000, method=m, q=4)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
-        out[name] = {"ms": round(ms, 2), "vcycles": st.vcycles, "rel_residual": st.rel_residual}
+        out[name] = {"ms": round(ms, 2), "vcycles": st.vcycles, "ms_per_vcycle": round(ms / st.vcycles, 3),
+                     "rel_residual": st.rel_residual}
         xs[name] = x.clone()
     s.close()
     return out, xs
@@ -473,6 +485,8 @@ def main():
     ap.add_argument("--only-batch", action="store_true")
     ap.add_argument("--only-chosen", action="store_true",
                     help="setup, tuning and training, then only the chosen-form solves (kernel profiles)")
+    ap.add_argument("--only-cube", action="store_true",
+                    help="only the 128^3 cube's FP32-in-FP64 MPE(4) solves, autotuned (kernel profiles)")
     ap.add_argument("--only-1d", action="store_true",
                     help="only the 1D model problem leg (Tables 1 and 4), printed as its own JSON line")
     ap.add_argument("--epochs", type=int, default=10)
@@ -536,6 +550,11 @@ def main():
         print(json.dumps({"only_chosen": True, "degree": p, "ms": round(ms, 3), "vcycles": st.vcycles,
                           "restarts": st.restarts, "learned": bool(rep["accepted"]),
                           "tuning": s.tuning()}), flush=True)
+        return
+
+    if args.only_cube:
+        c3, _ = c3_measure(igamg, torch, synth, args.steps, forms=("mpe4_ir",))
+        print(json.dumps({"only_cube": True, **c3}), flush=True)
         return
 
     if args.only_batch:

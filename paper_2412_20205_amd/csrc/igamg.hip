@@ -302,11 +302,22 @@ struct igamg_ctx {
 
     // out = b - A x (mode 0), A x (mode 1), Jacobi step (mode 2), z = D^{-1}(b - A x)
     // as float with per-block sums of z^2 in part (mode 3)
+    // (sum-factorised 3D levels: one workgroup per x-row where no per-block
+    // sums are asked for)
     template <typename T, typename Tout>
     void residual(int l, const T* bb, const T* x, Tout* out, int mode, double* part) {
         long long nb = residual_blocks(l);
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
+            if constexpr (!Op::kColourOrder && std::is_same_v<typename Op::Pt, Pt3>) {
+                if (!part && mode <= 2 && row3_available(l)) {
+                    const int n = lv[l].n;
+                    hipLaunchKernelGGL((k_residual_row3<Op, Tout>), dim3((unsigned)((long long)n * n)),
+                                       dim3(((n + 63) / 64) * 64), row3_lds_bytes(p, n, 2, sizeof(T)), stream, op,
+                                       bb, x, out, mode, opt.omega);
+                    return;
+                }
+            }
             hipLaunchKernelGGL((k_residual_sliced<Op, Tout>), dim3((unsigned)nb), dim3(64 * Op::NW), 0,
                                stream, op, bb, x, out, mode, opt.omega, lv[l].N, part);
         });
@@ -351,8 +362,14 @@ struct igamg_ctx {
         return row_sweeps_available(l) && (l >= (int)row_pref.size() || row_pref[l] != 0);
     }
     bool row_sweeps_available(int l) const {
+        if (kind == OP_KRON3D) return row3_available(l);
         return opt.row_sweeps && kind == OP_STENCIL2D && p <= 4 && row_fits(p, lv[l].n) &&
                coef_bytes(l, sizeof(double)) < (1LL << 32);
+    }
+    // Sum-factorised 3D levels of at most kRow3MaxN unknowns per direction:
+    // row-class sweeps and one-workgroup-per-row residuals.
+    bool row3_available(int l) const {
+        return opt.row_sweeps && kind == OP_KRON3D && lv[l].n <= kRow3MaxN;
     }
     // One multicolour Gauss-Seidel sweep of level l (multi-block launches).
     // Returns the number of launches; *bytes (when given) receives the
@@ -370,6 +387,25 @@ struct igamg_ctx {
         int launches = 0;
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
+            if constexpr (!Op::kColourOrder && std::is_same_v<typename Op::Pt, Pt3>) {
+                if (row_sweeps(l)) {
+                    const int P1 = p + 1;
+                    const size_t lds = row3_lds_bytes(p, v.n, 3, sizeof(T));
+                    const int th = ((v.n + 63) / 64) * 64;
+                    for (int ck = 0; ck < P1; ++ck)
+                        for (int cj = 0; cj < P1; ++cj) {
+                            const int nj = (v.n - cj + p) / P1, nk = (v.n - ck + p) / P1;
+                            if (nj <= 0 || nk <= 0) continue;
+                            hipLaunchKernelGGL((k_gs_rowclass3<Op>), dim3(nj * nk), dim3(th), lds, stream, op, bb,
+                                               x, cj, ck);
+                            ++launches;
+                            if (bytes)
+                                for (int ci = 0; ci < P1; ++ci)
+                                    *bytes += colour_size_host(v.n, p, dim, ci + P1 * (cj + P1 * ck)) * per_point;
+                        }
+                    return;
+                }
+            }
             if constexpr (Op::kColourOrder) {
                 if constexpr (row_kernel_ok<Op>()) {
                     if (row_sweeps(l)) {
@@ -491,15 +527,17 @@ struct igamg_ctx {
         int top = 0;
         for (int l = 0; l <= L && l < kTailMaxLevels; ++l) {
             used += tail_level_size<T>(l);
-            if (used + kTailPadVals + kTailPartVals > tail_capacity<T>() || !tail_level_ok<T>(l)) break;
+            if (used + kTailPadVals > tail_capacity<T>() || !tail_level_ok<T>(l)) break;
             top = l;
         }
         return top;
     }
     // The prefetching tail variant (FP32 stored stencils) needs the records of
-    // every level it smooths, which exist where a colour fits the block.
+    // every level it smooths, which exist where a colour fits the block; 3D
+    // levels need rows of at most one wave.
     template <typename T>
     bool tail_level_ok(int l) {
+        if (kind == OP_KRON3D && lv[l].n > kTail3MaxN) return false;  // one lane per point of a row
         bool ok = true;
         with_op<T>(l, [&](auto opl) {
             if constexpr (tail_prefetch<decltype(opl)>()) ok = (l == 0) || lv[l].rec32 != nullptr;
@@ -562,7 +600,7 @@ struct igamg_ctx {
                 a.PW[l] = lv[l].PW;
             }
         }
-        if (tail_top >= kTailMaxLevels || off + kTailPadVals + kTailPartVals > tail_capacity<T>())
+        if (tail_top >= kTailMaxLevels || off + kTailPadVals > tail_capacity<T>())
             throw Error(IGAMG_EINVAL, "levels 0..tail_top do not fit the single-workgroup kernel");
         return a;
     }

@@ -540,6 +540,205 @@ __global__ void __launch_bounds__(kRowThreads) k_gs_rowclass(Op A, const typenam
     for (int i = t; i < n; i += blockDim.x) xj[i] = xrow[i];
 }
 
+// ---- row-class multicolour Gauss-Seidel (sum-factorised 3D operators) -------
+//
+// The colours (ci, cj, ck), ci = 0..p, of one row class (cj, ck) are the points
+// of the x-rows (j, k) with j = cj and k = ck (mod p+1).  Two rows of a class
+// lie p+1 or more apart in j or in k, beyond the operator's reach, so one
+// workgroup per row runs the class's p+1 colour steps in order, and no row that
+// it reads from another class is written meanwhile.  Classes run in colour
+// order, so a sweep is the multicolour sweep of the per-colour kernel (the same
+// updates in the same order; the products are summed in another order).
+// With A = K(x)M(x)M + M(x)K(x)M + M(x)M(x)K (x index fastest), the product at
+// (i, j, k) factors through two contractions over the y and z bands:
+//   (A x)_i = sum_a Kx_{i,a} u_{i+a} + Mx_{i,a} v_{i+a},
+//   u_{i'} = sum_{b,c} My_{j,b} Mz_{k,c} x_{i', j+b, k+c},
+//   v_{i'} = sum_{b,c} (Ky_{j,b} Mz_{k,c} + My_{j,b} Kz_{k,c}) x_{i', j+b, k+c}.
+// The term of the row itself (b = c = 0) is split off: the rest comes from the
+// 2p(2p+2) neighbouring rows, which the class does not write, and is computed
+// once per row; the colour steps are then 1D Gauss-Seidel steps along the row
+// with the in-row coupling m00 Kx + g00 Mx (m00 = My_{j,0} Mz_{k,0},
+// g00 = Ky_{j,0} Mz_{k,0} + My_{j,0} Kz_{k,0}).  Per point: (2p+1)^2 - 1 loads
+// and about 2 (2p+1)^2 FMAs per sweep, against (2p+1)^3 of each per colour pass.
+
+constexpr int kRow3Threads = 1024;
+constexpr int kRow3MaxN = kRow3Threads;  // one lane per point of the row
+
+// u, v of column i of the row (j, k); without the row's own term unless kSelf.
+// Neighbour rows outside the grid have zero band entries: their addresses are
+// clamped and the loads stay unconditional.  kAhead: every load issued before
+// the first product (x in memory); else plane by plane (x in LDS, where the
+// registers of 48 values in flight cost more than the latency they hide).
+template <class Op, bool kSelf, bool kAhead = true>
+__device__ __forceinline__ void row3_contract(const Op& A, const typename Op::T* __restrict__ x, int j, int k,
+                                              int i, typename Op::T& u, typename Op::T& v) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W, WA = kAhead ? W : 1;
+    const int n = A.n;
+    const size_t nn = (size_t)n * n;
+    T xv[WA][W];
+    auto load_plane = [&](int c, T (&q)[W]) {
+        const T* xs = x + (size_t)clampi(k + c - P, 0, n - 1) * nn + i;
+#pragma unroll
+        for (int b = 0; b < W; ++b)
+            q[b] = (!kSelf && b == P && c == P) ? (T)0 : xs[(size_t)clampi(j + b - P, 0, n - 1) * n];
+    };
+    if constexpr (kAhead) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) load_plane(c, xv[c]);
+    }
+    u = 0;
+    v = 0;
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        T(&q)[W] = xv[kAhead ? c : 0];
+        if constexpr (!kAhead) load_plane(c, q);
+        T sm = 0, sk = 0;
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            if (!kSelf && b == P && c == P) continue;
+            sm = fma(A.M[(size_t)j * W + b], q[b], sm);
+            sk = fma(A.K[(size_t)j * W + b], q[b], sk);
+        }
+        const T mz = A.M[(size_t)k * W + c], kz = A.K[(size_t)k * W + c];
+        u = fma(mz, sm, u);
+        v = fma(kz, sm, fma(mz, sk, v));
+    }
+}
+
+// LDS bytes of the row kernels: u, v (and the row's iterate) with p zeros on
+// either side.
+__host__ __device__ constexpr int row3_lds_bytes(int p, int n, int arrays, int elem) {
+    return arrays * (n + 2 * p) * elem;
+}
+
+template <class Op>
+__global__ void __launch_bounds__(kRow3Threads) k_gs_rowclass3(Op A, const typename Op::T* __restrict__ b,
+                                                               typename Op::T* __restrict__ x, int cj, int ck) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W;
+    extern __shared__ __align__(16) unsigned char row3_lds[];
+    const int n = A.n, L = n + 2 * P;
+    T* su = (T*)row3_lds;
+    T* sv = su + L;
+    T* sx = sv + L;
+    const int nj = (n - cj + P) / (P + 1);
+    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int kq = blk / nj, jq = blk - kq * nj;
+    const int j = cj + (P + 1) * jq, k = ck + (P + 1) * kq;
+    const int t = threadIdx.x, i = min(t, n - 1);
+    const size_t row = ((size_t)k * n + j) * n;
+    const T xo = x[row + i], bo = b[row + i];
+    T kx[W], mx[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        kx[a] = A.K[(size_t)i * W + a];
+        mx[a] = A.M[(size_t)i * W + a];
+    }
+    T u, v;
+    row3_contract<Op, false>(A, x, j, k, i, u, v);
+    if (t < n) {
+        su[t + P] = u;
+        sv[t + P] = v;
+        sx[t + P] = xo;
+    } else if (t < n + P) {  // right pads
+        su[t + P] = 0;
+        sv[t + P] = 0;
+        sx[t + P] = 0;
+    }
+    if (t < P) {
+        su[t] = 0;
+        sv[t] = 0;
+        sx[t] = 0;
+    }
+    __syncthreads();
+    const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
+    const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
+    const T m00 = mj * mk, g00 = fma(kj, mk, mj * kk);
+    T rest = 0, cr[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        if (t < n) {
+            rest = fma(kx[a], su[t + a], rest);
+            rest = fma(mx[a], sv[t + a], rest);
+        }
+        cr[a] = fma(m00, kx[a], g00 * mx[a]);
+    }
+    const int s_own = t % (P + 1);
+#pragma unroll
+    for (int s = 0; s <= P; ++s) {
+        if (t < n && s_own == s) {
+            T acc = rest;
+#pragma unroll
+            for (int a = 0; a < W; ++a) acc = fma(cr[a], sx[t + a], acc);
+            sx[t + P] = sx[t + P] + (bo - acc) / cr[P];
+        }
+        if (s < P) __syncthreads();
+    }
+    if (t < n) x[row + t] = sx[t + P];
+}
+
+// Residual-type products of a sum-factorised 3D operator, one workgroup per
+// x-row (natural order): r = b - A x (mode 0), y = A x (mode 1), damped
+// Jacobi step (mode 2).
+template <class Op, typename Tout>
+__global__ void __launch_bounds__(kRow3Threads) k_residual_row3(Op A, const typename Op::T* __restrict__ b,
+                                                                const typename Op::T* __restrict__ x,
+                                                                Tout* __restrict__ out, int mode, double omega) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W;
+    extern __shared__ __align__(16) unsigned char row3_lds[];
+    const int n = A.n, L = n + 2 * P;
+    T* su = (T*)row3_lds;
+    T* sv = su + L;
+    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int k = blk / n, j = blk - k * n;
+    const int t = threadIdx.x, i = min(t, n - 1);
+    const size_t row = ((size_t)k * n + j) * n;
+    T bo = 0, xo = 0;
+    if (mode != 1) bo = b[row + i];
+    if (mode == 2) xo = x[row + i];
+    T kx[W], mx[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        kx[a] = A.K[(size_t)i * W + a];
+        mx[a] = A.M[(size_t)i * W + a];
+    }
+    T u, v;
+    row3_contract<Op, true>(A, x, j, k, i, u, v);
+    if (t < n) {
+        su[t + P] = u;
+        sv[t + P] = v;
+    } else if (t < n + P) {
+        su[t + P] = 0;
+        sv[t + P] = 0;
+    }
+    if (t < P) {
+        su[t] = 0;
+        sv[t] = 0;
+    }
+    __syncthreads();
+    if (t >= n) return;
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        acc = fma(kx[a], su[t + a], acc);
+        acc = fma(mx[a], sv[t + a], acc);
+    }
+    T r;
+    if (mode == 0)
+        r = bo - acc;
+    else if (mode == 1)
+        r = acc;
+    else {
+        const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
+        const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
+        const T d = fma(mj * mk, kx[P], fma(kj, mk, mj * kk) * mx[P]);
+        r = xo + (T)omega * (bo - acc) / d;
+    }
+    out[row + t] = (Tout)r;
+}
+
 template <class Op, typename Tout>
 __device__ __forceinline__ void residual_body(const Op& A, const typename Op::T* __restrict__ b,
                                               const typename Op::T* __restrict__ x,
@@ -1179,8 +1378,6 @@ constexpr int tail_threads() {
 __host__ __device__ constexpr int rec_len(int p) { return ((2 * p + 1) * (2 * p + 1) + 3) / 4 * 4; }
 constexpr int kTailLdsX = 153600;    // LDS bytes for the iterates of levels 0..top
 constexpr int kTailPadVals = 16;     // zero values after the last level (unclamped row reads)
-// slice partials and diagonals of the sliced 3D pass, at the end of the LDS store
-constexpr int kTailPartVals = kTailThreads + kTailThreads / 3 + 1;
 
 // Padded LDS layout of a level's iterate for stored 2D stencils: rows
 // j = -p .. n-1+p and, per row, a left pad of padl >= p columns (a multiple of
@@ -1263,9 +1460,9 @@ __device__ __forceinline__ void mu_schedule(int top, int mu, Down down, Coarse c
     }
 }
 
-// (A x)_I for one point of a sum-factorised operator: the bands of the point
-// are loaded once, the slices are summed in slice order (as the multi-block
-// kernels sum them); diag receives A_II.
+// (A x)_I for one point of a sum-factorised 2D operator: the bands of the
+// point are loaded once, the slices are summed in slice order (as the
+// multi-block kernels sum them); diag receives A_II.
 template <class Op>
 __device__ __forceinline__ typename Op::T tail_row(const Op& A, const typename Op::T* x,
                                                    const typename Op::Pt& pt, typename Op::T& diag) {
@@ -1273,60 +1470,21 @@ __device__ __forceinline__ typename Op::T tail_row(const Op& A, const typename O
     typename Op::Bands B;
     A.bands(pt, B);
     T acc = 0;
-    if constexpr (std::is_same<typename Op::Pt, Pt3>::value) {
-#pragma unroll 1
-        for (int w = 0; w < Op::NW; ++w) acc += A.slice_b(B, x, pt, w, diag);
-    } else {
 #pragma unroll
-        for (int w = 0; w < Op::NW; ++w) acc += A.slice_b(B, x, pt, w, diag);
-    }
+    for (int w = 0; w < Op::NW; ++w) acc += A.slice_b(B, x, pt, w, diag);
     return acc;
 }
 
-// Passes over the points of colours c0..c1-1 of one level by the whole block,
-// one thread per point.  mode 0: Gauss-Seidel colours in turn,
+// Passes over the points of colours c0..c1-1 of one 2D level by the whole
+// block, one thread per point.  mode 0: Gauss-Seidel colours in turn,
 // x_I += (b_I - (A x)_I) / A_II, a barrier after each colour.  mode 1:
 // r = b - A x on every point of the colours (x unchanged, one barrier at the
 // end).  x lives in LDS; b, r and the coefficients in memory.
 template <class Op>
 __device__ void tail_pass(const Op& A, const typename Op::T* __restrict__ b, typename Op::T* x,
-                          typename Op::T* __restrict__ r, int c0, int c1, int mode, typename Op::T* part) {
+                          typename Op::T* __restrict__ r, int c0, int c1, int mode) {
     using T = typename Op::T;
-    if constexpr (std::is_same<typename Op::Pt, Pt3>::value) {
-        // 3D: one lane per (point, slice), w fastest; the owner lane (w = 0)
-        // sums the point's slices in slice order after a barrier
-        constexpr int NW = Op::NW;
-        constexpr int PPG = kTailThreads / NW;  // points per group
-        for (int c = c0; c < c1; ++c) {
-            const int cs = A.colour_size(c);
-            for (int k0 = 0; k0 < cs; k0 += PPG) {
-                const int t = threadIdx.x, kk = t / NW, w = t - kk * NW, k = k0 + kk;
-                const bool act = kk < PPG && k < cs;
-                typename Op::Pt pt;
-                T bv = 0, d = 1;
-                if (act) {
-                    A.point(c, k, pt);
-                    if (w == 0) bv = b[pt.I];
-                    typename Op::Bands B;
-                    A.bands(pt, B);
-                    part[t] = A.slice_b(B, x, pt, w, d);
-                    if (w == NW / 2) part[kTailThreads + kk] = d;  // A_II from slice p
-                }
-                __syncthreads();
-                if (act && w == 0) {
-                    T acc = 0;
-#pragma unroll
-                    for (int v = 0; v < NW; ++v) acc += part[kk * NW + v];
-                    if (mode == 0)
-                        x[pt.I] = x[pt.I] + (bv - acc) / part[kTailThreads + kk];
-                    else
-                        r[pt.I] = bv - acc;
-                }
-                __syncthreads();
-            }
-        }
-        return;
-    }
+    static_assert(std::is_same<typename Op::Pt, Pt2>::value, "2D levels (3D levels: tail_rows3)");
     for (int c = c0; c < c1; ++c) {
         const int cs = A.colour_size(c);
         for (int k = threadIdx.x; k < cs; k += kTailThreads) {
@@ -1795,18 +1953,108 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
 
 // ---- sum-factorised operators: natural layout ------------------------------
 
+// ---- sum-factorised 3D levels in the single-workgroup kernel ---------------
+//
+// Row-class Gauss-Seidel as in k_gs_rowclass3 with x in LDS: one wave per
+// x-row of the class (n <= 64, one lane per point), the rows of a class spread
+// over the workgroup's waves.  A row's p+1 colour steps touch only its own
+// row, so they are ordered by the wave's own LDS operations; each class ends
+// with one workgroup barrier.  The neighbours' u, v come from the other lanes
+// by cross-lane reads.  The arithmetic is that of the multi-block kernels
+// (same contraction, same summation order), so both give the same iterates.
+constexpr int kTail3MaxN = 64;
+
+// sum_a Kx_{i,a} u_{i+a} + Mx_{i,a} v_{i+a} for the lane's point; lanes
+// outside the row hold u = v = 0 and out-of-row offsets have zero band entries.
+template <int W, typename T>
+__device__ __forceinline__ T tail3_xproduct(const T (&kx)[W], const T (&mx)[W], T u, T v, int lane, T acc) {
+    constexpr int P = (W - 1) / 2;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        const int src = clampi(lane + a - P, 0, 63);
+        acc = fma(kx[a], __shfl(u, src, 64), acc);
+        acc = fma(mx[a], __shfl(v, src, 64), acc);
+    }
+    return acc;
+}
+
+// gs: one multicolour Gauss-Seidel sweep of the level in row classes; else
+// r = b - A x on every point (x unchanged).  Ends with a workgroup barrier.
+template <class Op>
+__device__ void tail_rows3(const Op& A, const typename Op::T* __restrict__ b, typename Op::T* x,
+                           typename Op::T* __restrict__ r, bool gs) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W, NWAVE = kTailThreads / 64;
+    const int n = A.n;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = min(lane, n - 1);
+    // the lane's x bands, read from LDS after each contraction (fewer live registers)
+    T kx[W], mx[W];
+    auto xbands = [&]() {
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            kx[a] = A.K[i * W + a];
+            mx[a] = A.M[i * W + a];
+        }
+    };
+    if (!gs) {
+        for (int row = wave; row < n * n; row += NWAVE) {
+            const int k = row / n, j = row - k * n;
+            T u, v;
+            row3_contract<Op, true, false>(A, x, j, k, i, u, v);
+            if (lane >= n) u = v = 0;
+            xbands();
+            const T acc = tail3_xproduct<W, T>(kx, mx, u, v, lane, (T)0);
+            if (lane < n) r[(size_t)row * n + lane] = b[(size_t)row * n + lane] - acc;
+        }
+        __syncthreads();
+        return;
+    }
+    const int s_own = lane % (P + 1);
+    for (int ck = 0; ck <= P; ++ck)
+        for (int cj = 0; cj <= P; ++cj) {
+            const int nj = (n - cj + P) / (P + 1), nk = (n - ck + P) / (P + 1);
+            for (int rr = wave; rr < nj * nk; rr += NWAVE) {
+                const int kq = rr / nj, jq = rr - kq * nj;
+                const int j = cj + (P + 1) * jq, k = ck + (P + 1) * kq;
+                T* xr = x + ((size_t)k * n + j) * n;
+                const T bo = b[((size_t)k * n + j) * n + i];
+                T u, v;
+                row3_contract<Op, false, false>(A, x, j, k, i, u, v);
+                if (lane >= n) u = v = 0;
+                const T mj = A.M[j * W + P], kj = A.K[j * W + P];
+                const T mk = A.M[k * W + P], kk = A.K[k * W + P];
+                const T m00 = mj * mk, g00 = fma(kj, mk, mj * kk);
+                xbands();
+                const T rest = tail3_xproduct<W, T>(kx, mx, u, v, lane, (T)0);
+                T cr[W];
+#pragma unroll
+                for (int a = 0; a < W; ++a) cr[a] = fma(m00, kx[a], g00 * mx[a]);
+#pragma unroll
+                for (int s = 0; s <= P; ++s) {
+                    if (lane < n && s_own == s) {
+                        T acc = rest;
+#pragma unroll
+                        for (int a = 0; a < W; ++a) acc = fma(cr[a], xr[clampi(lane + a - P, 0, n - 1)], acc);
+                        xr[lane] = xr[lane] + (bo - acc) / cr[P];
+                    }
+                    pf_sync<true>();
+                }
+            }
+            __syncthreads();
+        }
+}
+
 // mu-cycle (Algorithm 2) on levels 0..top with right-hand side b[top] and
 // iterate x[top] (in place), by one workgroup.  LDS holds, level by
 // level, the 1D bands K and M (levels >= 1, at boff) and the iterate (at
-// xoff), then kTailPadVals zeros, and at its end kTailPartVals values for
-// the sliced 3D pass; the host checks that this fits.
+// xoff), then kTailPadVals zeros; the host checks that this fits.  3D
+// levels (at most kTail3MaxN unknowns per direction) sweep in row classes.
 template <class Op>
 __device__ void gt_vcycle(const TailArgs<Op>& a) {
     using T = typename Op::T;
     constexpr int DIM = std::is_same<typename Op::Pt, Pt3>::value ? 3 : 2;
     constexpr int P = Op::kP, W = Op::W;
     __shared__ T xs[tail_capacity<T>()];
-    T* part = xs + tail_capacity<T>() - kTailPartVals;
     const int top = a.top;
     for (int l = 1; l <= top; ++l) {
         const int nw = a.op[l].n * W;
@@ -1833,9 +2081,14 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
     auto down = [&](int l) {
         const Op A = lop(l);
         T* xl = xs + a.xoff[l];
-        for (int s = 0; s < a.nu1; ++s)
-            for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0, part);
-        tail_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1, part);
+        if constexpr (DIM == 3) {
+            for (int s = 0; s < a.nu1; ++s) tail_rows3(A, a.b[l], xl, a.r[l], true);
+            tail_rows3(A, a.b[l], xl, a.r[l], false);
+        } else {
+            for (int s = 0; s < a.nu1; ++s)
+                for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0);
+            tail_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1);
+        }
         tail_restrict<P, DIM, T>(a.r[l], A.n, a.b[l - 1], xs + a.xoff[l - 1], a.op[l - 1].n, a.rs[l],
                                  a.rw[l], a.RW[l]);
         __syncthreads();
@@ -1856,8 +2109,12 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
         T* xl = xs + a.xoff[l];
         tail_prolong<P, DIM, T>(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l]);
         __syncthreads();
-        for (int s = 0; s < a.nu2; ++s)
-            for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0, part);
+        for (int s = 0; s < a.nu2; ++s) {
+            if constexpr (DIM == 3)
+                tail_rows3(A, a.b[l], xl, a.r[l], true);
+            else
+                for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0);
+        }
     };
     mu_schedule(top, a.mu, down, coarse, up);
     {

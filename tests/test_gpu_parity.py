@@ -391,3 +391,65 @@ def test_row_class_sweeps_equal_colour_passes(geom, n_el, p, extra, prec):
         out.append(host(x))
         s.close()
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("n_el,p", [(16, 1), (32, 1), (16, 2), (32, 2), (16, 3), (32, 3)])
+def test_cube_row_class_sweeps_and_products(n_el, p):
+    """Sum-factorised cube levels: the row-class sweep (one launch per row class
+    (j, k mod p+1), each row's product factored through the y and z bands) and
+    the one-workgroup-per-row products (A x, damped Jacobi) equal the oracle's
+    multicolour sweeps, A x and Jacobi steps on every level (1e-13), as do the
+    per-colour kernels; the two GPU forms sum in different orders and agree to
+    the same bar.  With n = n_el + p unknowns per direction most levels leave
+    ragged row classes (n not a multiple of p + 1)."""
+    H = mg.build_hierarchy("cube", n_el, p)
+    got = {}
+    for rows in (0, 1):
+        print("[cube rows] n_el=%d p=%d rows=%d" % (n_el, p, rows), flush=True)
+        s = igamg.Solver(igamg.UNIT_CUBE, n_el, p, tail_items=0, row_sweeps=rows)
+        sj = igamg.Solver(igamg.UNIT_CUBE, n_el, p, tail_items=0, row_sweeps=rows,
+                          smoother=igamg.SMOOTH_JACOBI)
+        for l in range(1, len(H.levels)):
+            lev = H.levels[l]
+            N = lev.A.shape[0]
+            bl = synth.random_vector(N, 140 + l)
+            x0 = synth.random_vector(N, 150 + l)
+            xg = dev(x0)
+            s.smooth(l, dev(bl), xg, 2)
+            xr = mg.smooth(lev, bl, x0.copy(), mg.SMOOTH_MCGS, 2)
+            assert rel(host(xg), xr) < 1e-13, (rows, l)
+            y = torch.zeros(N, dtype=torch.float64, device=DEV)
+            s.apply(l, dev(x0), y)
+            assert rel(host(y), lev.A @ x0) < 1e-13, (rows, l)
+            xj = dev(x0)
+            sj.smooth(l, dev(bl), xj, 2)
+            assert rel(host(xj), mg.smooth(lev, bl, x0.copy(), mg.SMOOTH_JACOBI, 2)) < 1e-13, (rows, l)
+            got[rows, l] = (host(xg), host(y), host(xj))
+        s.close()
+        sj.close()
+    for l in range(1, len(H.levels)):
+        for a, b in zip(got[0, l], got[1, l]):
+            assert rel(b, a) < 1e-13, l
+
+
+@pytest.mark.parametrize("n_el,p", [(16, 1), (16, 2), (16, 3), (32, 3)])
+@pytest.mark.parametrize("prec", [igamg.FP64, igamg.FP32_IR])
+@pytest.mark.parametrize("mu", [1, 2])
+def test_cube_tail_equals_multiblock_bitwise(n_el, p, prec, mu):
+    """Cube levels in the single-workgroup kernel sweep in row classes with the
+    arithmetic of the multi-block row-class kernels (same contraction and
+    summation order; the same transfers and coarse solve), so V- and W-cycle
+    iterates with the small levels in one workgroup equal, bit for bit, those
+    with every level multi-block."""
+    out = []
+    for tail in (0, 512):
+        print("[cube tail] n_el=%d p=%d prec=%d mu=%d tail=%d" % (n_el, p, prec, mu, tail), flush=True)
+        s = igamg.Solver(igamg.UNIT_CUBE, n_el, p, tail_items=tail, precision=prec, mu=mu)
+        s.set_rhs_field(modes_for("cube", 2000 + p))
+        assert (s.tuning()["tail_top"] >= 2) == (tail > 0)
+        x = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+        for _ in range(3):
+            s.vcycle(x)
+        out.append(host(x))
+        s.close()
+    assert np.array_equal(out[0], out[1])
