@@ -350,7 +350,7 @@ def elliptic_measure(igamg, torch, steps):
     return out
 
 
-def c3_measure(igamg, torch, synth, steps, forms=None):
+def c3_measure(igamg, torch, synth, steps, forms=None, tuning=None):
     """Unit cube, p = 3, 128^3 elements, f = 3 pi^2 prod sin(pi x_d), V(2,2)
     multicolour GS (64 colours in 16 row classes): plain FP64 V-cycles, FP64
     MPE(4), and MPE(4) around FP32 V-cycles in FP64 refinement; launch shapes
@@ -366,7 +366,10 @@ def c3_measure(igamg, torch, synth, steps, forms=None):
             continue
         s.set_precision(prec)
         if prec not in tuned:
-            s.autotune()
+            if tuning is not None:  # launch shapes given (profiled runs)
+                s.set_tuning(tuning)
+            else:
+                s.autotune()
             tuned.add(prec)
             out["tuning"]["fp64" if prec == igamg.FP64 else "fp32"] = s.tuning()
         x = torch.zeros(s.ndof, dtype=torch.float64, device="cuda:0")
@@ -487,6 +490,9 @@ def main():
                     help="setup, tuning and training, then only the chosen-form solves (kernel profiles)")
     ap.add_argument("--only-cube", action="store_true",
                     help="only the 128^3 cube's FP32-in-FP64 MPE(4) solves, autotuned (kernel profiles)")
+    ap.add_argument("--cube-tuning", default=None,
+                    help="with --only-cube: launch shapes as JSON (tuning() of an unprofiled run) "
+                         "instead of autotuning")
     ap.add_argument("--only-1d", action="store_true",
                     help="only the 1D model problem leg (Tables 1 and 4), printed as its own JSON line")
     ap.add_argument("--epochs", type=int, default=10)
@@ -553,8 +559,15 @@ def main():
         return
 
     if args.only_cube:
-        c3, _ = c3_measure(igamg, torch, synth, args.steps, forms=("mpe4_ir",))
-        print(json.dumps({"only_cube": True, **c3}), flush=True)
+        c3, _ = c3_measure(igamg, torch, synth, args.steps, forms=("mpe4_ir",),
+                           tuning=json.loads(args.cube_tuning) if args.cube_tuning else None)
+        # a plain copy of known size (calibration of the traffic counters)
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        bcopy = torch.empty_like(a)
+        for _ in range(2):
+            bcopy.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"only_cube": True, "copy_bytes": 2 * a.numel() * 8, **c3}), flush=True)
         return
 
     if args.only_batch:

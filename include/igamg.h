@@ -336,7 +336,9 @@ igamg_status igamg_profile_smoother(igamg_ctx* ctx, int level, int precision, in
 /* Autotuner of the launch shapes, by timing on the device in the current
  * precision: (1) per level, row-class sweep launches (the p+1 colours of a row
  * class per launch, where the kernel applies: stored stencils, p <= 4) or one
- * launch per colour; (2) per level, the learned smoother's inference kernel
+ * launch per colour; on cubes row-class or plane-class launches (the (p+1)^2
+ * colours of a plane class per launch, levels of at most 64 unknowns per
+ * direction); (2) per level, the learned smoother's inference kernel
  * (the 16 x 16-tile VALU/MFMA kernel, or the all-MFMA kernel with 12 x 12 or
  * 28 x 28 tiles; timed with zero weights, whose values do not change the
  * time); (3) the split between multi-block levels and the single-workgroup
@@ -354,7 +356,9 @@ typedef struct {
     int tail_items;          /* the split threshold in use                      */
     int tail_top;            /* finest level of the single-workgroup kernel (0: none) */
     int num_levels;          /* levels of the hierarchy (<= 16)                 */
-    int row_class[16];       /* per level: 1 row-class sweep launches, 0 one per colour */
+    int row_class[16];       /* per level: 1 row-class sweep launches, 0 one per colour;
+                                cubes: 2 one launch per plane class (planes
+                                k = ck mod p+1, one workgroup per plane)      */
     int learned_kernel[16];  /* per level: 0 16x16-tile VALU/MFMA kernel; 12, 28 all-MFMA
                                 kernel with that tile (28: 512 threads); 29 tile 28
                                 with 256 threads                               */
@@ -362,8 +366,9 @@ typedef struct {
 } igamg_tuning;
 igamg_status igamg_get_tuning(const igamg_ctx* ctx, igamg_tuning* out);
 /* Sets the launch shapes (for instance a tuning saved by another process):
- * tail_items >= 0, row_class 0 or 1 (1 takes effect where row-class sweeps
- * apply), learned_kernel one of 0, 12, 28, 29; num_levels must match;
+ * tail_items >= 0, row_class 0 or 1 (cubes: 0, 1 or 2; each takes effect
+ * where its sweep applies, else the next lower one), learned_kernel one of
+ * 0, 12, 28, 29; num_levels must match;
  * tail_top and vcycle_ms are ignored.  EINVAL on a bad field. */
 igamg_status igamg_set_tuning(igamg_ctx* ctx, const igamg_tuning* in);
 

@@ -294,27 +294,30 @@ struct igamg_ctx {
         }
     }
 
+    // Per-block sums written by residual(): one per 64-point block, or per
+    // x-row on the 3D levels of the row kernels.
     long long residual_blocks(int l) const {
         const Level& v = lv[l];
         if (kind == OP_STENCIL2D) return (long long)v.ncol * (v.ncp / 64);
+        if (row3_available(l)) return (long long)v.n * v.n;
         return (v.N + 63) / 64;
     }
 
     // out = b - A x (mode 0), A x (mode 1), Jacobi step (mode 2), z = D^{-1}(b - A x)
     // as float with per-block sums of z^2 in part (mode 3)
-    // (sum-factorised 3D levels: one workgroup per x-row where no per-block
-    // sums are asked for)
+    // (sum-factorised 3D levels: one workgroup per x-row, modes 0-2)
     template <typename T, typename Tout>
     void residual(int l, const T* bb, const T* x, Tout* out, int mode, double* part) {
-        long long nb = residual_blocks(l);
+        const long long nb = residual_blocks(l);
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
             if constexpr (!Op::kColourOrder && std::is_same_v<typename Op::Pt, Pt3>) {
-                if (!part && mode <= 2 && row3_available(l)) {
+                if (row3_available(l)) {
+                    if (mode > 2) throw Error(IGAMG_EINVAL, "residual mode 3 needs a 2D level");
                     const int n = lv[l].n;
-                    hipLaunchKernelGGL((k_residual_row3<Op, Tout>), dim3((unsigned)((long long)n * n)),
-                                       dim3(((n + 63) / 64) * 64), row3_lds_bytes(p, n, 2, sizeof(T)), stream, op,
-                                       bb, x, out, mode, opt.omega);
+                    hipLaunchKernelGGL((k_residual_row3<Op, Tout>), dim3((unsigned)nb), dim3(((n + 63) / 64) * 64),
+                                       row3_lds_bytes(p, n, 2, sizeof(T)), stream, op, bb, x, out, mode,
+                                       opt.omega, part);
                     return;
                 }
             }
@@ -361,6 +364,18 @@ struct igamg_ctx {
     bool row_sweeps(int l) const {
         return row_sweeps_available(l) && (l >= (int)row_pref.size() || row_pref[l] != 0);
     }
+    // Sweep launches of level l in use: 0 one per colour, 1 one per row
+    // class, 2 one per plane class (3D).
+    int sweep_shape(int l) const {
+        if (!row_sweeps(l)) return 0;
+        return (l < (int)row_pref.size() && row_pref[l] == 2 && plane3_available(l)) ? 2 : 1;
+    }
+    // Sum-factorised 3D levels whose planes (with the waves' row buffers) fit
+    // the plane-class kernel's LDS in FP64, one lane per point of a row.
+    bool plane3_available(int l) const {
+        return row3_available(l) && lv[l].n <= kPlane3MaxN &&
+               plane3_lds_bytes(p, lv[l].n, sizeof(double)) <= kPlane3MaxLds;
+    }
     bool row_sweeps_available(int l) const {
         if (kind == OP_KRON3D) return row3_available(l);
         return opt.row_sweeps && kind == OP_STENCIL2D && p <= 4 && row_fits(p, lv[l].n) &&
@@ -388,6 +403,21 @@ struct igamg_ctx {
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
             if constexpr (!Op::kColourOrder && std::is_same_v<typename Op::Pt, Pt3>) {
+                if (sweep_shape(l) == 2) {
+                    const int P1 = p + 1;
+                    const size_t lds = plane3_lds_bytes(p, v.n, sizeof(T));
+                    const int th = 64 * plane3_waves(p, v.n);
+                    for (int ck = 0; ck < P1; ++ck) {
+                        const int nk = (v.n - ck + p) / P1;
+                        if (nk <= 0) continue;
+                        hipLaunchKernelGGL((k_gs_planeclass3<Op>), dim3(nk), dim3(th), lds, stream, op, bb, x, ck);
+                        ++launches;
+                        if (bytes)
+                            for (int c = P1 * P1 * ck; c < P1 * P1 * (ck + 1); ++c)
+                                *bytes += colour_size_host(v.n, p, dim, c) * per_point;
+                    }
+                    return;
+                }
                 if (row_sweeps(l)) {
                     const int P1 = p + 1;
                     const size_t lds = row3_lds_bytes(p, v.n, 3, sizeof(T));
@@ -486,6 +516,8 @@ struct igamg_ctx {
     // on the 1024^2 annulus hierarchy, p = 3).
     void default_shapes() {
         row_pref.assign(L + 1, 1);
+        for (int l = 0; l <= L; ++l)
+            if (plane3_available(l)) row_pref[l] = 2;
         learned_kern.assign(L + 1, 12);
         for (int l = 0; l <= L; ++l)
             if (lv[l].n >= 384) learned_kern[l] = 28;
@@ -1593,15 +1625,22 @@ void igamg_ctx::autotune(int* best_items, double* best_ms, bool tune_learned) {
             fill(v.x<T>(), v.N);
             hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(v.N)), dim3(kBlock), 0, stream, v.b<T>(), (T)1, v.N);
             check_launch();
-            double t[2] = {1e300, 1e300};
+            // 2D: one launch per colour or per row class (the same iterates);
+            // 3D: per row class or per plane class (the same iterates; one
+            // launch per colour sums in another order and is not a candidate)
+            const int lo = (kind == OP_KRON3D) ? 1 : 0, hi = plane3_available(l) ? 2 : 1;
+            double t[3] = {1e300, 1e300, 1e300};
             for (int trial = 0; trial < 2; ++trial)
-                for (int pref = 0; pref < 2; ++pref) {
+                for (int pref = lo; pref <= hi; ++pref) {
                     row_pref[l] = pref;
                     t[pref] = std::min(t[pref], timed([&] {
                         for (int k = 0; k < 4; ++k) mc_sweep<T>(l, v.b<T>(), v.x<T>());
                     }));
                 }
-            row_pref[l] = t[1] <= t[0] ? 1 : 0;
+            int best = hi;
+            for (int pref = hi - 1; pref >= lo; --pref)
+                if (t[pref] < t[best]) best = pref;
+            row_pref[l] = best;
         }
     };
     if (opt.precision == IGAMG_FP64)
@@ -3058,7 +3097,7 @@ igamg_status igamg_get_tuning(const igamg_ctx* ctx, igamg_tuning* out) {
         out->tail_top = ctx->tail_top;
         out->num_levels = ctx->L + 1;
         for (int l = 0; l <= ctx->L; ++l) {
-            out->row_class[l] = ctx->row_sweeps(l) ? 1 : 0;
+            out->row_class[l] = ctx->sweep_shape(l);
             out->learned_kernel[l] = ctx->learned_kern[l];
         }
         out->vcycle_ms = ctx->tuned_ms;
@@ -3071,7 +3110,8 @@ igamg_status igamg_set_tuning(igamg_ctx* ctx, const igamg_tuning* in) {
         need(in->num_levels == ctx->L + 1, "num_levels does not match the hierarchy");
         need(in->tail_items >= 0, "tail_items must be >= 0");
         for (int l = 0; l <= ctx->L; ++l) {
-            need(in->row_class[l] == 0 || in->row_class[l] == 1, "row_class must be 0 or 1");
+            need(in->row_class[l] >= 0 && in->row_class[l] <= (ctx->kind == OP_KRON3D ? 2 : 1),
+                 "row_class must be 0 or 1 (cubes: 0, 1 or 2)");
             const int k = in->learned_kernel[l];
             need(k == 0 || k == 12 || k == 28 || k == 29, "learned_kernel must be 0, 12, 28 or 29");
         }

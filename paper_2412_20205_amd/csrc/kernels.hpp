@@ -32,6 +32,19 @@ __device__ __forceinline__ int xcd_swizzle(int bid, int nblk) {
     return (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
+// Ordering point between two colour steps.  Several waves: a workgroup
+// barrier.  One wave (kSolo: the values a step reads were written by the same
+// wave): its LDS operations run in issue order, so waiting for its own
+// outstanding LDS operations, with the compiler kept from moving memory
+// accesses across the point, orders the updates without a workgroup barrier.
+template <bool kSolo>
+__device__ __forceinline__ void pf_sync() {
+    if constexpr (kSolo)
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    else
+        __syncthreads();
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) {
     return v < lo ? lo : (v > hi ? hi : v);
 }
@@ -641,15 +654,14 @@ __global__ void __launch_bounds__(kRow3Threads) k_gs_rowclass3(Op A, const typen
         su[t + P] = u;
         sv[t + P] = v;
         sx[t + P] = xo;
-    } else if (t < n + P) {  // right pads
-        su[t + P] = 0;
-        sv[t + P] = 0;
-        sx[t + P] = 0;
     }
-    if (t < P) {
+    if (t < P) {  // pads (threads t < P exist for every n; threads past n need not)
         su[t] = 0;
         sv[t] = 0;
         sx[t] = 0;
+        su[n + P + t] = 0;
+        sv[n + P + t] = 0;
+        sx[n + P + t] = 0;
     }
     __syncthreads();
     const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
@@ -678,16 +690,138 @@ __global__ void __launch_bounds__(kRow3Threads) k_gs_rowclass3(Op A, const typen
     if (t < n) x[row + t] = sx[t + P];
 }
 
-// Residual-type products of a sum-factorised 3D operator, one workgroup per
-// x-row (natural order): r = b - A x (mode 0), y = A x (mode 1), damped
-// Jacobi step (mode 2).
-template <class Op, typename Tout>
-__global__ void __launch_bounds__(kRow3Threads) k_residual_row3(Op A, const typename Op::T* __restrict__ b,
-                                                                const typename Op::T* __restrict__ x,
-                                                                Tout* __restrict__ out, int mode, double omega) {
+// ---- plane-class multicolour Gauss-Seidel (sum-factorised 3D operators) ----
+//
+// One launch per plane class ck: the planes k = ck (mod p+1) lie p+1 apart,
+// so one workgroup per plane sweeps the plane's (p+1)^2 colours (ci, cj, ck)
+// in colour order with the plane's iterate staged in LDS: the row classes cj
+// one after the other (a workgroup barrier each), the p+1 colour steps of a
+// row by one wave (ordered by the wave's own LDS operations).  The contraction
+// and the summation order are those of k_gs_rowclass3, so the iterates are the
+// same, from p+1 launches per sweep instead of (p+1)^2.  Levels of up to 64
+// unknowns per direction (one lane per point of a row): on larger levels the
+// planes of a class are too few workgroups to fill the GPU (a variant with
+// two points per lane at 65^3 took twice the time of the row-class launches).
+constexpr int kPlane3MaxN = 64;
+constexpr int kPlane3MaxLds = 65536;  // dynamic LDS bytes without a launch attribute
+// Waves per workgroup: one per row of a class, at most 16.
+__host__ __device__ constexpr int plane3_waves(int p, int n) {
+    return (n + p) / (p + 1) < 16 ? (n + p) / (p + 1) : 16;
+}
+__host__ __device__ constexpr long long plane3_lds_bytes(int p, int n, int elem) {
+    return ((long long)n * n + 2LL * plane3_waves(p, n) * (n + 2 * p)) * elem;
+}
+
+// row3_contract<Op, false> with the plane k (c = 0) read from the LDS copy xp.
+template <class Op>
+__device__ __forceinline__ void plane3_contract(const Op& A, const typename Op::T* __restrict__ x,
+                                                const typename Op::T* xp, int j, int k, int i,
+                                                typename Op::T& u, typename Op::T& v) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W;
+    const int n = A.n;
+    const size_t nn = (size_t)n * n;
+    T xv[W][W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        const T* xs = (c == P) ? xp + i : x + (size_t)clampi(k + c - P, 0, n - 1) * nn + i;
+#pragma unroll
+        for (int b = 0; b < W; ++b)
+            xv[c][b] = (b == P && c == P) ? (T)0 : xs[(size_t)clampi(j + b - P, 0, n - 1) * n];
+    }
+    u = 0;
+    v = 0;
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        T sm = 0, sk = 0;
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            if (b == P && c == P) continue;
+            sm = fma(A.M[(size_t)j * W + b], xv[c][b], sm);
+            sk = fma(A.K[(size_t)j * W + b], xv[c][b], sk);
+        }
+        const T mz = A.M[(size_t)k * W + c], kz = A.K[(size_t)k * W + c];
+        u = fma(mz, sm, u);
+        v = fma(kz, sm, fma(mz, sk, v));
+    }
+}
+
+template <class Op>
+__global__ void __launch_bounds__(1024) k_gs_planeclass3(Op A, const typename Op::T* __restrict__ b,
+                                                         typename Op::T* __restrict__ x, int ck) {
     using T = typename Op::T;
     constexpr int P = Op::kP, W = Op::W;
     extern __shared__ __align__(16) unsigned char row3_lds[];
+    const int n = A.n, L = n + 2 * P, nwave = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = min(lane, n - 1);
+    const size_t nn = (size_t)n * n;
+    T* xp = (T*)row3_lds;
+    T* su = xp + nn + (size_t)wave * 2 * L;
+    T* sv = su + L;
+    const int k = ck + (P + 1) * xcd_swizzle(blockIdx.x, gridDim.x);
+    T* xg = x + (size_t)k * nn;
+    for (int e = threadIdx.x; e < (int)nn; e += blockDim.x) xp[e] = xg[e];
+    if (lane < P) {
+        su[lane] = 0;
+        sv[lane] = 0;
+        su[n + P + lane] = 0;
+        sv[n + P + lane] = 0;
+    }
+    __syncthreads();
+    const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
+    const int s_own = lane % (P + 1);
+    for (int cj = 0; cj <= P; ++cj) {
+        const int nj = (n - cj + P) / (P + 1);
+        for (int jq = wave; jq < nj; jq += nwave) {
+            const int j = cj + (P + 1) * jq;
+            T* xr = xp + (size_t)j * n;
+            T u, v;
+            plane3_contract<Op>(A, x, xp, j, k, i, u, v);
+            if (lane < n) {
+                su[lane + P] = u;
+                sv[lane + P] = v;
+            }
+            pf_sync<true>();
+            const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
+            const T m00 = mj * mk, g00 = fma(kj, mk, mj * kk);
+            const T bo = b[(size_t)k * nn + (size_t)j * n + i];
+            T rest = 0, cr[W];
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                const T kx = A.K[(size_t)i * W + a], mx = A.M[(size_t)i * W + a];
+                rest = fma(kx, su[i + a], rest);
+                rest = fma(mx, sv[i + a], rest);
+                cr[a] = fma(m00, kx, g00 * mx);
+            }
+#pragma unroll
+            for (int s = 0; s <= P; ++s) {
+                if (lane < n && s_own == s) {
+                    T acc = rest;
+#pragma unroll
+                    for (int a = 0; a < W; ++a) acc = fma(cr[a], xr[clampi(lane + a - P, 0, n - 1)], acc);
+                    xr[lane] = xr[lane] + (bo - acc) / cr[P];
+                }
+                pf_sync<true>();
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < (int)nn; e += blockDim.x) xg[e] = xp[e];
+}
+
+// Residual-type products of a sum-factorised 3D operator, one workgroup per
+// x-row (natural order): r = b - A x (mode 0), y = A x (mode 1), damped
+// Jacobi step (mode 2); optionally the row's sum of squares of the output in
+// partial[row] (fixed reduction order).
+template <class Op, typename Tout>
+__global__ void __launch_bounds__(kRow3Threads) k_residual_row3(Op A, const typename Op::T* __restrict__ b,
+                                                                const typename Op::T* __restrict__ x,
+                                                                Tout* __restrict__ out, int mode, double omega,
+                                                                double* __restrict__ partial) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W;
+    extern __shared__ __align__(16) unsigned char row3_lds[];
+    __shared__ double red[kRow3Threads / 64];
     const int n = A.n, L = n + 2 * P;
     T* su = (T*)row3_lds;
     T* sv = su + L;
@@ -709,34 +843,40 @@ __global__ void __launch_bounds__(kRow3Threads) k_residual_row3(Op A, const type
     if (t < n) {
         su[t + P] = u;
         sv[t + P] = v;
-    } else if (t < n + P) {
-        su[t + P] = 0;
-        sv[t + P] = 0;
     }
-    if (t < P) {
+    if (t < P) {  // pads
         su[t] = 0;
         sv[t] = 0;
+        su[n + P + t] = 0;
+        sv[n + P + t] = 0;
     }
     __syncthreads();
-    if (t >= n) return;
-    T acc = 0;
+    double sq = 0.0;
+    if (t < n) {
+        T acc = 0;
 #pragma unroll
-    for (int a = 0; a < W; ++a) {
-        acc = fma(kx[a], su[t + a], acc);
-        acc = fma(mx[a], sv[t + a], acc);
+        for (int a = 0; a < W; ++a) {
+            acc = fma(kx[a], su[t + a], acc);
+            acc = fma(mx[a], sv[t + a], acc);
+        }
+        T r;
+        if (mode == 0)
+            r = bo - acc;
+        else if (mode == 1)
+            r = acc;
+        else {
+            const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
+            const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
+            const T d = fma(mj * mk, kx[P], fma(kj, mk, mj * kk) * mx[P]);
+            r = xo + (T)omega * (bo - acc) / d;
+        }
+        out[row + t] = (Tout)r;
+        sq = (double)r * (double)r;
     }
-    T r;
-    if (mode == 0)
-        r = bo - acc;
-    else if (mode == 1)
-        r = acc;
-    else {
-        const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
-        const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
-        const T d = fma(mj * mk, kx[P], fma(kj, mk, mj * kk) * mx[P]);
-        r = xo + (T)omega * (bo - acc) / d;
+    if (partial) {
+        const double tot = block_sum(sq, red);
+        if (t == 0) partial[blk] = tot;
     }
-    out[row + t] = (Tout)r;
 }
 
 template <class Op, typename Tout>
@@ -1806,19 +1946,6 @@ constexpr int pf_group() {
     int u = P + 1;
     while (u % R != 0) u += P + 1;
     return u;
-}
-
-// Ordering point between two colour steps.  Several waves: a workgroup
-// barrier.  One wave (kSolo: every point of every colour in wave 0): its LDS
-// operations run in issue order, so waiting for its own outstanding LDS
-// operations, with the compiler kept from moving memory accesses across the
-// point, orders the updates without a workgroup barrier.
-template <bool kSolo>
-__device__ __forceinline__ void pf_sync() {
-    if constexpr (kSolo)
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    else
-        __syncthreads();
 }
 
 template <int P, bool kSolo, int U = 0>

@@ -393,43 +393,84 @@ def test_row_class_sweeps_equal_colour_passes(geom, n_el, p, extra, prec):
     assert np.array_equal(out[0], out[1])
 
 
+def _with_shape(s, shape):
+    """Sets every level's sweep launch shape (0 per colour, 1 per row class,
+    2 per plane class where it applies) and the multi-block split 0."""
+    t = s.tuning()
+    t["tail_items"] = 0
+    t["row_class"] = [shape] * t["num_levels"]
+    s.set_tuning(t)
+    return s.tuning()["row_class"]
+
+
 @pytest.mark.parametrize("n_el,p", [(16, 1), (32, 1), (16, 2), (32, 2), (16, 3), (32, 3)])
 def test_cube_row_class_sweeps_and_products(n_el, p):
     """Sum-factorised cube levels: the row-class sweep (one launch per row class
-    (j, k mod p+1), each row's product factored through the y and z bands) and
+    (j, k mod p+1), each row's product factored through the y and z bands), the
+    plane-class sweep (one launch per plane class, one workgroup per plane) and
     the one-workgroup-per-row products (A x, damped Jacobi) equal the oracle's
     multicolour sweeps, A x and Jacobi steps on every level (1e-13), as do the
-    per-colour kernels; the two GPU forms sum in different orders and agree to
-    the same bar.  With n = n_el + p unknowns per direction most levels leave
-    ragged row classes (n not a multiple of p + 1)."""
+    per-colour kernels.  Row- and plane-class sweeps are equal bit for bit; the
+    per-colour kernels sum in another order and agree with them to the same
+    bar.  With n = n_el + p - 2 unknowns per direction most levels leave ragged
+    classes (n not a multiple of p + 1)."""
     H = mg.build_hierarchy("cube", n_el, p)
     got = {}
     for rows in (0, 1):
-        print("[cube rows] n_el=%d p=%d rows=%d" % (n_el, p, rows), flush=True)
         s = igamg.Solver(igamg.UNIT_CUBE, n_el, p, tail_items=0, row_sweeps=rows)
         sj = igamg.Solver(igamg.UNIT_CUBE, n_el, p, tail_items=0, row_sweeps=rows,
                           smoother=igamg.SMOOTH_JACOBI)
-        for l in range(1, len(H.levels)):
-            lev = H.levels[l]
-            N = lev.A.shape[0]
-            bl = synth.random_vector(N, 140 + l)
-            x0 = synth.random_vector(N, 150 + l)
-            xg = dev(x0)
-            s.smooth(l, dev(bl), xg, 2)
-            xr = mg.smooth(lev, bl, x0.copy(), mg.SMOOTH_MCGS, 2)
-            assert rel(host(xg), xr) < 1e-13, (rows, l)
-            y = torch.zeros(N, dtype=torch.float64, device=DEV)
-            s.apply(l, dev(x0), y)
-            assert rel(host(y), lev.A @ x0) < 1e-13, (rows, l)
-            xj = dev(x0)
-            sj.smooth(l, dev(bl), xj, 2)
-            assert rel(host(xj), mg.smooth(lev, bl, x0.copy(), mg.SMOOTH_JACOBI, 2)) < 1e-13, (rows, l)
-            got[rows, l] = (host(xg), host(y), host(xj))
+        for shape in ((0,) if rows == 0 else (1, 2)):
+            print("[cube shapes] n_el=%d p=%d rows=%d shape=%d" % (n_el, p, rows, shape), flush=True)
+            used = _with_shape(s, shape)
+            if shape == 2:
+                assert 2 in used  # the plane-class kernel applies on the finest level at least
+            for l in range(1, len(H.levels)):
+                lev = H.levels[l]
+                N = lev.A.shape[0]
+                bl = synth.random_vector(N, 140 + l)
+                x0 = synth.random_vector(N, 150 + l)
+                xg = dev(x0)
+                s.smooth(l, dev(bl), xg, 2)
+                xr = mg.smooth(lev, bl, x0.copy(), mg.SMOOTH_MCGS, 2)
+                assert rel(host(xg), xr) < 1e-13, (shape, l)
+                y = torch.zeros(N, dtype=torch.float64, device=DEV)
+                s.apply(l, dev(x0), y)
+                assert rel(host(y), lev.A @ x0) < 1e-13, (shape, l)
+                xj = dev(x0)
+                sj.smooth(l, dev(bl), xj, 2)
+                assert rel(host(xj), mg.smooth(lev, bl, x0.copy(), mg.SMOOTH_JACOBI, 2)) < 1e-13, (shape, l)
+                got[shape, l] = (host(xg), host(y), host(xj))
         s.close()
         sj.close()
     for l in range(1, len(H.levels)):
+        assert all(np.array_equal(a, b) for a, b in zip(got[1, l], got[2, l])), l
         for a, b in zip(got[0, l], got[1, l]):
             assert rel(b, a) < 1e-13, l
+
+
+@pytest.mark.parametrize("n_el,p", [(32, 1), (32, 2), (32, 3), (64, 2), (64, 3)])
+@pytest.mark.parametrize("prec", [igamg.FP64, igamg.FP32_IR])
+def test_cube_plane_class_equals_row_class_bitwise(n_el, p, prec):
+    """V-cycles with every cube level multi-block: one launch per plane class
+    (where it applies: 64 unknowns per direction at most, so the 64^3 level of
+    n_el = 64, p = 2 and not the 65^3 one of p = 3) gives the iterates of one
+    launch per row class bit for bit.  (n = 64 also checks the rows' zero
+    pads when no thread lies past the row's last point.)"""
+    out = []
+    for shape in (1, 2):
+        print("[cube plane] n_el=%d p=%d prec=%d shape=%d" % (n_el, p, prec, shape), flush=True)
+        s = igamg.Solver(igamg.UNIT_CUBE, n_el, p, precision=prec)
+        s.set_rhs_field(modes_for("cube", 2000 + p))
+        used = _with_shape(s, shape)
+        assert (2 in used) == (shape == 2)
+        x = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
+        for _ in range(3):
+            s.vcycle(x)
+        out.append(host(x))
+        s.close()
+    assert np.all(np.isfinite(out[0]))
+    assert np.array_equal(out[0], out[1])
 
 
 @pytest.mark.parametrize("n_el,p", [(16, 1), (16, 2), (16, 3), (32, 3)])
