@@ -602,10 +602,11 @@ def main():
             rep = s.train_smoother([synth.random_field_modes(5000 + k) for k in range(16)],
                                    val_modes=synth.random_field_modes(5900), epochs=args.epochs)
             res["learned_training"] = {k: v for k, v in rep.items()
-                                       if k not in ("loss_first", "loss_last")}
+                                       if k not in ("loss_first", "loss_last", "rho_plain_level",
+                                                    "rho_learned_level")}
             L = s.num_levels
-            res["learned_training"]["loss_first"] = [round(v, 5) for v in rep["loss_first"][:L]]
-            res["learned_training"]["loss_last"] = [round(v, 5) for v in rep["loss_last"][:L]]
+            for k in ("loss_first", "loss_last", "rho_plain_level", "rho_learned_level"):
+                res["learned_training"][k] = [round(v, 5) for v in rep[k][:L]]
             trained = bool(rep["accepted"])
         s.set_rhs_field(synth.random_field_modes(2000 + p))
         forms = (("plain_fp64", igamg.EXTRAP_NONE, igamg.FP64, False),

@@ -403,6 +403,12 @@ typedef struct {
     double rho_learned;
     int accepted;            /* 1 if rho_learned < rho_plain (learned step enabled) */
     double train_ms;
+    double rho_plain_level[16];   /* per level l >= 1: the same contraction for the
+                                     cycle started on level l (levels 0..l), right-
+                                     hand side the validation b restricted to level
+                                     l; entry L equals rho_plain; 0 for level 0 */
+    double rho_learned_level[16]; /* the same with the networks (levels above the
+                                     single-workgroup split use them)          */
 } igamg_train_report;
 
 void igamg_train_options_default(igamg_train_options* o);

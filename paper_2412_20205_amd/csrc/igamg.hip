@@ -1033,6 +1033,7 @@ struct igamg_ctx {
     int level_solve(int l, const double* f, double* u, double tol, int maxit);
     void train(const igamg_train_options& o, igamg_train_report& rep);
     double measure_rho(int vcycles, bool learned);
+    double measure_rho_level(int l, const double* f, int vcycles, bool learned);
 
     void autotune(int* best_items, double* best_ms, bool tune_learned = true);
     void precond_apply(int precond, int q, const double* v, double* z);
@@ -1838,6 +1839,26 @@ double igamg_ctx::measure_rho(int vcycles, bool learned) {
     return std::pow(r_e / r_h, 1.0 / (vcycles - h));
 }
 
+// The same measure for the cycle started on level l (levels 0..l) with
+// right-hand side f of level l.
+double igamg_ctx::measure_rho_level(int l, const double* f, int vcycles, bool learned) {
+    bool save = learned_on;
+    learned_on = learned;
+    double* u = alloc<double>(lv[l].N);
+    fill(u, lv[l].N);
+    int h = vcycles / 2;
+    double r_h = 0.0, r_e = 0.0;
+    for (int k = 1; k <= vcycles; ++k) {
+        vcycle_from<double>(l, f, u);
+        if (k == h) r_h = level_resnorm(l, f, u, 1.0);
+        if (k == vcycles) r_e = level_resnorm(l, f, u, 1.0);
+    }
+    release(u);
+    learned_on = save;
+    if (!(r_h > 0.0) || !(r_e > 0.0)) return 0.0;
+    return std::pow(r_e / r_h, 1.0 / (vcycles - h));
+}
+
 void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
     auto t0 = std::chrono::steady_clock::now();
     if (dim != 2) throw Error(IGAMG_EINVAL, "the learned smoother is 2D only");
@@ -2054,6 +2075,21 @@ void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
         set_rhs_field(o.modes, o.n_modes);
     double rp = measure_rho(o.val_vcycles, false);
     double rl = measure_rho(o.val_vcycles, true);
+    // per level: the cycle started on level l, right-hand side R^(L-l) b
+    {
+        std::vector<double*> f(L + 1, nullptr);
+        f[L] = b;
+        for (int l = L; l >= 2; --l) {
+            f[l - 1] = alloc<double>(lv[l - 1].N);
+            restrict_<double>(l, f[l], f[l - 1]);
+        }
+        for (int l = 0; l < 16; ++l) rep.rho_plain_level[l] = rep.rho_learned_level[l] = 0.0;
+        for (int l = 1; l <= L && l < 16; ++l) {
+            rep.rho_plain_level[l] = (l == L) ? rp : measure_rho_level(l, f[l], o.val_vcycles, false);
+            rep.rho_learned_level[l] = (l == L) ? rl : measure_rho_level(l, f[l], o.val_vcycles, true);
+        }
+        for (int l = 1; l < L; ++l) release(f[l]);
+    }
     rep.levels_trained = trained;
     rep.patches = total_patches;
     for (int l = 0; l < 16; ++l) {

@@ -88,13 +88,16 @@ class TrainReport(ctypes.Structure):
     _fields_ = [("levels_trained", ctypes.c_int), ("patches", ctypes.c_int),
                 ("loss_first", ctypes.c_double * 16), ("loss_last", ctypes.c_double * 16),
                 ("rho_plain", ctypes.c_double), ("rho_learned", ctypes.c_double),
-                ("accepted", ctypes.c_int), ("train_ms", ctypes.c_double)]
+                ("accepted", ctypes.c_int), ("train_ms", ctypes.c_double),
+                ("rho_plain_level", ctypes.c_double * 16), ("rho_learned_level", ctypes.c_double * 16)]
 
     def as_dict(self):
         return {"levels_trained": self.levels_trained, "patches": self.patches,
                 "loss_first": list(self.loss_first), "loss_last": list(self.loss_last),
                 "rho_plain": self.rho_plain, "rho_learned": self.rho_learned,
-                "accepted": self.accepted, "train_ms": self.train_ms}
+                "accepted": self.accepted, "train_ms": self.train_ms,
+                "rho_plain_level": list(self.rho_plain_level),
+                "rho_learned_level": list(self.rho_learned_level)}
 
 
 class IgamgError(RuntimeError):

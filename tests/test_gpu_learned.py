@@ -126,6 +126,19 @@ def test_training_gain_and_fallback():
     print("[learned train] loss last ", np.round(rep["loss_last"][:9], 4))
     assert rep["levels_trained"] >= 2
     assert rep["accepted"] == 1 and rep["rho_learned"] < rep["rho_plain"]
+    # per-level contraction: the cycle started on level l (levels 0..l) on the
+    # validation right-hand side restricted to level l
+    L = s.num_levels - 1
+    top = s.tuning()["tail_top"]
+    rp, rl = rep["rho_plain_level"], rep["rho_learned_level"]
+    print("[learned rho per level] plain", np.round(rp[:L + 1], 4), "learned", np.round(rl[:L + 1], 4),
+          "split", top)
+    assert rp[0] == 0.0 and rl[0] == 0.0
+    assert rp[L] == rep["rho_plain"] and rl[L] == rep["rho_learned"]
+    for l in range(1, L + 1):
+        assert 0.0 < rp[l] < 1.0 and 0.0 < rl[l] < 1.0, l
+        if l <= top:  # no network in a cycle that runs in the single-workgroup kernel
+            assert rl[l] == rp[l], l
     s.set_rhs_field(synth.random_field_modes(5901))
     x = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
     st_l, _ = s.solve(x, tol=1e-10, max_restarts=100, method=igamg.RRE, q=5)
