@@ -553,8 +553,12 @@ def main():
         s.set_rhs_field(synth.random_field_modes(2000 + p))
         ms, st, _ = time_form(s, igamg, torch, igamg.RRE, igamg.FP32_IR, args.steps, args.warmup, True,
                               bool(rep["accepted"]))
+        L = s.num_levels
         print(json.dumps({"only_chosen": True, "degree": p, "ms": round(ms, 3), "vcycles": st.vcycles,
                           "restarts": st.restarts, "learned": bool(rep["accepted"]),
+                          "accepted_level": rep["accepted_level"][:L],
+                          "rho_plain_level": [round(v, 4) for v in rep["rho_plain_level"][:L]],
+                          "rho_learned_level": [round(v, 4) for v in rep["rho_learned_level"][:L]],
                           "tuning": s.tuning()}), flush=True)
         return
 
@@ -603,9 +607,9 @@ def main():
                                    val_modes=synth.random_field_modes(5900), epochs=args.epochs)
             res["learned_training"] = {k: v for k, v in rep.items()
                                        if k not in ("loss_first", "loss_last", "rho_plain_level",
-                                                    "rho_learned_level")}
+                                                    "rho_learned_level", "accepted_level")}
             L = s.num_levels
-            for k in ("loss_first", "loss_last", "rho_plain_level", "rho_learned_level"):
+            for k in ("loss_first", "loss_last", "rho_plain_level", "rho_learned_level", "accepted_level"):
                 res["learned_training"][k] = [round(v, 5) for v in rep[k][:L]]
             trained = bool(rep["accepted"])
         s.set_rhs_field(synth.random_field_modes(2000 + p))

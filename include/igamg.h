@@ -392,6 +392,10 @@ typedef struct {
     int val_n_modes;
     int val_vcycles;         /* V-cycles of the contraction measurement (12)     */
     double solve_tol;        /* relative tolerance of the level solves (1e-12)   */
+    int per_level_accept;    /* 1: keep a level's network only if the cycle started
+                                on that level contracts better with it (bottom-up);
+                                0 (default): every trained level keeps its network
+                                and only the whole-cycle test decides            */
 } igamg_train_options;
 
 typedef struct {
@@ -407,8 +411,13 @@ typedef struct {
                                      cycle started on level l (levels 0..l), right-
                                      hand side the validation b restricted to level
                                      l; entry L equals rho_plain; 0 for level 0 */
-    double rho_learned_level[16]; /* the same with the networks (levels above the
-                                     single-workgroup split use them)          */
+    double rho_learned_level[16]; /* the same with the networks kept (levels above
+                                     the single-workgroup split use them)      */
+    int accepted_level[16];       /* 1 where the level's network is kept (above the
+                                     single-workgroup split; with per_level_accept,
+                                     bottom-up: level l keeps it only if the cycle
+                                     started on level l contracts better with it
+                                     than without, the levels below as decided)  */
 } igamg_train_report;
 
 void igamg_train_options_default(igamg_train_options* o);
@@ -416,8 +425,10 @@ void igamg_train_options_default(igamg_train_options* o);
  * right-hand sides (the target is the part of the algebraic error that the
  * coarse-grid correction cannot remove, e - P A_{l-1}^{-1} R r, from tight level
  * solves), trains every level's network on the device (Adam, FP32 master
- * weights), measures the contraction with and without the networks and
- * enables them only if they contract better.  The right-hand side and the
+ * weights), with per_level_accept keeps each level's network only where it
+ * makes the cycle started on that level contract better (bottom-up), measures
+ * the whole-cycle contraction with and without the networks kept and enables
+ * them only if they contract better.  The right-hand side and the
  * iterate state of the context are restored.  Errors: EINVAL (3D, bad options). */
 igamg_status igamg_train_smoother(igamg_ctx* ctx, const igamg_train_options* opt,
                                   igamg_train_report* report);

@@ -180,6 +180,7 @@ struct igamg_ctx {
     // learned smoother
     struct Net {
         bool have = false;
+        bool on = true;  // used by the V-cycle (training may turn a level's network off)
         uint16_t *wc = nullptr, *w2f = nullptr, *w2b = nullptr;
         float* mf32 = nullptr;       // per-lane MFMA records of the inference kernel
         uint16_t* mfbf = nullptr;
@@ -675,7 +676,7 @@ struct igamg_ctx {
         if constexpr (std::is_same_v<T, double>) return diag64[l]; else return diag32[l];
     }
     bool use_learned(int l) const {
-        return learned_on && l > tail_top && l < (int)nets.size() && nets[l].have;
+        return learned_on && l > tail_top && l < (int)nets.size() && nets[l].have && nets[l].on;
     }
     // Learned first pre-smoothing step on level l: x += sigma N_l(D^{-1} r / sigma).
     // The residual kernel writes z = D^{-1} r and per-block sums of z^2 directly;
@@ -2004,6 +2005,7 @@ void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
                            net.m, net.v, (const float*)g, 0.f, 0.9f, 0.999f, 1e-8f, 1.f, 1.f, net.wc, net.w2f,
                            net.w2b, net.mf32, net.mfbf);
         net.have = true;
+        net.on = true;
         int tiles = ((ls + kLTile - 1) / kLTile) * ((ls + kLTile - 1) / kLTile);
         int B = std::min(o.batch, np);
         float* gpart = alloc<float>((size_t)B * tiles * kLWeights);
@@ -2074,15 +2076,31 @@ void igamg_ctx::train(const igamg_train_options& o, igamg_train_report& rep) {
     else
         set_rhs_field(o.modes, o.n_modes);
     double rp = measure_rho(o.val_vcycles, false);
-    double rl = measure_rho(o.val_vcycles, true);
-    // per level: the cycle started on level l, right-hand side R^(L-l) b
+    double rl = 0.0;
     {
+        // per level: the cycle started on level l, right-hand side R^(L-l) b
         std::vector<double*> f(L + 1, nullptr);
         f[L] = b;
         for (int l = L; l >= 2; --l) {
             f[l - 1] = alloc<double>(lv[l - 1].N);
             restrict_<double>(l, f[l], f[l - 1]);
         }
+        // per_level_accept, bottom-up: level l keeps its network only if the
+        // cycle started on level l contracts better with it than without (the
+        // levels below as already decided)
+        for (int l = 0; l < 16; ++l) rep.accepted_level[l] = 0;
+        for (int l = 1; l <= L; ++l) {
+            if (l <= tail_top || l >= (int)nets.size() || !nets[l].have) continue;
+            if (o.per_level_accept) {
+                nets[l].on = false;
+                const double off = measure_rho_level(l, f[l], o.val_vcycles, true);
+                nets[l].on = true;
+                const double on = measure_rho_level(l, f[l], o.val_vcycles, true);
+                if (!(on > 0.0 && on < off)) nets[l].on = false;
+            }
+            if (l < 16) rep.accepted_level[l] = nets[l].on ? 1 : 0;
+        }
+        rl = measure_rho(o.val_vcycles, true);
         for (int l = 0; l < 16; ++l) rep.rho_plain_level[l] = rep.rho_learned_level[l] = 0.0;
         for (int l = 1; l <= L && l < 16; ++l) {
             rep.rho_plain_level[l] = (l == L) ? rp : measure_rho_level(l, f[l], o.val_vcycles, false);
@@ -3226,6 +3244,7 @@ igamg_status igamg_set_smoother_weights(igamg_ctx* ctx, int level, const uint16_
         ctx->check_launch();
         ctx->sync();
         net.have = true;
+        net.on = true;
         ctx->graph_method = -1;
     });
 }

@@ -81,7 +81,7 @@ class TrainOptions(ctypes.Structure):
                 ("vcycles_per_rhs", ctypes.c_int), ("epochs", ctypes.c_int), ("batch", ctypes.c_int),
                 ("lr", ctypes.c_double), ("seed", ctypes.c_ulonglong), ("val_modes", ctypes.c_void_p),
                 ("val_n_modes", ctypes.c_int), ("val_vcycles", ctypes.c_int),
-                ("solve_tol", ctypes.c_double)]
+                ("solve_tol", ctypes.c_double), ("per_level_accept", ctypes.c_int)]
 
 
 class TrainReport(ctypes.Structure):
@@ -89,7 +89,8 @@ class TrainReport(ctypes.Structure):
                 ("loss_first", ctypes.c_double * 16), ("loss_last", ctypes.c_double * 16),
                 ("rho_plain", ctypes.c_double), ("rho_learned", ctypes.c_double),
                 ("accepted", ctypes.c_int), ("train_ms", ctypes.c_double),
-                ("rho_plain_level", ctypes.c_double * 16), ("rho_learned_level", ctypes.c_double * 16)]
+                ("rho_plain_level", ctypes.c_double * 16), ("rho_learned_level", ctypes.c_double * 16),
+                ("accepted_level", ctypes.c_int * 16)]
 
     def as_dict(self):
         return {"levels_trained": self.levels_trained, "patches": self.patches,
@@ -97,7 +98,8 @@ class TrainReport(ctypes.Structure):
                 "rho_plain": self.rho_plain, "rho_learned": self.rho_learned,
                 "accepted": self.accepted, "train_ms": self.train_ms,
                 "rho_plain_level": list(self.rho_plain_level),
-                "rho_learned_level": list(self.rho_learned_level)}
+                "rho_learned_level": list(self.rho_learned_level),
+                "accepted_level": list(self.accepted_level)}
 
 
 class IgamgError(RuntimeError):

@@ -114,13 +114,15 @@ def test_gradients_match_oracle(solver, level, seed):
 
 
 def test_training_gain_and_fallback():
-    """Train on a 256^2 annulus (p = 3); the trained networks must contract
-    better than the Gauss-Seidel sweep they replace and the RRE(5) solve must
-    reach 1e-10 by the true residual with no more V-cycles than without them."""
+    """Train on a 256^2 annulus (p = 3), keeping each level's network only if
+    the cycle started on that level contracts better with it; the networks kept
+    must contract better than the Gauss-Seidel sweeps they replace and the
+    RRE(5) solve must reach 1e-10 by the true residual with no more V-cycles
+    than without them."""
     print("[case] annulus 256 p=3 training", flush=True)
     s = igamg.Solver(igamg.QUARTER_ANNULUS, 256, 3)
     modes = [synth.random_field_modes(5000 + k) for k in range(8)]
-    rep = s.train_smoother(modes, val_modes=synth.random_field_modes(5900), epochs=8)
+    rep = s.train_smoother(modes, val_modes=synth.random_field_modes(5900), epochs=8, per_level_accept=1)
     print("[learned train]", {k: v for k, v in rep.items() if k not in ("loss_first", "loss_last")})
     print("[learned train] loss first", np.round(rep["loss_first"][:9], 4))
     print("[learned train] loss last ", np.round(rep["loss_last"][:9], 4))
@@ -133,11 +135,16 @@ def test_training_gain_and_fallback():
     rp, rl = rep["rho_plain_level"], rep["rho_learned_level"]
     print("[learned rho per level] plain", np.round(rp[:L + 1], 4), "learned", np.round(rl[:L + 1], 4),
           "split", top)
+    acc = rep["accepted_level"]
+    print("[learned levels kept]", acc[:L + 1])
     assert rp[0] == 0.0 and rl[0] == 0.0
     assert rp[L] == rep["rho_plain"] and rl[L] == rep["rho_learned"]
+    assert sum(acc) >= 1 and all(a in (0, 1) for a in acc)
     for l in range(1, L + 1):
         assert 0.0 < rp[l] < 1.0 and 0.0 < rl[l] < 1.0, l
         if l <= top:  # no network in a cycle that runs in the single-workgroup kernel
+            assert rl[l] == rp[l] and acc[l] == 0, l
+        if not any(acc[1:l + 1]):  # no network kept on levels 0..l: the same cycle
             assert rl[l] == rp[l], l
     s.set_rhs_field(synth.random_field_modes(5901))
     x = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
@@ -161,3 +168,22 @@ def test_training_gain_and_fallback():
     print("[learned fallback] fallbacks %d vcycles %d" % (st_f.learned_fallbacks, st_f.vcycles))
     assert s.residual(x1) <= 1.0000001e-10
     assert st_f.learned_fallbacks >= 1
+
+
+def test_default_training_keeps_every_trained_level():
+    """Without per_level_accept every trained level (those above the
+    single-workgroup split) keeps its network; the per-level contraction
+    figures are reported all the same."""
+    print("[case] annulus 128 p=3 training, default acceptance", flush=True)
+    s = igamg.Solver(igamg.QUARTER_ANNULUS, 128, 3)
+    rep = s.train_smoother([synth.random_field_modes(5000 + k) for k in range(4)],
+                           val_modes=synth.random_field_modes(5900), epochs=2)
+    L = s.num_levels - 1
+    top = s.tuning()["tail_top"]
+    print("[learned default] kept", rep["accepted_level"][:L + 1], "split", top,
+          "rho", np.round(rep["rho_plain_level"][:L + 1], 4), np.round(rep["rho_learned_level"][:L + 1], 4))
+    assert rep["levels_trained"] == L - top
+    assert rep["accepted_level"][:L + 1] == [0] * (top + 1) + [1] * (L - top)
+    for l in range(1, L + 1):
+        assert 0.0 < rep["rho_plain_level"][l] < 1.0 and 0.0 < rep["rho_learned_level"][l] < 1.0
+    s.close()
