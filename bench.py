@@ -105,10 +105,11 @@ def smoother_roofline(s, igamg, precision, nsweeps=8):
             "avg_launch_us": round(ms * 1e3, 3), "bytes_per_launch": int(by), "launches": n}
 
 
-def batch_measure(igamg, torch, synth, steps, warmup):
+def batch_measure(igamg, torch, synth, steps, warmup, sequential=True):
     """96 independent 2D problems (seeded sizes 32^2..512^2, p in 2..5, square or
     annulus, RHS seed 4000 + i) solved by one batch, RRE(5) around FP32 V-cycles
-    in FP64 refinement; the same problems solved one after another beside it."""
+    in FP64 refinement; the same problems solved one after another beside it
+    (unless not sequential)."""
     probs = synth.batch_instances(96, 4)
     geo = {0: igamg.UNIT_SQUARE, 1: igamg.QUARTER_ANNULUS}
     t0 = time.perf_counter()
@@ -138,6 +139,9 @@ def batch_measure(igamg, torch, synth, steps, warmup):
         inst = B.instances[i]
         upd += sum(inst.level_ndof(l) for l in range(1, inst.num_levels)) * 4 * st.vcycles
     B.close()
+    if not sequential:
+        return {"problems": len(probs), "ndof": ndof, "batch_ms": round(ms, 2),
+                "max_restarts": max(st.restarts for st in stats), "setup_s": round(setup_s, 2)}
     # the same problems one by one (default single-problem path)
     seq_ms = 0.0
     for i, (ne, p, g, seed) in enumerate(probs):
@@ -160,17 +164,22 @@ def batch_measure(igamg, torch, synth, steps, warmup):
             "setup_s": round(setup_s, 2)}
 
 
-def c1_measure(igamg, torch, synth, steps):
+def c1_measure(igamg, torch, synth, steps, forms=None):
     """Unit square, p = 2, 64^2 elements, f = 2 pi^2 sin(pi x) sin(pi y), FP64:
-    {multicolour, lexicographic} V(2,2) x {plain, RRE(5), MPE(5)}."""
+    {multicolour, lexicographic} V(2,2) x {plain, RRE(5), MPE(5)} (forms: a
+    subset of their names, e.g. "mcgs_rre5")."""
     out = {}
     for sm_name, sm in (("mcgs", igamg.SMOOTH_MCGS), ("lexgs", igamg.SMOOTH_LEXGS)):
+        if forms is not None and not any(f.startswith(sm_name) for f in forms):
+            continue
         s = igamg.Solver(igamg.UNIT_SQUARE, 64, 2, smoother=sm)
         s.set_rhs_field(synth.manufactured_sine_modes_2d())
         if sm == igamg.SMOOTH_MCGS:
             s.autotune()  # sweep launch shapes and the single-workgroup split
             out["mcgs_tuning"] = s.tuning()
         for m_name, m in (("plain", igamg.EXTRAP_NONE), ("rre5", igamg.RRE), ("mpe5", igamg.MPE)):
+            if forms is not None and "%s_%s" % (sm_name, m_name) not in forms:
+                continue
             ms, st, _ = time_form(s, igamg, torch, m, igamg.FP64, steps, 1)
             out["%s_%s" % (sm_name, m_name)] = {"ms": round(ms, 3), "vcycles": st.vcycles,
                                                 "restarts": st.restarts,
@@ -493,6 +502,10 @@ def main():
     ap.add_argument("--cube-tuning", default=None,
                     help="with --only-cube: launch shapes as JSON (tuning() of an unprofiled run) "
                          "instead of autotuning")
+    ap.add_argument("--only-square", action="store_true",
+                    help="only the 64^2 unit square's multicolour FP64 RRE(5) solves, autotuned (kernel profiles)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="with --only-batch: skip the one-by-one comparison (kernel profiles)")
     ap.add_argument("--only-1d", action="store_true",
                     help="only the 1D model problem leg (Tables 1 and 4), printed as its own JSON line")
     ap.add_argument("--epochs", type=int, default=10)
@@ -575,8 +588,13 @@ def main():
         return
 
     if args.only_batch:
-        print(json.dumps({"batch": batch_measure(igamg, torch, synth, args.steps, args.warmup)}),
-              flush=True)
+        print(json.dumps({"batch": batch_measure(igamg, torch, synth, args.steps, args.warmup,
+                                                 sequential=not args.no_sequential)}), flush=True)
+        return
+
+    if args.only_square:
+        print(json.dumps({"only_square": True,
+                          **c1_measure(igamg, torch, synth, args.steps, forms=("mcgs_rre5",))}), flush=True)
         return
 
     if args.only_1d:

@@ -134,11 +134,13 @@ typedef struct {
     int row_sweeps;      /* stored stencils: sweep the p+1 colours of a row
                             class (rows j = r mod p+1) in one launch, one
                             workgroup per row (default 1); 0: one launch per
-                            colour.  Both give the same iterates.  Cubes:
-                            row classes (j, k mod p+1), the rows' products
-                            sum-factorised (iterates equal to rounding), and
-                            one-workgroup-per-row residuals; 0: one launch
-                            per colour and per-point residuals.              */
+                            colour.  Both give the same iterates.  Sum-
+                            factorised operators (unit square, cube): row
+                            classes (j, or j and k, mod p+1), the rows'
+                            products factored through the y (and z) bands
+                            (iterates equal to rounding), and one-workgroup-
+                            per-row residuals; 0: one launch per colour and
+                            per-point residuals.                             */
     void* stream;        /* hipStream_t or NULL                               */
 } igamg_options;
 

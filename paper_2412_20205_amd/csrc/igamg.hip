@@ -300,25 +300,25 @@ struct igamg_ctx {
     long long residual_blocks(int l) const {
         const Level& v = lv[l];
         if (kind == OP_STENCIL2D) return (long long)v.ncol * (v.ncp / 64);
-        if (row3_available(l)) return (long long)v.n * v.n;
+        if (kron_rows_available(l)) return (dim == 3) ? (long long)v.n * v.n : (long long)v.n;
         return (v.N + 63) / 64;
     }
 
     // out = b - A x (mode 0), A x (mode 1), Jacobi step (mode 2), z = D^{-1}(b - A x)
     // as float with per-block sums of z^2 in part (mode 3)
-    // (sum-factorised 3D levels: one workgroup per x-row, modes 0-2)
+    // (sum-factorised levels: one workgroup per x-row, modes 0-2)
     template <typename T, typename Tout>
     void residual(int l, const T* bb, const T* x, Tout* out, int mode, double* part) {
         const long long nb = residual_blocks(l);
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
-            if constexpr (!Op::kColourOrder && std::is_same_v<typename Op::Pt, Pt3>) {
-                if (row3_available(l)) {
-                    if (mode > 2) throw Error(IGAMG_EINVAL, "residual mode 3 needs a 2D level");
+            if constexpr (!Op::kColourOrder) {
+                if (kron_rows_available(l)) {
+                    if (mode > 2) throw Error(IGAMG_EINVAL, "residual mode 3 needs stored stencils");
                     const int n = lv[l].n;
-                    hipLaunchKernelGGL((k_residual_row3<Op, Tout>), dim3((unsigned)nb), dim3(((n + 63) / 64) * 64),
-                                       row3_lds_bytes(p, n, 2, sizeof(T)), stream, op, bb, x, out, mode,
-                                       opt.omega, part);
+                    hipLaunchKernelGGL((k_residual_row_kron<Op, Tout>), dim3((unsigned)nb),
+                                       dim3(((n + 63) / 64) * 64), row_kron_lds_bytes(p, n, 2, sizeof(T)), stream,
+                                       op, bb, x, out, mode, opt.omega, part);
                     return;
                 }
             }
@@ -374,18 +374,18 @@ struct igamg_ctx {
     // Sum-factorised 3D levels whose planes (with the waves' row buffers) fit
     // the plane-class kernel's LDS in FP64, one lane per point of a row.
     bool plane3_available(int l) const {
-        return row3_available(l) && lv[l].n <= kPlane3MaxN &&
+        return kind == OP_KRON3D && kron_rows_available(l) && lv[l].n <= kPlane3MaxN &&
                plane3_lds_bytes(p, lv[l].n, sizeof(double)) <= kPlane3MaxLds;
     }
     bool row_sweeps_available(int l) const {
-        if (kind == OP_KRON3D) return row3_available(l);
+        if (kind != OP_STENCIL2D) return kron_rows_available(l);
         return opt.row_sweeps && kind == OP_STENCIL2D && p <= 4 && row_fits(p, lv[l].n) &&
                coef_bytes(l, sizeof(double)) < (1LL << 32);
     }
-    // Sum-factorised 3D levels of at most kRow3MaxN unknowns per direction:
+    // Sum-factorised levels of at most kRowKronMaxN unknowns per direction:
     // row-class sweeps and one-workgroup-per-row residuals.
-    bool row3_available(int l) const {
-        return opt.row_sweeps && kind == OP_KRON3D && lv[l].n <= kRow3MaxN;
+    bool kron_rows_available(int l) const {
+        return opt.row_sweeps && (kind == OP_KRON3D || kind == OP_KRON2D) && lv[l].n <= kRowKronMaxN;
     }
     // One multicolour Gauss-Seidel sweep of level l (multi-block launches).
     // Returns the number of launches; *bytes (when given) receives the
@@ -403,32 +403,35 @@ struct igamg_ctx {
         int launches = 0;
         with_op<T>(l, [&](auto op) {
             using Op = decltype(op);
-            if constexpr (!Op::kColourOrder && std::is_same_v<typename Op::Pt, Pt3>) {
-                if (sweep_shape(l) == 2) {
-                    const int P1 = p + 1;
-                    const size_t lds = plane3_lds_bytes(p, v.n, sizeof(T));
-                    const int th = 64 * plane3_waves(p, v.n);
-                    for (int ck = 0; ck < P1; ++ck) {
-                        const int nk = (v.n - ck + p) / P1;
-                        if (nk <= 0) continue;
-                        hipLaunchKernelGGL((k_gs_planeclass3<Op>), dim3(nk), dim3(th), lds, stream, op, bb, x, ck);
-                        ++launches;
-                        if (bytes)
-                            for (int c = P1 * P1 * ck; c < P1 * P1 * (ck + 1); ++c)
-                                *bytes += colour_size_host(v.n, p, dim, c) * per_point;
+            if constexpr (!Op::kColourOrder) {
+                if constexpr (std::is_same_v<typename Op::Pt, Pt3>) {
+                    if (sweep_shape(l) == 2) {
+                        const int P1 = p + 1;
+                        const size_t lds = plane3_lds_bytes(p, v.n, sizeof(T));
+                        const int th = 64 * plane3_waves(p, v.n);
+                        for (int ck = 0; ck < P1; ++ck) {
+                            const int nk = (v.n - ck + p) / P1;
+                            if (nk <= 0) continue;
+                            hipLaunchKernelGGL((k_gs_planeclass3<Op>), dim3(nk), dim3(th), lds, stream, op, bb,
+                                               x, ck);
+                            ++launches;
+                            if (bytes)
+                                for (int c = P1 * P1 * ck; c < P1 * P1 * (ck + 1); ++c)
+                                    *bytes += colour_size_host(v.n, p, dim, c) * per_point;
+                        }
+                        return;
                     }
-                    return;
                 }
                 if (row_sweeps(l)) {
                     const int P1 = p + 1;
-                    const size_t lds = row3_lds_bytes(p, v.n, 3, sizeof(T));
+                    const size_t lds = row_kron_lds_bytes(p, v.n, 3, sizeof(T));
                     const int th = ((v.n + 63) / 64) * 64;
-                    for (int ck = 0; ck < P1; ++ck)
+                    for (int ck = 0; ck < (dim == 3 ? P1 : 1); ++ck)
                         for (int cj = 0; cj < P1; ++cj) {
-                            const int nj = (v.n - cj + p) / P1, nk = (v.n - ck + p) / P1;
+                            const int nj = (v.n - cj + p) / P1, nk = (dim == 3) ? (v.n - ck + p) / P1 : 1;
                             if (nj <= 0 || nk <= 0) continue;
-                            hipLaunchKernelGGL((k_gs_rowclass3<Op>), dim3(nj * nk), dim3(th), lds, stream, op, bb,
-                                               x, cj, ck);
+                            hipLaunchKernelGGL((k_gs_rowclass_kron<Op>), dim3(nj * nk), dim3(th), lds, stream, op,
+                                               bb, x, cj, ck);
                             ++launches;
                             if (bytes)
                                 for (int ci = 0; ci < P1; ++ci)
@@ -566,11 +569,11 @@ struct igamg_ctx {
         return top;
     }
     // The prefetching tail variant (FP32 stored stencils) needs the records of
-    // every level it smooths, which exist where a colour fits the block; 3D
-    // levels need rows of at most one wave.
+    // every level it smooths, which exist where a colour fits the block;
+    // sum-factorised levels need rows of at most one wave.
     template <typename T>
     bool tail_level_ok(int l) {
-        if (kind == OP_KRON3D && lv[l].n > kTail3MaxN) return false;  // one lane per point of a row
+        if (kind != OP_STENCIL2D && lv[l].n > kTailKronMaxN) return false;  // one lane per point of a row
         bool ok = true;
         with_op<T>(l, [&](auto opl) {
             if constexpr (tail_prefetch<decltype(opl)>()) ok = (l == 0) || lv[l].rec32 != nullptr;
@@ -1627,10 +1630,15 @@ void igamg_ctx::autotune(int* best_items, double* best_ms, bool tune_learned) {
             fill(v.x<T>(), v.N);
             hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(v.N)), dim3(kBlock), 0, stream, v.b<T>(), (T)1, v.N);
             check_launch();
-            // 2D: one launch per colour or per row class (the same iterates);
-            // 3D: per row class or per plane class (the same iterates; one
-            // launch per colour sums in another order and is not a candidate)
-            const int lo = (kind == OP_KRON3D) ? 1 : 0, hi = plane3_available(l) ? 2 : 1;
+            // stored stencils: one launch per colour or per row class (the
+            // same iterates); sum-factorised operators: per row class, or (3D)
+            // per plane class (the same iterates; one launch per colour sums
+            // in another order and is not a candidate)
+            const int lo = (kind == OP_STENCIL2D) ? 0 : 1, hi = plane3_available(l) ? 2 : 1;
+            if (hi == lo) {
+                row_pref[l] = lo;
+                continue;
+            }
             double t[3] = {1e300, 1e300, 1e300};
             for (int trial = 0; trial < 2; ++trial)
                 for (int pref = lo; pref <= hi; ++pref) {

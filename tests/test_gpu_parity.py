@@ -395,7 +395,7 @@ def test_row_class_sweeps_equal_colour_passes(geom, n_el, p, extra, prec):
 
 def _with_shape(s, shape):
     """Sets every level's sweep launch shape (0 per colour, 1 per row class,
-    2 per plane class where it applies) and the multi-block split 0."""
+    2 per plane class where it applies: cubes) and the multi-block split 0."""
     t = s.tuning()
     t["tail_items"] = 0
     t["row_class"] = [shape] * t["num_levels"]
@@ -403,25 +403,30 @@ def _with_shape(s, shape):
     return s.tuning()["row_class"]
 
 
-@pytest.mark.parametrize("n_el,p", [(16, 1), (32, 1), (16, 2), (32, 2), (16, 3), (32, 3)])
-def test_cube_row_class_sweeps_and_products(n_el, p):
-    """Sum-factorised cube levels: the row-class sweep (one launch per row class
-    (j, k mod p+1), each row's product factored through the y and z bands), the
-    plane-class sweep (one launch per plane class, one workgroup per plane) and
-    the one-workgroup-per-row products (A x, damped Jacobi) equal the oracle's
+KRON_ROW_CASES = ([("cube", n, p) for n, p in [(16, 1), (32, 1), (16, 2), (32, 2), (16, 3), (32, 3)]] +
+                  [("square", n, p) for n, p in [(16, 1), (64, 2), (32, 3), (16, 4), (32, 5)]])
+
+
+@pytest.mark.parametrize("geom,n_el,p", KRON_ROW_CASES)
+def test_kron_row_class_sweeps_and_products(geom, n_el, p):
+    """Sum-factorised levels (unit square and cube): the row-class sweep (one
+    launch per row class, j (and k) fixed mod p+1, each row's product factored
+    through the y (and z) bands), on the cube also the plane-class sweep (one
+    launch per plane class, one workgroup per plane), and the
+    one-workgroup-per-row products (A x, damped Jacobi) equal the oracle's
     multicolour sweeps, A x and Jacobi steps on every level (1e-13), as do the
     per-colour kernels.  Row- and plane-class sweeps are equal bit for bit; the
     per-colour kernels sum in another order and agree with them to the same
     bar.  With n = n_el + p - 2 unknowns per direction most levels leave ragged
     classes (n not a multiple of p + 1)."""
-    H = mg.build_hierarchy("cube", n_el, p)
+    H = mg.build_hierarchy(geom, n_el, p)
     got = {}
     for rows in (0, 1):
-        s = igamg.Solver(igamg.UNIT_CUBE, n_el, p, tail_items=0, row_sweeps=rows)
-        sj = igamg.Solver(igamg.UNIT_CUBE, n_el, p, tail_items=0, row_sweeps=rows,
-                          smoother=igamg.SMOOTH_JACOBI)
-        for shape in ((0,) if rows == 0 else (1, 2)):
-            print("[cube shapes] n_el=%d p=%d rows=%d shape=%d" % (n_el, p, rows, shape), flush=True)
+        s = igamg.Solver(GEOM[geom], n_el, p, tail_items=0, row_sweeps=rows)
+        sj = igamg.Solver(GEOM[geom], n_el, p, tail_items=0, row_sweeps=rows, smoother=igamg.SMOOTH_JACOBI)
+        shapes = (0,) if rows == 0 else ((1, 2) if geom == "cube" else (1,))
+        for shape in shapes:
+            print("[kron shapes] %s n_el=%d p=%d rows=%d shape=%d" % (geom, n_el, p, rows, shape), flush=True)
             used = _with_shape(s, shape)
             if shape == 2:
                 assert 2 in used  # the plane-class kernel applies on the finest level at least
@@ -444,7 +449,8 @@ def test_cube_row_class_sweeps_and_products(n_el, p):
         s.close()
         sj.close()
     for l in range(1, len(H.levels)):
-        assert all(np.array_equal(a, b) for a, b in zip(got[1, l], got[2, l])), l
+        if geom == "cube":
+            assert all(np.array_equal(a, b) for a, b in zip(got[1, l], got[2, l])), l
         for a, b in zip(got[0, l], got[1, l]):
             assert rel(b, a) < 1e-13, l
 
@@ -473,20 +479,22 @@ def test_cube_plane_class_equals_row_class_bitwise(n_el, p, prec):
     assert np.array_equal(out[0], out[1])
 
 
-@pytest.mark.parametrize("n_el,p", [(16, 1), (16, 2), (16, 3), (32, 3)])
+@pytest.mark.parametrize("geom,n_el,p", [("cube", 16, 1), ("cube", 16, 2), ("cube", 16, 3), ("cube", 32, 3),
+                                         ("square", 64, 2), ("square", 32, 3), ("square", 16, 5)])
 @pytest.mark.parametrize("prec", [igamg.FP64, igamg.FP32_IR])
 @pytest.mark.parametrize("mu", [1, 2])
-def test_cube_tail_equals_multiblock_bitwise(n_el, p, prec, mu):
-    """Cube levels in the single-workgroup kernel sweep in row classes with the
-    arithmetic of the multi-block row-class kernels (same contraction and
-    summation order; the same transfers and coarse solve), so V- and W-cycle
-    iterates with the small levels in one workgroup equal, bit for bit, those
-    with every level multi-block."""
+def test_kron_tail_equals_multiblock_bitwise(geom, n_el, p, prec, mu):
+    """Sum-factorised levels in the single-workgroup kernel (rows of at most 64
+    unknowns) sweep in row classes with the arithmetic of the multi-block
+    row-class kernels (same contraction and summation order; the same
+    transfers and coarse solve), so V- and W-cycle iterates with the small
+    levels in one workgroup equal, bit for bit, those with every level
+    multi-block."""
     out = []
     for tail in (0, 512):
-        print("[cube tail] n_el=%d p=%d prec=%d mu=%d tail=%d" % (n_el, p, prec, mu, tail), flush=True)
-        s = igamg.Solver(igamg.UNIT_CUBE, n_el, p, tail_items=tail, precision=prec, mu=mu)
-        s.set_rhs_field(modes_for("cube", 2000 + p))
+        print("[kron tail] %s n_el=%d p=%d prec=%d mu=%d tail=%d" % (geom, n_el, p, prec, mu, tail), flush=True)
+        s = igamg.Solver(GEOM[geom], n_el, p, tail_items=tail, precision=prec, mu=mu)
+        s.set_rhs_field(modes_for(geom, 2000 + p))
         assert (s.tuning()["tail_top"] >= 2) == (tail > 0)
         x = torch.zeros(s.ndof, dtype=torch.float64, device=DEV)
         for _ in range(3):
