@@ -164,7 +164,7 @@ def batch_measure(igamg, torch, synth, steps, warmup, sequential=True):
             "setup_s": round(setup_s, 2)}
 
 
-def c1_measure(igamg, torch, synth, steps, forms=None):
+def c1_measure(igamg, torch, synth, steps, forms=None, tuning=None):
     """Unit square, p = 2, 64^2 elements, f = 2 pi^2 sin(pi x) sin(pi y), FP64:
     {multicolour, lexicographic} V(2,2) x {plain, RRE(5), MPE(5)} (forms: a
     subset of their names, e.g. "mcgs_rre5")."""
@@ -175,7 +175,10 @@ def c1_measure(igamg, torch, synth, steps, forms=None):
         s = igamg.Solver(igamg.UNIT_SQUARE, 64, 2, smoother=sm)
         s.set_rhs_field(synth.manufactured_sine_modes_2d())
         if sm == igamg.SMOOTH_MCGS:
-            s.autotune()  # sweep launch shapes and the single-workgroup split
+            if tuning is not None:  # launch shapes given (profiled runs)
+                s.set_tuning(tuning)
+            else:
+                s.autotune()  # sweep launch shapes and the single-workgroup split
             out["mcgs_tuning"] = s.tuning()
         for m_name, m in (("plain", igamg.EXTRAP_NONE), ("rre5", igamg.RRE), ("mpe5", igamg.MPE)):
             if forms is not None and "%s_%s" % (sm_name, m_name) not in forms:
@@ -499,9 +502,9 @@ def main():
                     help="setup, tuning and training, then only the chosen-form solves (kernel profiles)")
     ap.add_argument("--only-cube", action="store_true",
                     help="only the 128^3 cube's FP32-in-FP64 MPE(4) solves, autotuned (kernel profiles)")
-    ap.add_argument("--cube-tuning", default=None,
-                    help="with --only-cube: launch shapes as JSON (tuning() of an unprofiled run) "
-                         "instead of autotuning")
+    ap.add_argument("--tuning", default=None,
+                    help="with --only-cube or --only-square: launch shapes as JSON (tuning() of an "
+                         "unprofiled run) instead of autotuning")
     ap.add_argument("--only-square", action="store_true",
                     help="only the 64^2 unit square's multicolour FP64 RRE(5) solves, autotuned (kernel profiles)")
     ap.add_argument("--no-sequential", action="store_true",
@@ -577,7 +580,7 @@ def main():
 
     if args.only_cube:
         c3, _ = c3_measure(igamg, torch, synth, args.steps, forms=("mpe4_ir",),
-                           tuning=json.loads(args.cube_tuning) if args.cube_tuning else None)
+                           tuning=json.loads(args.tuning) if args.tuning else None)
         # a plain copy of known size (calibration of the traffic counters)
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
         bcopy = torch.empty_like(a)
@@ -594,7 +597,8 @@ def main():
 
     if args.only_square:
         print(json.dumps({"only_square": True,
-                          **c1_measure(igamg, torch, synth, args.steps, forms=("mcgs_rre5",))}), flush=True)
+                          **c1_measure(igamg, torch, synth, args.steps, forms=("mcgs_rre5",),
+                                       tuning=json.loads(args.tuning) if args.tuning else None)}), flush=True)
         return
 
     if args.only_1d:

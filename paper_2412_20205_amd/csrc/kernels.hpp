@@ -2106,7 +2106,7 @@ __device__ void ft_vcycle(const TailArgs<Stencil2D<P, T>>& a) {
 constexpr int kTailKronMaxN = 64;
 
 // sum_a Kx_{i,a} u_{i+a} + Mx_{i,a} v_{i+a} for the lane's point i (its band
-// rows kxr, mxr in LDS, read at their use); lanes outside the row hold
+// rows kxr, mxr, each entry read at its use); lanes outside the row hold
 // u = v = 0 and out-of-row offsets have zero band entries.  cr (optional)
 // receives the in-row coupling m00 Kx_{i,a} + g00 Mx_{i,a}.
 template <int W, typename T>
@@ -2134,8 +2134,22 @@ __device__ void tail_rows_kron(const Op& A, const typename Op::T* __restrict__ b
     constexpr int P = Op::kP, W = Op::W, DIM = is_kron3<Op>() ? 3 : 2;
     const int n = A.n, NWAVE = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = min(lane, n - 1);
-    const T* kxr = A.K + i * W;  // the lane's x band rows (LDS)
+    // the lane's x band rows: read from LDS at their use (2D, where registers
+    // are short at high degree) or loaded after each contraction (3D)
+    T kxa[W], mxa[W];
+    const T* kxr = A.K + i * W;
     const T* mxr = A.M + i * W;
+    auto xbands = [&]() {
+        if constexpr (DIM == 3) {
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                kxa[a] = A.K[i * W + a];
+                mxa[a] = A.M[i * W + a];
+            }
+        }
+    };
+    const T* kxp = (DIM == 3) ? kxa : kxr;
+    const T* mxp = (DIM == 3) ? mxa : mxr;
     if (!gs) {
         const int rows = (DIM == 3) ? n * n : n;
         for (int row = wave; row < rows; row += NWAVE) {
@@ -2143,7 +2157,8 @@ __device__ void tail_rows_kron(const Op& A, const typename Op::T* __restrict__ b
             T u, v;
             kron_row_contract<Op, true, false>(A, x, j, k, i, u, v);
             if (lane >= n) u = v = 0;
-            const T acc = tail_kron_xproduct<W, T>(kxr, mxr, u, v, lane, (T)0, (T)0, (T*)nullptr);
+            xbands();
+            const T acc = tail_kron_xproduct<W, T>(kxp, mxp, u, v, lane, (T)0, (T)0, (T*)nullptr);
             if (lane < n) r[(size_t)row * n + lane] = b[(size_t)row * n + lane] - acc;
         }
         __syncthreads();
@@ -2165,7 +2180,8 @@ __device__ void tail_rows_kron(const Op& A, const typename Op::T* __restrict__ b
                 T m00, g00;
                 kron_row_self(A, j, k, m00, g00);
                 T cr[W];
-                const T rest = tail_kron_xproduct<W, T>(kxr, mxr, u, v, lane, m00, g00, cr);
+                xbands();
+                const T rest = tail_kron_xproduct<W, T>(kxp, mxp, u, v, lane, m00, g00, cr);
 #pragma unroll
                 for (int s = 0; s <= P; ++s) {
                     if (lane < n && s_own == s) {
