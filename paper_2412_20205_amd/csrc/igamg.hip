@@ -379,7 +379,9 @@ struct igamg_ctx {
     }
     bool row_sweeps_available(int l) const {
         if (kind != OP_STENCIL2D) return kron_rows_available(l);
-        return opt.row_sweeps && kind == OP_STENCIL2D && p <= 4 && row_fits(p, lv[l].n) &&
+        // (the row kernel's register bound: p <= 4 in FP64, p <= 5 in FP32)
+        const bool deg_ok = p <= 4 || (p == 5 && opt.precision == IGAMG_FP32_IR);
+        return opt.row_sweeps && kind == OP_STENCIL2D && deg_ok && row_fits(p, lv[l].n) &&
                coef_bytes(l, sizeof(double)) < (1LL << 32);
     }
     // Sum-factorised levels of at most kRowKronMaxN unknowns per direction:

@@ -433,13 +433,14 @@ struct RowRegs {
     typename Op::T cv[Op::S];
     typename Op::T bv;
 };
-// Degrees where one launch per row class was measured faster than one per
-// colour on the 1024^2 annulus hierarchy (p <= 4, both precisions; at p = 5
-// the per-point coefficient registers leave no room to load ahead and the
-// per-colour launches are as fast or faster).
+// One colour step's coefficients per lane (S + 1 values) must fit the register
+// budget of 512 threads: FP64 up to p = 4, FP32 up to p = 5.  (At p = 5 no
+// step can be loaded ahead; on the finest 1024^2 level the row-class launches
+// are then no faster than one launch per colour, on the coarser, launch-bound
+// levels they are: the autotuner chooses per level.)
 template <class Op>
 constexpr bool row_kernel_ok() {
-    return Op::kP <= 4 && (Op::S + 1) * (int)sizeof(typename Op::T) / 4 <= 170;
+    return (Op::S + 1) * (int)sizeof(typename Op::T) / 4 <= 170;
 }
 // Colour steps loaded ahead of the one being updated (register budget of the
 // ring: about half of the 256 registers a lane has at 512 threads).
