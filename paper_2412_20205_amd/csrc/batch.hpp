@@ -33,6 +33,19 @@ __global__ void __launch_bounds__(64 * Op::NW) k_b_gs(const BGs<Op>* __restrict_
     gs_colour_body(en.op, en.b, en.x, c, blockIdx.x - o[e]);
 }
 
+// Row-class sweep step of many problems: offs holds, per class r, the prefix
+// counts of the problems' rows in that class; a workgroup runs one row
+// (workgroups of one problem's rows are consecutive, in XCD order).
+template <class Op, bool kStream>
+__global__ void __launch_bounds__(kRowThreads) k_b_rowclass(const BGs<Op>* __restrict__ E,
+                                                            const int* __restrict__ offs, int ne, int r) {
+    const int* o = offs + (size_t)r * (ne + 1);
+    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int e = bmap_find(o, ne, blk);
+    const BGs<Op> en = E[e];
+    rowclass_body<Op, kStream>(en.op, en.b, en.x, r, blk - o[e]);
+}
+
 template <class Op, typename Tout>
 struct BRes {
     Op op;

@@ -2263,6 +2263,44 @@ struct igamg_batch {
                 tot[c] = offs[(size_t)c * (nsel + 1) + nsel];
             }
             const BGs<Op32>* dE = up(E);
+            if constexpr (row_kernel_ok<Op32>()) {
+                // one launch per row class: workgroup per row, sized for the
+                // group's widest row (the same iterates as per-colour launches)
+                bool rows = true;
+                int th = 64;
+                long long coef = 0;
+                for (int k = 0; k < nsel; ++k) {
+                    igamg_ctx* cx = inst[mem[sel[k]]];
+                    const int l = cx->L - d;
+                    rows = rows && cx->row_sweeps_available(l);
+                    th = std::max(th, row_threads(P, cx->lv[l].n));
+                    coef = std::max(coef, cx->coef_bytes(l, sizeof(float)));
+                }
+                if (rows) {
+                    std::vector<int> ro((size_t)(P + 1) * (nsel + 1), 0);
+                    std::vector<int> rt(P + 1, 0);
+                    for (int r = 0; r <= P; ++r) {
+                        for (int k = 0; k < nsel; ++k) {
+                            igamg_ctx* cx = inst[mem[sel[k]]];
+                            const int nj = (cx->lv[cx->L - d].n - r + P) / (P + 1);
+                            ro[(size_t)r * (nsel + 1) + k + 1] = ro[(size_t)r * (nsel + 1) + k] + std::max(nj, 0);
+                        }
+                        rt[r] = ro[(size_t)r * (nsel + 1) + nsel];
+                    }
+                    const int* dR = up(ro);
+                    const bool stream_coef = coef > igamg_ctx::kCachedCoefBytes;
+                    for (int s2 = 0; s2 < nsweeps; ++s2)
+                        for (int r = 0; r <= P; ++r) {
+                            if (rt[r] <= 0) continue;
+                            if (stream_coef)
+                                BLAUNCH((k_b_rowclass<Op32, true>), dim3(rt[r]), dim3(th), 0, st, dE, dR, nsel, r);
+                            else
+                                BLAUNCH((k_b_rowclass<Op32, false>), dim3(rt[r]), dim3(th), 0, st, dE, dR, nsel,
+                                        r);
+                        }
+                    return;
+                }
+            }
             const int* dO = up(offs);
             for (int s2 = 0; s2 < nsweeps; ++s2)
                 for (int c = 0; c < NC; ++c)

@@ -526,14 +526,14 @@ __device__ __forceinline__ void row_stage(const T* __restrict__ x, int n, int j,
     }
 }
 
-template <class Op, bool kStream = true>
-__global__ void __launch_bounds__(kRowThreads) k_gs_rowclass(Op A, const typename Op::T* __restrict__ b,
-                                                             typename Op::T* __restrict__ x, int r) {
+// Row jj of class r (one workgroup; at least row_threads(p, n) threads).
+template <class Op, bool kStream>
+__device__ __forceinline__ void rowclass_body(const Op& A, const typename Op::T* __restrict__ b,
+                                              typename Op::T* __restrict__ x, int r, int jj) {
     using T = typename Op::T;
     constexpr int P = Op::kP, W = Op::W, D = row_depth<Op>();
     __shared__ __align__(16) T xs[W * kRowMaxStride];
     const int n = A.n, RS = row_stride(n);
-    const int jj = xcd_swizzle(blockIdx.x, gridDim.x);
     const int j = r + (P + 1) * jj;
     const T* bj = b + (size_t)j * n;
     const int t = threadIdx.x;
@@ -552,6 +552,12 @@ __global__ void __launch_bounds__(kRowThreads) k_gs_rowclass(Op A, const typenam
     }
     T* xj = x + (size_t)j * n;
     for (int i = t; i < n; i += blockDim.x) xj[i] = xrow[i];
+}
+
+template <class Op, bool kStream = true>
+__global__ void __launch_bounds__(kRowThreads) k_gs_rowclass(Op A, const typename Op::T* __restrict__ b,
+                                                             typename Op::T* __restrict__ x, int r) {
+    rowclass_body<Op, kStream>(A, b, x, r, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 // ---- row-class multicolour Gauss-Seidel (sum-factorised operators) ----------

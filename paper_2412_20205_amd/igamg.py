@@ -559,8 +559,9 @@ class _Borrowed(Solver):
 class Batch:
     """A batch of independent 2D problems (include/igamg.h, igamg_setup_batch)."""
 
-    def __init__(self, problems, stream=None, tail_items=32):
-        """problems: list of (geometry, n_el, degree); tail_items < 0 autotunes."""
+    def __init__(self, problems, stream=None, tail_items=32, row_sweeps=1):
+        """problems: list of (geometry, n_el, degree); tail_items < 0 autotunes;
+        row_sweeps 0 sweeps one colour per launch instead of one row class."""
         import torch
         if stream is None:
             cs = torch.cuda.current_stream()
@@ -571,6 +572,7 @@ class Batch:
         o = default_options()
         o.stream = stream
         o.tail_items = tail_items
+        o.row_sweeps = row_sweeps
         h = _P()
         _check(lib().igamg_setup_batch(n, ctypes.cast(geoms, _P), ctypes.cast(degs, _P),
                                        ctypes.byref(o), ctypes.byref(h)), "igamg_setup_batch")

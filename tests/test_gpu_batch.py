@@ -88,3 +88,23 @@ def test_autotune_choice_is_cached_and_used():
     sc, _ = t.solve(xc, tol=1e-10, method=igamg.RRE, q=5)
     assert sc.vcycles == sa.vcycles
     assert torch.equal(xc, xa)
+
+
+def test_batch_row_class_sweeps_equal_colour_launches():
+    """The batched row-class sweep (one launch per row class for every problem
+    of a degree, a workgroup per row) gives the iterates of one launch per
+    colour, bit for bit, and the same counts."""
+    out = []
+    for rows in (0, 1):
+        print("[batch rows] row_sweeps=%d" % rows, flush=True)
+        B = igamg.Batch(PROBLEMS, row_sweeps=rows)
+        xs = []
+        for i in range(len(PROBLEMS)):
+            B.instances[i].set_rhs_field(synth.random_field_modes(4100 + i))
+            xs.append(torch.zeros(B.instances[i].ndof, dtype=torch.float64, device=DEV))
+        stats, _ = B.solve(xs, tol=1e-10, max_restarts=60, q=5)
+        out.append(([x.cpu().numpy() for x in xs], [(st.restarts, st.vcycles) for st in stats]))
+        B.close()
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    assert out[0][1] == out[1][1]
