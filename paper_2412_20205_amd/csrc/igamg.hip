@@ -316,9 +316,24 @@ struct igamg_ctx {
                 if (kron_rows_available(l)) {
                     if (mode > 2) throw Error(IGAMG_EINVAL, "residual mode 3 needs stored stencils");
                     const int n = lv[l].n;
-                    hipLaunchKernelGGL((k_residual_row_kron<Op, Tout>), dim3((unsigned)nb),
-                                       dim3(((n + 63) / 64) * 64), row_kron_lds_bytes(p, n, 2, sizeof(T)), stream,
-                                       op, bb, x, out, mode, opt.omega, part);
+                    if constexpr (is_kron3<Op>()) {
+                        if (n < kResRollMinN || n > kResRollMaxN) {
+                            hipLaunchKernelGGL((k_residual_row_kron<Op, Tout>), dim3((unsigned)nb),
+                                               dim3(((n + 63) / 64) * 64), row_kron_lds_bytes(p, n, 2, sizeof(T)),
+                                               stream, op, bb, x, out, mode, opt.omega, part);
+                            check_launch();
+                            return;
+                        }
+                        const unsigned grid = (unsigned)n * ((n + kResRollPlanes - 1) / kResRollPlanes);
+                        hipLaunchKernelGGL((k_residual_roll_kron3<Op, Tout>), dim3(grid), dim3(((n + 63) / 64) * 64),
+                                           res_roll_lds_bytes(p, n, sizeof(T)), stream, op, bb, x, out, mode,
+                                           opt.omega, part);
+                    } else {
+                        hipLaunchKernelGGL((k_residual_row_kron<Op, Tout>), dim3((unsigned)nb),
+                                           dim3(((n + 63) / 64) * 64), row_kron_lds_bytes(p, n, 2, sizeof(T)),
+                                           stream, op, bb, x, out, mode, opt.omega, part);
+                    }
+                    check_launch();
                     return;
                 }
             }
@@ -373,9 +388,32 @@ struct igamg_ctx {
     }
     // Sum-factorised 3D levels whose planes (with the waves' row buffers) fit
     // the plane-class kernel's LDS in FP64, one lane per point of a row.
+    // (LDS for the planes in the sweeps' precision: FP64 solves, or FP32
+    // V-cycles inside FP64 refinement)
     bool plane3_available(int l) const {
+        const int elem = (opt.precision == IGAMG_FP64) ? 8 : 4;
         return kind == OP_KRON3D && kron_rows_available(l) && lv[l].n <= kPlane3MaxN &&
-               plane3_lds_bytes(p, lv[l].n, sizeof(double)) <= kPlane3MaxLds;
+               plane3_lds_bytes(p, lv[l].n, elem) <= kPlane3MaxLds;
+    }
+    // The plane-class kernels and the 3D residual of the large levels take more
+    // than the default dynamic LDS; the attribute is raised once per context,
+    // before any launch or capture.
+    void raise_kron3_lds() {
+        if (kind != OP_KRON3D) return;
+        auto raise = [](const void* f, int bytes) {
+            IGAMG_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+        };
+        with_p3([&](auto PC) {
+            constexpr int P = decltype(PC)::value;
+            using F = Kron3D<P, float>;
+            using D = Kron3D<P, double>;
+            raise(reinterpret_cast<const void*>(&k_gs_planeclass3<F>), kPlane3MaxLds);
+            raise(reinterpret_cast<const void*>(&k_gs_planeclass3<D>), kPlane3MaxLds);
+            const int roll = res_roll_lds_bytes(P, kResRollMaxN, sizeof(double));
+            raise(reinterpret_cast<const void*>(&k_residual_roll_kron3<F, float>), roll);
+            raise(reinterpret_cast<const void*>(&k_residual_roll_kron3<D, float>), roll);
+            raise(reinterpret_cast<const void*>(&k_residual_roll_kron3<D, double>), roll);
+        });
     }
     bool row_sweeps_available(int l) const {
         if (kind != OP_STENCIL2D) return kron_rows_available(l);
@@ -1381,6 +1419,7 @@ void igamg_ctx::setup(const igamg_geometry& g, int degree, int levels) {
         fill(v.b64, v.N);
         fill(v.b32, v.N);
     }
+    raise_kron3_lds();
     default_shapes();
     choose_tail();
     b = alloc<double>(lv[L].N);

@@ -753,53 +753,56 @@ __global__ void __launch_bounds__(kRowKronThreads) k_gs_rowclass_kron(Op A, cons
 //
 // One launch per plane class ck: the planes k = ck (mod p+1) lie p+1 apart,
 // so one workgroup per plane sweeps the plane's (p+1)^2 colours (ci, cj, ck)
-// in colour order with the plane's iterate staged in LDS: the row classes cj
-// one after the other (a workgroup barrier each), the p+1 colour steps of a
-// row by one wave (ordered by the wave's own LDS operations).  The contraction
-// and the summation order are those of k_gs_rowclass_kron, so the iterates are the
-// same, from p+1 launches per sweep instead of (p+1)^2.  Levels of up to 64
-// unknowns per direction (one lane per point of a row): on larger levels the
+// in colour order.  The workgroup first copies into LDS, in one bulk load,
+// the 2p+1 planes k-p..k+p (the other planes do not change during the
+// launch; its own plane is updated there), the plane of b and the 1D bands;
+// then it runs the row classes cj one after the other (a workgroup barrier
+// each), the p+1 colour steps of a row by one wave (ordered by the wave's own
+// LDS operations), with no memory access but LDS until the plane is written
+// back.  The contraction and the summation order are those of
+// k_gs_rowclass_kron, so the iterates are the same, from p+1 launches per
+// sweep instead of (p+1)^2.  Levels of up to 64 unknowns per direction (one
+// lane per point of a row) whose planes fit the LDS: on larger levels the
 // planes of a class are too few workgroups to fill the GPU (a variant with
 // two points per lane at 65^3 took twice the time of the row-class launches).
 constexpr int kPlane3MaxN = 64;
-constexpr int kPlane3MaxLds = 65536;  // dynamic LDS bytes without a launch attribute
+constexpr int kPlane3MaxLds = 160 * 1024;  // LDS per workgroup (dynamic; the launch attribute is raised)
 // Waves per workgroup: one per row of a class, at most 16.
 __host__ __device__ constexpr int plane3_waves(int p, int n) {
     return (n + p) / (p + 1) < 16 ? (n + p) / (p + 1) : 16;
 }
+// LDS: 2p+1 planes of x, the plane of b, the K and M bands, and each wave's
+// two padded rows of partial sums.
 __host__ __device__ constexpr long long plane3_lds_bytes(int p, int n, int elem) {
-    return ((long long)n * n + 2LL * plane3_waves(p, n) * (n + 2 * p)) * elem;
+    return ((long long)(2 * p + 2) * n * n + 2LL * n * (2 * p + 1) + 2LL * plane3_waves(p, n) * (n + 2 * p)) *
+           elem;
 }
 
-// kron_row_contract<Op, false> (3D) with the plane k (c = 0) read from the LDS copy xp.
+// kron_row_contract<Op, false> (3D) with the planes k-p..k+p read from the
+// LDS slab (plane c at slab + c n^2) and the bands from LDS.
 template <class Op>
-__device__ __forceinline__ void plane3_contract(const Op& A, const typename Op::T* __restrict__ x,
-                                                const typename Op::T* xp, int j, int k, int i,
+__device__ __forceinline__ void plane3_contract(const typename Op::T* sK, const typename Op::T* sM,
+                                                const typename Op::T* slab, int n, int j, int k, int i,
                                                 typename Op::T& u, typename Op::T& v) {
     using T = typename Op::T;
     constexpr int P = Op::kP, W = Op::W;
-    const int n = A.n;
-    const size_t nn = (size_t)n * n;
-    T xv[W][W];
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-        const T* xs = (c == P) ? xp + i : x + (size_t)clampi(k + c - P, 0, n - 1) * nn + i;
-#pragma unroll
-        for (int b = 0; b < W; ++b)
-            xv[c][b] = (b == P && c == P) ? (T)0 : xs[(size_t)clampi(j + b - P, 0, n - 1) * n];
-    }
+    const int nn = n * n;
     u = 0;
     v = 0;
 #pragma unroll
     for (int c = 0; c < W; ++c) {
+        const T* xs = slab + c * nn + i;
+        T xv[W];
+#pragma unroll
+        for (int b = 0; b < W; ++b) xv[b] = (b == P && c == P) ? (T)0 : xs[clampi(j + b - P, 0, n - 1) * n];
         T sm = 0, sk = 0;
 #pragma unroll
         for (int b = 0; b < W; ++b) {
             if (b == P && c == P) continue;
-            sm = fma(A.M[(size_t)j * W + b], xv[c][b], sm);
-            sk = fma(A.K[(size_t)j * W + b], xv[c][b], sk);
+            sm = fma(sM[j * W + b], xv[b], sm);
+            sk = fma(sK[j * W + b], xv[b], sk);
         }
-        const T mz = A.M[(size_t)k * W + c], kz = A.K[(size_t)k * W + c];
+        const T mz = sM[k * W + c], kz = sK[k * W + c];
         u = fma(mz, sm, u);
         v = fma(kz, sm, fma(mz, sk, v));
     }
@@ -812,14 +815,35 @@ __global__ void __launch_bounds__(1024) k_gs_planeclass3(Op A, const typename Op
     constexpr int P = Op::kP, W = Op::W;
     extern __shared__ __align__(16) unsigned char row_kron_lds[];
     const int n = A.n, L = n + 2 * P, nwave = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = min(lane, n - 1);
-    const size_t nn = (size_t)n * n;
-    T* xp = (T*)row_kron_lds;
-    T* su = xp + nn + (size_t)wave * 2 * L;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63,
+              i = min(lane, n - 1);
+    const int nn = n * n;
+    T* slab = (T*)row_kron_lds;
+    T* sb = slab + W * nn;
+    T* sK = sb + nn;
+    T* sM = sK + n * W;
+    T* su = sM + n * W + wave * 2 * L;
     T* sv = su + L;
     const int k = ck + (P + 1) * xcd_swizzle(blockIdx.x, gridDim.x);
-    T* xg = x + (size_t)k * nn;
-    for (int e = threadIdx.x; e < (int)nn; e += blockDim.x) xp[e] = xg[e];
+    // planes k-p..k+p (clamped to the grid: their band entries are zero) and
+    // b, the 2p+2 loads of a point in flight before their stores; the bands
+    {
+        const T* src[W + 1];
+#pragma unroll
+        for (int c = 0; c < W; ++c) src[c] = x + (size_t)clampi(k + c - P, 0, n - 1) * nn;
+        src[W] = b + (size_t)k * nn;
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            T r[W + 1];
+#pragma unroll
+            for (int c = 0; c <= W; ++c) r[c] = src[c][e];
+#pragma unroll
+            for (int c = 0; c <= W; ++c) slab[c * nn + e] = r[c];
+        }
+        for (int e = threadIdx.x; e < n * W; e += blockDim.x) {
+            sK[e] = A.K[e];
+            sM[e] = A.M[e];
+        }
+    }
     if (lane < P) {
         su[lane] = 0;
         sv[lane] = 0;
@@ -827,27 +851,28 @@ __global__ void __launch_bounds__(1024) k_gs_planeclass3(Op A, const typename Op
         sv[n + P + lane] = 0;
     }
     __syncthreads();
-    const T mk = A.M[(size_t)k * W + P], kk = A.K[(size_t)k * W + P];
+    T* xp = slab + P * nn;  // the plane itself
+    const T mk = sM[k * W + P], kk = sK[k * W + P];
     const int s_own = lane % (P + 1);
     for (int cj = 0; cj <= P; ++cj) {
         const int nj = (n - cj + P) / (P + 1);
         for (int jq = wave; jq < nj; jq += nwave) {
             const int j = cj + (P + 1) * jq;
-            T* xr = xp + (size_t)j * n;
+            T* xr = xp + j * n;
             T u, v;
-            plane3_contract<Op>(A, x, xp, j, k, i, u, v);
+            plane3_contract<Op>(sK, sM, slab, n, j, k, i, u, v);
             if (lane < n) {
                 su[lane + P] = u;
                 sv[lane + P] = v;
             }
             pf_sync<true>();
-            const T mj = A.M[(size_t)j * W + P], kj = A.K[(size_t)j * W + P];
+            const T mj = sM[j * W + P], kj = sK[j * W + P];
             const T m00 = mj * mk, g00 = fma(kj, mk, mj * kk);
-            const T bo = b[(size_t)k * nn + (size_t)j * n + i];
+            const T bo = sb[j * n + i];
             T rest = 0, cr[W];
 #pragma unroll
             for (int a = 0; a < W; ++a) {
-                const T kx = A.K[(size_t)i * W + a], mx = A.M[(size_t)i * W + a];
+                const T kx = sK[i * W + a], mx = sM[i * W + a];
                 rest = fma(kx, su[i + a], rest);
                 rest = fma(mx, sv[i + a], rest);
                 cr[a] = fma(m00, kx, g00 * mx);
@@ -865,7 +890,8 @@ __global__ void __launch_bounds__(1024) k_gs_planeclass3(Op A, const typename Op
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < (int)nn; e += blockDim.x) xg[e] = xp[e];
+    T* xg = x + (size_t)k * nn;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) xg[e] = xp[e];
 }
 
 // Residual-type products of a sum-factorised operator, one workgroup per
@@ -935,6 +961,173 @@ __global__ void __launch_bounds__(kRowKronThreads) k_residual_row_kron(Op A, con
     if (partial) {
         const double tot = block_sum(sq, red);
         if (t == 0) partial[blk] = tot;
+    }
+}
+
+// The same products on the large 3D levels, one workgroup per x-row j and
+// run of kResRollPlanes planes k.  The y-contractions of a plane (the sums
+// over b of M[j,b] x and K[j,b] x along the row's 2p+1 neighbour rows) enter
+// the 2p+1 output planes around it; they are kept in a window of registers as
+// k advances, so that each x value is read from L2 about (2p+1)(1 + 2p/8)
+// times rather than (2p+1)^2.  The loads of the next two planes are in flight
+// during the current plane's output: the 1D bands sit in LDS, and the next
+// plane's b is requested before them, so that no wait for a value in use
+// (vector memory counts drain in issue order) waits for the prefetch.  Every
+// sum is formed in the order of k_residual_row_kron (so the outputs and the
+// per-row sums of squares in partial[k n + j] are the same, bit for bit).  On
+// levels below kResRollMinN unknowns per direction the chain of planes of a
+// workgroup outlasts the whole per-row launch, which is used there (and above
+// kResRollMaxN, rows of more than 512 threads).
+constexpr int kResRollPlanes = 8;
+constexpr int kResRollMinN = 96;
+constexpr int kResRollMaxN = 512;
+// LDS: the squares of the run's outputs (one per plane and thread) and their
+// per-wave sums (FP64), the 1D bands and the two (u, v) row buffers.
+__host__ __device__ constexpr int res_roll_lds_bytes(int p, int n, int elem) {
+    return kResRollPlanes * (((n + 63) / 64) * 64 + kResRollMaxN / 64) * 8 +
+           (2 * n * (2 * p + 1) + 4 * (n + 2 * p)) * elem;
+}
+template <class Op, typename Tout>
+__global__ void __launch_bounds__(kResRollMaxN) k_residual_roll_kron3(Op A, const typename Op::T* __restrict__ b,
+                                                                      const typename Op::T* __restrict__ x,
+                                                                      Tout* __restrict__ out, int mode, double omega,
+                                                                      double* __restrict__ partial) {
+    using T = typename Op::T;
+    constexpr int P = Op::kP, W = Op::W;
+    static_assert(is_kron3<Op>(), "3D sum-factorised operators");
+    extern __shared__ __align__(16) unsigned char row_kron_lds[];
+    constexpr int KC = kResRollPlanes, MW = kResRollMaxN / 64;
+    const int n = A.n, L = n + 2 * P;
+    const size_t nn = (size_t)n * n;
+    double* sqb = (double*)row_kron_lds;  // KC x blockDim squares
+    double* redk = sqb + KC * blockDim.x;  // KC x MW per-wave sums
+    T* cK = (T*)(redk + KC * MW);          // the 1D bands, n x (2p+1) each
+    T* cM = cK + n * W;
+    T* sbuf = cM + n * W;  // two buffers of (u row, v row), each padded by p zeros
+    const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int kc = lb / n, j = lb - kc * n;
+    const int k0 = kc * kResRollPlanes, k1 = min(k0 + kResRollPlanes, n);
+    const int t = threadIdx.x, i = min(t, n - 1);
+    // x at (plane q clamped, rows j-p..j+p clamped, column i)
+    auto load = [&](int q, T (&r)[W]) {
+        const T* xs = x + (size_t)clampi(q, 0, n - 1) * nn + i;
+#pragma unroll
+        for (int bb = 0; bb < W; ++bb) r[bb] = xs[(size_t)clampi(j + bb - P, 0, n - 1) * n];
+    };
+    for (int e = t; e < n * W; e += blockDim.x) {
+        cK[e] = A.K[e];
+        cM[e] = A.M[e];
+    }
+    // Every step issues the same loads (clamped indices; b replaced by x where
+    // it is not read), so that the compiler's wait for a plane counts the
+    // loads issued after it on every path and leaves them in flight.
+    const T* bsrc = (mode != 1) ? b : x;
+    T buf0[W], buf1[W];
+    load(k0 - P, buf0);
+    load(k0 - P + 1, buf1);  // steps >= 2p+1 >= 3
+    // b and x at the next output plane (x read by the Jacobi step only)
+    T bo = bsrc[(size_t)k0 * nn + (size_t)j * n + i], xo = x[(size_t)k0 * nn + (size_t)j * n + i];
+    if (t < P) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            sbuf[q * L + t] = 0;
+            sbuf[q * L + n + P + t] = 0;
+        }
+    }
+    __syncthreads();
+    T sm[W], sk[W];  // y-contractions of planes k-p..k+p (index c = plane - k + p)
+    const int steps = (k1 - k0) + 2 * P;
+    // step st: the plane k0-p+st enters the window (from buf, which then takes
+    // the loads of the plane two steps on); from st = 2p on, plane k0+st-2p out
+    auto step = [&](int st, T (&buf)[W]) {
+#pragma unroll
+        for (int c = 0; c + 1 < W; ++c) {
+            sm[c] = sm[c + 1];
+            sk[c] = sk[c + 1];
+        }
+        {
+            T a0 = 0, a1 = 0;
+#pragma unroll
+            for (int bb = 0; bb < W; ++bb) {
+                a0 = fma(cM[j * W + bb], buf[bb], a0);
+                a1 = fma(cK[j * W + bb], buf[bb], a1);
+            }
+            sm[W - 1] = a0;
+            sk[W - 1] = a1;
+        }
+        const int k = k0 + st - 2 * P;
+        const size_t row = (size_t)k * nn + (size_t)j * n;
+        const T bk = bo, xk = xo;
+        {
+            const size_t nxt = (size_t)clampi(k + 1, k0, k1 - 1) * nn + (size_t)j * n + i;
+            bo = bsrc[nxt];
+            xo = x[nxt];
+        }
+        load(k0 - P + st + 2, buf);
+        if (st < 2 * P) return;
+        T u = 0, v = 0;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            const T mz = cM[k * W + c], kz = cK[k * W + c];
+            u = fma(mz, sm[c], u);
+            v = fma(kz, sm[c], fma(mz, sk[c], v));
+        }
+        T* su = sbuf + (k & 1) * 2 * L;
+        T* sv = su + L;
+        if (t < n) {
+            su[t + P] = u;
+            sv[t + P] = v;
+        }
+        __syncthreads();
+        double sq = 0.0;
+        if (t < n) {
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                acc = fma(cK[i * W + a], su[t + a], acc);
+                acc = fma(cM[i * W + a], sv[t + a], acc);
+            }
+            T r;
+            if (mode == 0)
+                r = bk - acc;
+            else if (mode == 1)
+                r = acc;
+            else {
+                const T mj = cM[j * W + P], kj = cK[j * W + P], mk = cM[k * W + P], kk = cK[k * W + P];
+                const T m00 = mj * mk, g00 = fma(kj, mk, mj * kk);
+                const T d = fma(m00, cK[i * W + P], g00 * cM[i * W + P]);
+                r = xk + (T)omega * (bk - acc) / d;
+            }
+            out[row + t] = (Tout)r;
+            sq = (double)r * (double)r;
+        }
+        if (partial) sqb[(k - k0) * blockDim.x + t] = sq;
+    };
+    int st = 0;
+    for (; st + 1 < steps; st += 2) {
+        step(st, buf0);
+        step(st + 1, buf1);
+    }
+    if (st < steps) step(st, buf0);
+    // The rows' sums of squares, with block_sum's tree (each wave sums its 64
+    // lanes, then the wave sums in order), for all the run's planes at once.
+    if (partial) {
+        const int np = k1 - k0, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+        double v[KC];
+#pragma unroll
+        for (int q = 0; q < KC; ++q) v[q] = (q < np) ? sqb[q * blockDim.x + t] : 0.0;
+#pragma unroll
+        for (int q = 0; q < KC; ++q) v[q] = wave_sum(v[q]);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < KC; ++q) redk[q * MW + w] = v[q];
+        }
+        __syncthreads();
+        if (t < np) {
+            double tot = 0.0;
+            for (int e = 0; e < nw; ++e) tot += redk[t * MW + e];
+            partial[(size_t)(k0 + t) * n + j] = tot;
+        }
     }
 }
 

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import synth
-from oracle import assemble, extrapolation as ex, multigrid as mg
+from oracle import assemble, bspline, extrapolation as ex, multigrid as mg
 from paper_2412_20205_amd import igamg
 
 pytestmark = pytest.mark.gpu
@@ -455,14 +455,70 @@ def test_kron_row_class_sweeps_and_products(geom, n_el, p):
             assert rel(b, a) < 1e-13, l
 
 
+def _cube_apply(n_el, p, x):
+    """A x and diag(A) for the unit-cube operator K(x)M(x)M + M(x)K(x)M +
+    M(x)M(x)K (first factor on k, x index fastest), from the oracle's 1D
+    stiffness and mass matrices by dense tensor contractions (grids too large
+    for the assembled matrix)."""
+    K, M = (np.asarray(a.todense()) if hasattr(a, "todense") else np.asarray(a)
+            for a in bspline.stiffness_mass_1d(n_el, p))
+    n = K.shape[0]
+    X = x.reshape(n, n, n)
+    ax = lambda F, Y: Y @ F.T                            # along i
+    ay = lambda F, Y: np.matmul(F, Y)                    # along j
+    az = lambda F, Y: np.tensordot(F, Y, axes=(1, 0))    # along k
+    Xm = ax(M, X)
+    y = az(K, ay(M, Xm)) + az(M, ay(K, Xm)) + az(M, ay(M, ax(K, X)))
+    kd, md = np.diag(K), np.diag(M)
+    d = (kd[:, None, None] * md[None, :, None] * md[None, None, :] +
+         md[:, None, None] * kd[None, :, None] * md[None, None, :] +
+         md[:, None, None] * md[None, :, None] * kd[None, None, :])
+    return y.ravel(), d.ravel()
+
+
+@pytest.mark.parametrize("n_el,p", [(96, 2), (96, 3), (128, 1), (128, 3)])
+def test_cube_products_rolling_planes(n_el, p):
+    """The products of the large 3D levels (one workgroup per x-row and run
+    of 8 planes, the y-contractions of the planes kept in a window as the
+    plane advances): A x, the damped Jacobi step and the relative residual
+    from the per-row sums of squares equal the operator's definition applied
+    to random vectors (1e-13).  n = 96 (whole runs), 97 and 129 (a last run of
+    one plane, shorter than the window of 2p+1 planes), 127 (a last run of
+    seven)."""
+    n = n_el + p - 2
+    N = n ** 3
+    x = synth.random_vector(N, 170 + p)
+    b = synth.random_vector(N, 171 + p)
+    Ax, d = _cube_apply(n_el, p, x)
+    print("[cube rolling] n_el=%d p=%d" % (n_el, p), flush=True)
+    s = igamg.Solver(igamg.UNIT_CUBE, n_el, p, n_el_coarsest=0)
+    fine = s.num_levels - 1
+    assert s.level_ndof(fine) == N
+    y = torch.zeros(N, dtype=torch.float64, device=DEV)
+    s.apply(fine, dev(x), y)
+    assert rel(host(y), Ax) < 1e-13
+    s.set_rhs(dev(b))
+    ref = np.linalg.norm(b - Ax) / np.linalg.norm(b)
+    got = s.residual(dev(x))
+    assert abs(got - ref) <= 1e-13 * ref
+    s.close()
+    sj = igamg.Solver(igamg.UNIT_CUBE, n_el, p, n_el_coarsest=0, smoother=igamg.SMOOTH_JACOBI)
+    xj = dev(x)
+    sj.smooth(fine, dev(b), xj, 1)
+    assert rel(host(xj), x + (2.0 / 3.0) * (b - Ax) / d) < 1e-13
+    sj.close()
+
+
 @pytest.mark.parametrize("n_el,p", [(32, 1), (32, 2), (32, 3), (64, 2), (64, 3)])
 @pytest.mark.parametrize("prec", [igamg.FP64, igamg.FP32_IR])
 def test_cube_plane_class_equals_row_class_bitwise(n_el, p, prec):
     """V-cycles with every cube level multi-block: one launch per plane class
-    (where it applies: 64 unknowns per direction at most, so the 64^3 level of
-    n_el = 64, p = 2 and not the 65^3 one of p = 3) gives the iterates of one
-    launch per row class bit for bit.  (n = 64 also checks the rows' zero
-    pads when no thread lies past the row's last point.)"""
+    (where it applies: at most 64 unknowns per direction, with the 2p+1
+    planes of x, the plane of b and the bands in LDS, so the 64^3 level of
+    n_el = 64, p = 2 in FP32 but not in FP64, and not the 65^3 one of p = 3)
+    gives the iterates of one launch per row class bit for bit.  (n = 64 also
+    checks the rows' zero pads when no thread lies past the row's last
+    point.)"""
     out = []
     for shape in (1, 2):
         print("[cube plane] n_el=%d p=%d prec=%d shape=%d" % (n_el, p, prec, shape), flush=True)
