@@ -509,6 +509,31 @@ def test_cube_products_rolling_planes(n_el, p):
     sj.close()
 
 
+@pytest.mark.parametrize("prec,method", [(igamg.FP32_IR, igamg.MPE), (igamg.FP64, igamg.RRE)])
+def test_cube_large_solve_reaches_tolerance(prec, method):
+    """A 97^3 cube (n_el = 96, p = 3: the residuals of the finest level by the
+    windowed kernel, FP64 in and FP32 out for the refinement's right-hand side)
+    solved to 1e-10 from zero for a random right-hand side: the relative
+    residual of the returned x, recomputed on the host from the operator's
+    Kronecker definition, is within the tolerance (up to the rounding of the
+    two computations)."""
+    n_el, p = 96, 3
+    n = n_el + p - 2
+    b = synth.random_vector(n ** 3, 181)
+    print("[cube large solve] prec=%d method=%d" % (prec, method), flush=True)
+    s = igamg.Solver(igamg.UNIT_CUBE, n_el, p, n_el_coarsest=0, precision=prec)
+    s.set_rhs(dev(b))
+    x = torch.zeros(n ** 3, dtype=torch.float64, device=DEV)
+    st, _ = s.solve(x, tol=1e-10, max_restarts=200, method=method, q=4)
+    s.close()
+    Ax, _ = _cube_apply(n_el, p, host(x))
+    got = np.linalg.norm(b - Ax) / np.linalg.norm(b)
+    print("[cube large solve] vcycles=%d restarts=%d rel=%.3e host=%.3e"
+          % (st.vcycles, st.restarts, st.rel_residual, got), flush=True)
+    assert st.rel_residual <= 1e-10
+    assert got <= 1.0001e-10
+
+
 @pytest.mark.parametrize("n_el,p", [(32, 1), (32, 2), (32, 3), (64, 2), (64, 3)])
 @pytest.mark.parametrize("prec", [igamg.FP64, igamg.FP32_IR])
 def test_cube_plane_class_equals_row_class_bitwise(n_el, p, prec):
