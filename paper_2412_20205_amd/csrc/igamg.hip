@@ -2189,7 +2189,12 @@ struct igamg_batch {
     bool own_stream = false;
     std::vector<hipStream_t> side;  // one per degree group (graph branches)
     std::vector<hipEvent_t> ev;
-    std::vector<void*> plan_allocs;
+    // argument tables of the captured plan: packed on the host by the prepare
+    // pass, uploaded in one copy into a device buffer kept (and grown) across plans
+    std::vector<unsigned char> plan_host;
+    std::vector<size_t> plan_offs;
+    unsigned char* plan_dev = nullptr;
+    size_t plan_cap = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<int> plan_active;
@@ -2200,6 +2205,7 @@ struct igamg_batch {
 
     ~igamg_batch() {
         clear_plan();
+        if (plan_dev) (void)hipFree(plan_dev);
         for (auto* c : inst) delete c;
         for (auto e : ev) (void)hipEventDestroy(e);
         for (auto st : side) (void)hipStreamDestroy(st);
@@ -2213,23 +2219,38 @@ struct igamg_batch {
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
-        for (void* a : plan_allocs) (void)hipFree(a);
-        plan_allocs.clear();
+        plan_host.clear();
+        plan_offs.clear();
         plan_active.clear();
         plan_q = -1;
     }
-    // Tables are built in a prepare pass (allocated and uploaded, nothing
-    // launched) and reused, in the same order, by the capture pass.
+    // Tables are built in a prepare pass (packed on the host, nothing launched),
+    // uploaded once (upload_plan), and handed out in the same order by the
+    // capture pass.
     bool preparing = false;
     size_t cursor = 0;
     template <typename E>
     const E* up(const std::vector<E>& v) {
-        if (!preparing) return (const E*)plan_allocs.at(cursor++);
-        void* d = nullptr;
-        IGAMG_HIP(hipMalloc(&d, std::max<size_t>(1, v.size()) * sizeof(E)));
-        plan_allocs.push_back(d);
-        IGAMG_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice));
-        return (const E*)d;
+        if (!preparing) return reinterpret_cast<const E*>(plan_dev + plan_offs.at(cursor++));
+        const size_t off = (plan_host.size() + 15) & ~(size_t)15;
+        const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(E);
+        plan_host.resize(off + bytes, 0);
+        if (!v.empty()) std::memcpy(plan_host.data() + off, v.data(), v.size() * sizeof(E));
+        plan_offs.push_back(off);
+        return nullptr;  // (the prepare pass launches nothing)
+    }
+    // One copy of the packed tables; the previous plan's graph has finished
+    // (every round ends with a stream synchronisation).
+    void upload_plan() {
+        const size_t need = std::max<size_t>(plan_host.size(), 16);
+        if (need > plan_cap) {
+            if (plan_dev) IGAMG_HIP(hipFree(plan_dev));
+            plan_dev = nullptr;
+            plan_cap = 0;
+            IGAMG_HIP(hipMalloc((void**)&plan_dev, need + need / 2));
+            plan_cap = need + need / 2;
+        }
+        IGAMG_HIP(hipMemcpy(plan_dev, plan_host.data(), plan_host.size(), hipMemcpyHostToDevice));
     }
     // prefix offsets of per-entry block counts
     const int* offsets(const std::vector<int>& counts, int& total) {
@@ -2485,6 +2506,7 @@ struct igamg_batch {
             preparing = true;
             restart_round(act, q);
             preparing = false;
+            upload_plan();
             cursor = 0;
             IGAMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
             try {
