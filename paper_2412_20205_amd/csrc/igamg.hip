@@ -2205,6 +2205,7 @@ struct igamg_batch {
 
     ~igamg_batch() {
         clear_plan();
+        destroy_retired();
         if (plan_dev) (void)hipFree(plan_dev);
         for (auto* c : inst) delete c;
         for (auto e : ev) (void)hipEventDestroy(e);
@@ -2214,9 +2215,20 @@ struct igamg_batch {
         if (scal_ptrs) (void)hipFree((void*)scal_ptrs);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
+    // Graphs of earlier plans, idle (every round ends with a stream
+    // synchronisation), destroyed after the next plan's launch so that their
+    // host-side teardown overlaps the GPU's work.
+    std::vector<hipGraphExec_t> retired_exec;
+    std::vector<hipGraph_t> retired_graph;
+    void destroy_retired() {
+        for (auto e : retired_exec) (void)hipGraphExecDestroy(e);
+        for (auto g : retired_graph) (void)hipGraphDestroy(g);
+        retired_exec.clear();
+        retired_graph.clear();
+    }
     void clear_plan() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
+        if (gexec) retired_exec.push_back(gexec);
+        if (graph) retired_graph.push_back(graph);
         gexec = nullptr;
         graph = nullptr;
         plan_host.clear();
@@ -2523,6 +2535,7 @@ struct igamg_batch {
             plan_q = q;
         }
         IGAMG_HIP(hipGraphLaunch(gexec, stream));
+        destroy_retired();
         IGAMG_HIP(hipMemcpyAsync(rel_host, rel_dev, inst.size() * sizeof(double), hipMemcpyDeviceToHost,
                                  stream));
         IGAMG_HIP(hipStreamSynchronize(stream));
