@@ -970,9 +970,10 @@ __global__ void __launch_bounds__(kRowKronThreads) k_residual_row_kron(Op A, con
 // the 2p+1 output planes around it; they are kept in a window of registers as
 // k advances, so that each x value is read from L2 about (2p+1)(1 + 2p/8)
 // times rather than (2p+1)^2.  The loads of the next two planes are in flight
-// during the current plane's output: the 1D bands sit in LDS, and the next
-// plane's b is requested before them, so that no wait for a value in use
-// (vector memory counts drain in issue order) waits for the prefetch.  Every
+// during the current plane's output: the 1D bands sit in LDS, and b of the
+// next output plane is requested before the prefetched planes, so that no
+// wait for a value in use (vector memory counts drain in issue order) waits
+// for the prefetch.  Every
 // sum is formed in the order of k_residual_row_kron (so the outputs and the
 // per-row sums of squares in partial[k n + j] are the same, bit for bit).  On
 // levels below kResRollMinN unknowns per direction the chain of planes of a
